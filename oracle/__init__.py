@@ -1,0 +1,6 @@
+"""FP64 CPU oracle for the voxel cone tracing hot path.
+
+Test infrastructure only: imported by tests/, the smoke check and the
+cpu_baseline leg of bench.py, never by the library or its binding."""
+from .vct_oracle import (build_mips, mip_adjoint, taps, sample, cone_lanes, march,  # noqa: F401
+                         assemble, trace, trace_backward, lane_grads, render)
