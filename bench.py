@@ -1,0 +1,185 @@
+"""Benchmark of the voxel-cone-tracing hot path on one GPU.
+
+A step is one pass of the whole hot path over the 256^3 / 1920x1080 scene:
+vct_build_mips (float32 grid -> pyramid), vct_trace (5 diffuse + specular +
+occlusion cones per pixel) and vct_trace_backward (gradient into the float32
+base grid for a seeded dL/d(out)).  Inputs are resident in HBM before timing.
+
+    python bench.py [--steps K] [--warmup W] [--dtype f32|f16|bf16] [--no-cpu-baseline]
+
+Prints one JSON line.  value = forward cone samples per second of the whole
+fwd+bwd step; the breakdown also gives forward-only rates, the per-call
+times (HIP events on the stream the library launches on) and the
+float16-storage forward for comparison.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("cone samples/s + ms/frame at 1080p (fwd, fwd+bwd), % HBM peak, FP16 vs FP32 storage")
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "c1"
+WORKLOAD_DESC = ("procedural Cornell box 256^3 (9 levels, 4-8 boxes and spheres), 1 view 1920x1080, "
+                 "5 diffuse cones (front + 4 at 45 deg, 60 deg aperture) + specular + occlusion, "
+                 "beta 0.5, t0 0.001, max_dist 1, alpha_thresh 0.99")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the float16-storage forward comparison")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, n_pix=24576, seed=0):
+    """The FP64 oracle as it stands on a seeded pixel sample of the same frame
+    (build_mips of the full grid + all cones of n_pix pixels)."""
+    import oracle
+    from tests.workloads import sample_pixels
+
+    v, y, x = sample_pixels(w.shape, n_pix, seed)
+    t = time.perf_counter()
+    mips = oracle.build_mips(w.base)
+    _, info = oracle.trace(mips, w.pos_rough[v, y, x][None, None], w.normal[v, y, x][None, None], w.cam_pos,
+                           w.params, return_info=True)
+    dt = time.perf_counter() - t
+    return {"value": info["samples"] / dt, "unit": "cone samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"build_mips of the 256^3 grid + all 7 cones of {n_pix} seeded pixels of the 1080p frame "
+                      f"({info['samples']} samples, {dt:.1f} s, NumPy FP64, single thread)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path has no multi-GPU "
+              f"implementation in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2104_00618_amd as vct
+    from scenes import make_workload
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    w = make_workload(WORKLOAD)
+    log(f"workload generated in {time.perf_counter() - t0:.1f} s")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    base, pr, nr, cam = T(w.base), T(w.pos_rough), T(w.normal), T(w.cam_pos)
+    rng = np.random.default_rng(0)
+    gout = T(rng.normal(size=w.shape + (8,)).astype(np.float32) * 1e-3)
+    grid = vct.Grid(w.n, dtype=args.dtype)
+    pyr = torch.empty(vct.pyramid_bytes(grid), dtype=torch.uint8, device=dev)
+    out = torch.empty(w.shape + (8,), dtype=torch.float32, device=dev)
+    ws = torch.empty(vct.backward_workspace_bytes(grid, pr, nr, cam, w.params), dtype=torch.uint8, device=dev)
+    gbase = torch.empty_like(base)
+    vct.build_mips(base, grid, pyr)
+    samples = vct.count_samples(pyr, grid, pr, nr, cam, w.params)
+    npix = int(np.prod(w.shape))
+    log(f"{samples} cone samples per frame ({samples / npix:.1f} per pixel), workspace {ws.numel() / 2**30:.2f} GiB")
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        vct.build_mips(base, grid, pyr)
+        if ev is not None:
+            ev[1].record()
+        vct.trace(pyr, grid, pr, nr, cam, w.params, out)
+        if ev is not None:
+            ev[2].record()
+        vct.trace_backward(pyr, grid, pr, nr, cam, w.params, gout, ws, gbase)
+        if ev is not None:
+            ev[3].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    mips_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    fwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    ms_step = wall * 1e3 / args.steps
+    log(f"step {ms_step:.3f} ms: mips {mips_ms:.3f}, trace {fwd_ms:.3f}, backward {bwd_ms:.3f}")
+
+    texel_bytes = 16 if args.dtype == "f32" else 8
+    trace_bytes = samples * 16 * texel_bytes + npix * 64
+    achieved = trace_bytes / (fwd_ms * 1e-3) / 1e9
+    breakdown = {
+        "build_mips_ms": mips_ms, "trace_ms": fwd_ms, "trace_backward_ms": bwd_ms,
+        "fwd_ms_per_frame": mips_ms + fwd_ms, "fwd_bwd_ms_per_frame": mips_ms + fwd_ms + bwd_ms,
+        "samples_per_frame": samples, "samples_per_pixel": samples / npix,
+        "fwd_samples_per_s": samples / ((mips_ms + fwd_ms) * 1e-3),
+        "trace_kernel_samples_per_s": samples / (fwd_ms * 1e-3),
+    }
+
+    if not args.no_compare and args.dtype == "f32":
+        g16 = vct.Grid(w.n, dtype="f16")
+        p16 = vct.build_mips(base, g16)
+        o16 = torch.empty_like(out)
+        s16 = vct.count_samples(p16, g16, pr, nr, cam, w.params)
+        for _ in range(2):
+            vct.trace(p16, g16, pr, nr, cam, w.params, o16)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        for _ in range(args.steps):
+            vct.build_mips(base, g16, p16)
+        e[1].record()
+        for _ in range(args.steps):
+            vct.trace(p16, g16, pr, nr, cam, w.params, o16)
+        e[2].record()
+        torch.cuda.synchronize()
+        m16 = e[0].elapsed_time(e[1]) / args.steps
+        f16 = e[1].elapsed_time(e[2]) / args.steps
+        breakdown["f16_storage"] = {
+            "build_mips_ms": m16, "trace_ms": f16, "samples_per_frame": s16,
+            "trace_speedup_vs_f32": fwd_ms / f16, "fwd_speedup_vs_f32": (mips_ms + fwd_ms) / (m16 + f16),
+            "trace_logical_GBps": (s16 * 128 + npix * 64) / (f16 * 1e-3) / 1e9}
+        log(f"f16 storage: mips {m16:.3f} ms, trace {f16:.3f} ms ({fwd_ms / f16:.2f}x vs f32)")
+
+    res = {
+        "metric": METRIC,
+        "value": samples / (ms_step * 1e-3),
+        "unit": "cone samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic (seeded procedural scene and G-buffer; random dL/dout)",
+        "config": {"workload": WORKLOAD_DESC, "grid": w.n, "levels": w.levels, "views": w.shape[0],
+                   "height": w.shape[1], "width": w.shape[2], "cones_per_pixel": w.params.n_diffuse + 2,
+                   "step": "build_mips + trace + trace_backward"},
+        "breakdown": breakdown,
+        "roofline": {"kernel": "k_trace (forward cone march, one launch per step)", "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None,
+                     "bytes_per_launch": trace_bytes,
+                     "bytes_model": f"{16 * texel_bytes} B per cone sample (16 texel reads) + 64 B per pixel "
+                                    f"(G-buffer read, output write)"},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a pixel sample")
+        res["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

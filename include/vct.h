@@ -1,0 +1,176 @@
+/*
+ * vct.h - C ABI of the voxel-cone-tracing hot path for AMD Instinct MI355X (gfx950).
+ *
+ * The library computes the data-parallel core of voxel cone tracing as defined in
+ * arXiv 2104.00618 ("Real-Time Global Illumination Using OpenGL And Voxel Cone
+ * Tracing"): a mip pyramid of a premultiplied RGBA voxel grid, and for every
+ * G-buffer pixel u diffuse cones, one specular cone and one occlusion cone that
+ * march through that pyramid, sampling quadrilinearly and compositing front to
+ * back; plus the adjoint of the march with respect to the base grid.
+ *
+ * Conventions shared by every entry point
+ *   - Data pointers are DEVICE pointers unless marked "host".  Struct pointers
+ *     (vct_grid, vct_gbuffer, vct_cone_params) point to host memory and are read
+ *     during the call only.
+ *   - Work is enqueued on `stream` (a hipStream_t; 0 = the null stream) and runs
+ *     asynchronously; the call returns before it completes.  The library never
+ *     synchronises the device or the stream.
+ *   - The caller owns every buffer.  The library allocates no memory that the
+ *     caller can see and keeps no pointer after a call returns.
+ *   - Every entry point returns VCT_OK (0) or a negative error code.  All
+ *     arguments are validated before anything is enqueued, so a call that fails
+ *     validation has no side effects.  vct_last_error() then gives a
+ *     "function: message" string (thread-local, valid until the next call on
+ *     that thread).  No C++ exception or abort crosses this interface.
+ *   - Grids are cubes of N^3 texels, N = 2^k with 1 <= N <= 1024, covering the
+ *     world-space cube [origin, origin + extent]^3.  Texel (i, j, k) of level l
+ *     has its centre at origin + (i + 1/2, j + 1/2, k + 1/2) * extent / N_l with
+ *     N_l = N >> l.  Logical grid buffers are contiguous float32
+ *     [z][y][x][4] (x fastest) holding premultiplied (r*a, g*a, b*a, a).
+ *   - Non-finite grid, G-buffer or gradient VALUES are not checked (that would
+ *     need a device synchronisation); they propagate into the results, and every
+ *     march stays bounded in time regardless.
+ */
+#ifndef VCT_H
+#define VCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VCT_OK 0
+#define VCT_EINVAL (-1)        /* a shape, size or parameter is out of range, or a pointer is null */
+#define VCT_EWORKSPACE (-2)    /* a caller buffer is smaller than the size query requires */
+#define VCT_EDEVICE (-3)       /* the HIP runtime refused a launch; the message carries its error */
+#define VCT_EUNSUPPORTED (-4)  /* valid request that this build does not implement */
+
+#define VCT_MAX_DIFFUSE 16
+#define VCT_MAX_N 1024
+#define VCT_MAX_STEPS (1 << 20) /* bound on max_dist / (step_factor * voxel size) */
+
+/* Storage type of the mip pyramid.  Sampling, compositing and gradients are
+ * always float32; reduced-precision pyramids are rounded to nearest even. */
+typedef enum { VCT_F32 = 0, VCT_F16 = 1, VCT_BF16 = 2 } vct_dtype;
+
+/* The voxel grid and its pyramid (the thesis's VoxelMap 3D texture and its
+ * mipmaps; Section 4.3.3 "Mipmaps", Section 5.4.4 "Additional components"). */
+typedef struct {
+    int32_t n;         /* base resolution N = 2^k, 1..1024 */
+    int32_t levels;    /* pyramid levels L, 1 <= L <= log2(N) + 1 (level l has N >> l texels a side) */
+    int32_t dtype;     /* vct_dtype of the pyramid storage */
+    float origin[3];   /* world position of the grid's minimum corner */
+    float extent;      /* side length of the grid cube, world units, finite and > 0 */
+} vct_grid;
+
+/* Deferred-shading G-buffer: one cone origin per pixel (Section 5.1.3 adopts
+ * deferred shading; the cone-trace fragment inputs are position, normal,
+ * material and camera, Section 5.4.4 "Cone Tracing"). */
+typedef struct {
+    int32_t b, h, w;          /* views, rows, columns; any may be 0 (nothing to do) */
+    const float* pos_rough;   /* device [b][h][w][4] = (x, y, z, roughness) in world units */
+    const float* normal;      /* device [b][h][w][4] = (nx, ny, nz, valid); valid == 0 marks background */
+    const float* cam_pos;     /* device [b][3] camera position of each view */
+} vct_gbuffer;
+
+/* Cone set and march parameters.  The thesis groups an initial offset t0, an
+ * aperture and a step factor per cone class (Section 5.4.4 "Additional
+ * components") and traces u diffuse cones, a specular cone in the reflection
+ * direction and an occlusion cone toward the light (Section 4.2). */
+typedef struct {
+    int32_t n_diffuse;                           /* u, 0..16 */
+    float diffuse_dir[VCT_MAX_DIFFUSE][3];       /* tangent-frame axes (x = tangent, y = bitangent, z = normal) */
+    float diffuse_weight[VCT_MAX_DIFFUSE];       /* weight of each diffuse cone in the D output */
+    float diffuse_aperture;                      /* radians, finite, >= 0 */
+    int32_t enable_spec;                         /* nonzero: trace the specular cone */
+    int32_t enable_occ;                          /* nonzero: trace the occlusion cone */
+    float spec_aperture_scale;                   /* specular aperture = roughness * scale (radians), >= 0 */
+    float occ_aperture;                          /* radians, finite, >= 0 */
+    float light_pos[3];                          /* point light, world units */
+    float step_factor;                           /* beta > 0: t += beta * d */
+    float t0;                                    /* initial offset along the axis, >= 0 */
+    float normal_offset;                         /* cone origin = x + n * normal_offset * voxel size */
+    float max_dist;                              /* > 0: samples only at t <= max_dist */
+    float alpha_thresh;                          /* > 0: samples only while accumulated alpha < alpha_thresh */
+} vct_cone_params;
+
+/* Bytes of the opaque pyramid buffer for `grid` (host only, enqueues nothing).
+ * Layout (informative): each level stored as 4^3-texel bricks in the storage
+ * type, levels concatenated at 256-byte alignment, followed by a small float32
+ * staging area used while the pyramid is built. */
+int vct_pyramid_bytes(const vct_grid* grid, size_t* bytes);
+
+/* Build the mip pyramid: level 0 = `base`, level l+1 = mean of the 2x2x2
+ * children of level l (sum in float32 as ((c0+c1)+(c2+c3))+((c4+c5)+(c6+c7)),
+ * times 1/8), every level computed from float32 parents and then rounded once
+ * to the storage type.  Texture filtering, Section 4.3.3; mipmaps generated
+ * after voxelization, Sections 4.5 and 5.4.4.
+ *   base          device float32 [N][N][N][4], premultiplied RGBA, read only
+ *   pyramid       device buffer of at least vct_pyramid_bytes(grid) bytes, overwritten
+ *   pyramid_bytes its size (VCT_EWORKSPACE if too small) */
+int vct_build_mips(const vct_grid* grid, const float* base, void* pyramid, size_t pyramid_bytes,
+                   hipStream_t stream);
+
+/* Copy level `level` of a built pyramid out as logical float32
+ * [N_l][N_l][N_l][4] (test and inspection hook; the thesis's
+ * VoxelMap::retrieveData, Section 5.4.4). */
+int vct_unpack_level(const vct_grid* grid, const void* pyramid, int32_t level, float* out,
+                     hipStream_t stream);
+
+/* Forward cone trace (Section 4.3.2 cone-trace function; sampler of Section
+ * 4.5; cone set of Sections 4.2 and 5.4.4).  For every pixel with valid != 0:
+ *   o = x + normalize(n) * normal_offset * voxel;  frame t = normalize(a x n),
+ *   b = n x t with a = (1,0,0) if |n_y| > 0.9 else (0,1,0);
+ *   diffuse q: axis normalize(t*d.x + b*d.y + n*d.z), aperture diffuse_aperture;
+ *   specular:  axis reflect(normalize(x - cam), n), aperture roughness * scale;
+ *   occlusion: axis toward light_pos, t_max = min(max_dist, |light - o|).
+ * Each cone: t = t0, C = 0, A = 0; while t <= t_max and A < alpha_thresh:
+ *   d = max(2 t tan(aperture / 2), voxel); lod = clamp(log2(d / voxel), 0, L - 1);
+ *   s = quadrilinear sample at o + t * axis (clamp-to-edge);
+ *   C += (1 - A) s.rgb; A += (1 - A) s.a; t += step_factor * d.
+ *   out        device float32 [b][h][w][8], overwritten:
+ *              (sum_q w_q C_q, sum_q w_q A_q, C_spec, A_occ); background pixels and
+ *              disabled cones give 0.  May be null when b*h*w == 0. */
+int vct_trace(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+              const vct_cone_params* params, float* out, hipStream_t stream);
+
+/* Same march as vct_trace, but instead of radiance it writes the total number
+ * of cone samples taken over all pixels and cones to *count (device uint64,
+ * overwritten).  Used to state throughput in samples per second. */
+int vct_count_samples(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                      const vct_cone_params* params, unsigned long long* count, hipStream_t stream);
+
+/* Device workspace bytes needed by vct_trace_backward for these shapes (host only). */
+int vct_backward_workspace_bytes(const vct_grid* grid, const vct_gbuffer* gbuf,
+                                 const vct_cone_params* params, size_t* bytes);
+
+/* Adjoint of vct_build_mips followed by vct_trace with respect to `base`,
+ * holding the number of samples of every cone fixed.  Per cone, with
+ * T_k = 1 - A_k: dL/dc_k = T_k dL/dC and
+ * dL/da_k = -T_k (dL/dC . (C_K - C_{k+1}) - dL/dA T_K) / T_{k+1}
+ * (dL/da_{K-1} = T_{K-1} dL/dA), transmittance recomputed by re-marching, never
+ * stored; each sample's gradient is spread over its 16 taps with the tap
+ * weights and reduced deterministically (64-bit fixed point, exact integer
+ * sums: bitwise identical results on every run); then carried through the mip
+ * reduction (each child receives 1/8 of its parent's gradient).  For float16 or
+ * bfloat16 pyramids the sampled values are the stored ones and the rounding is
+ * treated as the identity.
+ *   grad_out   device float32 [b][h][w][8] = dL/d(out of vct_trace)
+ *   grad_base  device float32 [N][N][N][4], overwritten (not accumulated)
+ *   workspace  device buffer of at least vct_backward_workspace_bytes bytes */
+int vct_trace_backward(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                       const vct_cone_params* params, const float* grad_out, float* grad_base,
+                       void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* vct_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VCT_H */

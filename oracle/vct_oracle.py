@@ -59,6 +59,7 @@ import numpy as np
 
 AMBIG_ALPHA = 1e-5      # |alpha_k - alpha_thresh| below this marks a tie
 AMBIG_T_REL = 1e-6      # |t_k - t_max| below this * t_max marks a tie
+AMBIG_FRAME = 1e-6      # ||n_y| - 0.9| below this marks a tangent-frame tie (R10)
 
 
 # ---------------------------------------------------------------------------
@@ -172,7 +173,8 @@ def cone_lanes(pos_rough, normal, cam_pos, params, n, origin=(0.0, 0.0, 0.0), ex
     a = np.where((np.abs(nn[:, 1]) > 0.9)[:, None], np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0]))
     tt = _normalize(np.cross(a, nn))
     bb = np.cross(nn, tt)
-    lanes = {k: [] for k in ("pix", "slot", "o", "w", "gamma", "tmax")}
+    lanes = {k: [] for k in ("pix", "slot", "o", "w", "gamma", "tmax", "tie")}
+    frame_tie = np.abs(np.abs(nn[:, 1]) - 0.9) < AMBIG_FRAME
     dirs = np.asarray(params.diffuse_dirs, dtype=np.float64)
     m = len(pix)
     for q in range(len(dirs)):
@@ -184,6 +186,7 @@ def cone_lanes(pos_rough, normal, cam_pos, params, n, origin=(0.0, 0.0, 0.0), ex
         lanes["w"].append(wq)
         lanes["gamma"].append(np.full(m, float(params.diffuse_aperture)))
         lanes["tmax"].append(np.full(m, float(params.max_dist)))
+        lanes["tie"].append(frame_tie)
     slot = len(dirs)
     if params.enable_spec:
         cam = np.asarray(cam_pos, dtype=np.float64).reshape(-1, 3)[view[pix]]
@@ -195,6 +198,7 @@ def cone_lanes(pos_rough, normal, cam_pos, params, n, origin=(0.0, 0.0, 0.0), ex
         lanes["w"].append(_normalize(r))
         lanes["gamma"].append(rough * float(params.spec_aperture_scale))
         lanes["tmax"].append(np.full(m, float(params.max_dist)))
+        lanes["tie"].append(np.zeros(m, dtype=bool))
     slot += 1
     if params.enable_occ:
         lvec = np.asarray(params.light_pos, dtype=np.float64)[None, :] - o
@@ -208,11 +212,13 @@ def cone_lanes(pos_rough, normal, cam_pos, params, n, origin=(0.0, 0.0, 0.0), ex
         lanes["w"].append(wl)
         lanes["gamma"].append(np.full(m, float(params.occ_aperture)))
         lanes["tmax"].append(np.minimum(float(params.max_dist), dist))
+        lanes["tie"].append(np.zeros(m, dtype=bool))
     out = {}
     for k, v in lanes.items():
-        out[k] = np.concatenate(v) if v else np.zeros((0,) if k in ("pix", "slot", "gamma", "tmax") else (0, 3))
+        out[k] = np.concatenate(v) if v else np.zeros((0, 3) if k in ("o", "w") else (0,))
     out["pix"] = out["pix"].astype(np.int64)
     out["slot"] = out["slot"].astype(np.int64)
+    out["tie"] = out["tie"].astype(bool)
     return out
 
 
@@ -239,7 +245,7 @@ def march(mips, lanes, params, origin=(0.0, 0.0, 0.0), extent=1.0, record=False)
     c = np.zeros((m, 3))
     alpha = np.zeros(m)
     K = np.zeros(m, dtype=np.int64)
-    amb = np.abs(t - tmax) < AMBIG_T_REL * np.abs(tmax)
+    amb = (np.abs(t - tmax) < AMBIG_T_REL * np.abs(tmax)) | lanes.get("tie", np.zeros(m, dtype=bool))
     active = (t <= tmax) & (alpha < thresh)
     steps = []
     cap = int(np.ceil(np.max(tmax, initial=0.0) / (beta * v0))) + 4

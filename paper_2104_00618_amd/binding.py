@@ -1,0 +1,284 @@
+"""Thin ctypes binding of libvct (argument marshalling only).
+
+Every computation runs in the HIP library; torch supplies device memory and
+the current stream.  If libvct.so is missing the import of any entry point
+raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvct.so")
+
+VCT_F32, VCT_F16, VCT_BF16 = 0, 1, 2
+DTYPES = {"f32": VCT_F32, "f16": VCT_F16, "bf16": VCT_BF16}
+MAX_DIFFUSE = 16
+
+
+class VctError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class CGrid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("levels", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("origin", ctypes.c_float * 3), ("extent", ctypes.c_float)]
+
+
+class CGBuffer(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("pos_rough", ctypes.c_void_p), ("normal", ctypes.c_void_p), ("cam_pos", ctypes.c_void_p)]
+
+
+class CConeParams(ctypes.Structure):
+    _fields_ = [("n_diffuse", ctypes.c_int32),
+                ("diffuse_dir", (ctypes.c_float * 3) * MAX_DIFFUSE),
+                ("diffuse_weight", ctypes.c_float * MAX_DIFFUSE),
+                ("diffuse_aperture", ctypes.c_float),
+                ("enable_spec", ctypes.c_int32), ("enable_occ", ctypes.c_int32),
+                ("spec_aperture_scale", ctypes.c_float), ("occ_aperture", ctypes.c_float),
+                ("light_pos", ctypes.c_float * 3),
+                ("step_factor", ctypes.c_float), ("t0", ctypes.c_float), ("normal_offset", ctypes.c_float),
+                ("max_dist", ctypes.c_float), ("alpha_thresh", ctypes.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvct.so (built in-tree by paper_2104_00618_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2104_00618_amd.build.build() (no fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    sig = {
+        "vct_pyramid_bytes": [P(CGrid), P(sz)],
+        "vct_build_mips": [P(CGrid), vp, vp, sz, vp],
+        "vct_unpack_level": [P(CGrid), vp, ctypes.c_int32, vp, vp],
+        "vct_trace": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
+        "vct_count_samples": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
+        "vct_backward_workspace_bytes": [P(CGrid), P(CGBuffer), P(CConeParams), P(sz)],
+        "vct_trace_backward": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp, vp, sz, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.vct_last_error.argtypes = []
+    L.vct_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise VctError(rc, lib().vct_last_error().decode())
+
+
+# ---------------------------------------------------------------------------
+# argument structs
+# ---------------------------------------------------------------------------
+
+class Grid:
+    """Grid descriptor: N^3 base texels over [origin, origin + extent]^3."""
+
+    def __init__(self, n, levels=None, dtype="f32", origin=(0.0, 0.0, 0.0), extent=1.0):
+        self.n = int(n)
+        self.levels = int(levels) if levels is not None else int(round(math.log2(max(self.n, 1)))) + 1
+        self.dtype = dtype
+        self.origin = tuple(float(v) for v in origin)
+        self.extent = float(extent)
+
+    def c(self):
+        g = CGrid()
+        g.n = self.n
+        g.levels = self.levels
+        g.dtype = DTYPES[self.dtype] if isinstance(self.dtype, str) else int(self.dtype)
+        for i in range(3):
+            g.origin[i] = self.origin[i]
+        g.extent = self.extent
+        return g
+
+
+def cone_params(p):
+    """C struct from any object with the cone-set attributes (n_diffuse taken
+    from len(diffuse_dirs))."""
+    c = CConeParams()
+    dirs = [tuple(map(float, d)) for d in p.diffuse_dirs]
+    wts = [float(w) for w in p.diffuse_weights]
+    if len(dirs) > MAX_DIFFUSE or len(wts) != len(dirs):
+        raise ValueError("diffuse_dirs / diffuse_weights: at most 16 cones, one weight per direction")
+    c.n_diffuse = len(dirs)
+    for q, d in enumerate(dirs):
+        for i in range(3):
+            c.diffuse_dir[q][i] = d[i]
+        c.diffuse_weight[q] = wts[q]
+    c.diffuse_aperture = float(p.diffuse_aperture)
+    c.enable_spec = int(bool(p.enable_spec))
+    c.enable_occ = int(bool(p.enable_occ))
+    c.spec_aperture_scale = float(p.spec_aperture_scale)
+    c.occ_aperture = float(p.occ_aperture)
+    for i in range(3):
+        c.light_pos[i] = float(p.light_pos[i])
+    c.step_factor = float(p.step_factor)
+    c.t0 = float(p.t0)
+    c.normal_offset = float(p.normal_offset)
+    c.max_dist = float(p.max_dist)
+    c.alpha_thresh = float(p.alpha_thresh)
+    return c
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(dev):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _need(t, name, dtype, shape=None, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _gbuf(pos_rough, normal, cam_pos):
+    dev = pos_rough.device
+    b, h, w = pos_rough.shape[:3]
+    _need(pos_rough, "pos_rough", torch.float32, (b, h, w, 4))
+    _need(normal, "normal", torch.float32, (b, h, w, 4), dev)
+    _need(cam_pos, "cam_pos", torch.float32, (b, 3), dev)
+    g = CGBuffer()
+    g.b, g.h, g.w = b, h, w
+    g.pos_rough = pos_rough.data_ptr()
+    g.normal = normal.data_ptr()
+    g.cam_pos = cam_pos.data_ptr()
+    return g
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+
+def pyramid_bytes(grid):
+    n = ctypes.c_size_t()
+    _check(lib().vct_pyramid_bytes(ctypes.byref(grid.c()), ctypes.byref(n)))
+    return n.value
+
+
+def build_mips(base, grid, pyramid=None):
+    """Pack `base` (float32 [N,N,N,4] premultiplied RGBA, on the GPU) and build
+    its mip pyramid.  Returns the opaque pyramid buffer (uint8 tensor)."""
+    _need(base, "base", torch.float32, (grid.n, grid.n, grid.n, 4))
+    nb = pyramid_bytes(grid)
+    if pyramid is None:
+        pyramid = torch.empty(nb, dtype=torch.uint8, device=base.device)
+    _need(pyramid, "pyramid", torch.uint8, None, base.device)
+    with torch.cuda.device(base.device):
+        _check(lib().vct_build_mips(ctypes.byref(grid.c()), _ptr(base), _ptr(pyramid), pyramid.numel(),
+                                    _stream(base.device)))
+    return pyramid
+
+
+def unpack_level(pyramid, grid, level):
+    nl = grid.n >> level
+    out = torch.empty((nl, nl, nl, 4), dtype=torch.float32, device=pyramid.device)
+    with torch.cuda.device(pyramid.device):
+        _check(lib().vct_unpack_level(ctypes.byref(grid.c()), _ptr(pyramid), int(level), _ptr(out),
+                                      _stream(pyramid.device)))
+    return out
+
+
+def trace(pyramid, grid, pos_rough, normal, cam_pos, params, out=None):
+    """Forward cone trace.  Returns float32 [b,h,w,8] = (D.rgb, D.a, S.rgb, O)."""
+    gb = _gbuf(pos_rough, normal, cam_pos)
+    _need(pyramid, "pyramid", torch.uint8, None, pos_rough.device)
+    if out is None:
+        out = torch.empty(tuple(pos_rough.shape[:3]) + (8,), dtype=torch.float32, device=pos_rough.device)
+    _need(out, "out", torch.float32, tuple(pos_rough.shape[:3]) + (8,), pos_rough.device)
+    with torch.cuda.device(pos_rough.device):
+        _check(lib().vct_trace(ctypes.byref(grid.c()), _ptr(pyramid), ctypes.byref(gb),
+                               ctypes.byref(cone_params(params)), _ptr(out), _stream(pos_rough.device)))
+    return out
+
+
+def count_samples(pyramid, grid, pos_rough, normal, cam_pos, params):
+    """Total cone samples the forward march takes (integer, exact)."""
+    gb = _gbuf(pos_rough, normal, cam_pos)
+    cnt = torch.zeros(1, dtype=torch.int64, device=pos_rough.device)
+    with torch.cuda.device(pos_rough.device):
+        _check(lib().vct_count_samples(ctypes.byref(grid.c()), _ptr(pyramid), ctypes.byref(gb),
+                                       ctypes.byref(cone_params(params)), _ptr(cnt), _stream(pos_rough.device)))
+    return int(cnt.item())
+
+
+def backward_workspace_bytes(grid, pos_rough, normal, cam_pos, params):
+    gb = _gbuf(pos_rough, normal, cam_pos)
+    n = ctypes.c_size_t()
+    _check(lib().vct_backward_workspace_bytes(ctypes.byref(grid.c()), ctypes.byref(gb),
+                                              ctypes.byref(cone_params(params)), ctypes.byref(n)))
+    return n.value
+
+
+def trace_backward(pyramid, grid, pos_rough, normal, cam_pos, params, grad_out, workspace=None, grad_base=None):
+    """dL/d(base) float32 [N,N,N,4] for dL/d(out) = grad_out."""
+    gb = _gbuf(pos_rough, normal, cam_pos)
+    dev = pos_rough.device
+    _need(grad_out, "grad_out", torch.float32, tuple(pos_rough.shape[:3]) + (8,), dev)
+    nbytes = backward_workspace_bytes(grid, pos_rough, normal, cam_pos, params)
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    _need(workspace, "workspace", torch.uint8, None, dev)
+    if grad_base is None:
+        grad_base = torch.empty((grid.n, grid.n, grid.n, 4), dtype=torch.float32, device=dev)
+    _need(grad_base, "grad_base", torch.float32, (grid.n, grid.n, grid.n, 4), dev)
+    with torch.cuda.device(dev):
+        _check(lib().vct_trace_backward(ctypes.byref(grid.c()), _ptr(pyramid), ctypes.byref(gb),
+                                        ctypes.byref(cone_params(params)), _ptr(grad_out), _ptr(grad_base),
+                                        _ptr(workspace), workspace.numel(), _stream(dev)))
+    return grad_base
+
+
+class VCTTrace(torch.autograd.Function):
+    """out = trace(build_mips(base)); backward gives dL/d(base) through
+    vct_trace_backward (hand-written adjoint, deterministic)."""
+
+    @staticmethod
+    def forward(ctx, base, pos_rough, normal, cam_pos, grid, params):
+        pyr = build_mips(base.contiguous(), grid)
+        out = trace(pyr, grid, pos_rough, normal, cam_pos, params)
+        ctx.save_for_backward(pos_rough, normal, cam_pos)
+        ctx.pyr = pyr
+        ctx.grid = grid
+        ctx.params = params
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        pos_rough, normal, cam_pos = ctx.saved_tensors
+        g = trace_backward(ctx.pyr, ctx.grid, pos_rough, normal, cam_pos, ctx.params, grad_out.contiguous())
+        return g, None, None, None, None, None
+
+
+def render(base, grid, pos_rough, normal, cam_pos, params):
+    """Differentiable forward: build_mips + trace."""
+    return VCTTrace.apply(base, pos_rough, normal, cam_pos, grid, params)

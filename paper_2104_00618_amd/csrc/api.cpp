@@ -1,0 +1,276 @@
+// C ABI of libvct: argument validation, pyramid layout, launch planning.
+// Every entry point validates all arguments before enqueuing anything and
+// reports failures through a return code plus a thread-local
+// "function: message" string (the thesis's checkErrors(context) convention,
+// Section 5.4.1 "IoObject").
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "vct_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fn, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = std::string(fn) + ": " + buf;
+    return code;
+}
+
+void ok() { g_err.clear(); }
+
+bool finite(float v) { return isfinite(v); }
+
+int check_grid(const char* fn, const vct_grid* g) {
+    if (!g) return fail(VCT_EINVAL, fn, "grid is null");
+    if (g->n < 1 || g->n > VCT_MAX_N || (g->n & (g->n - 1)))
+        return fail(VCT_EINVAL, fn, "grid n = %d must be a power of two in [1, %d]", g->n, VCT_MAX_N);
+    int lmax = vct_log2i(g->n) + 1;
+    if (g->levels < 1 || g->levels > lmax)
+        return fail(VCT_EINVAL, fn, "grid levels = %d must be in [1, %d] for n = %d", g->levels, lmax, g->n);
+    if (g->dtype != VCT_F32 && g->dtype != VCT_F16 && g->dtype != VCT_BF16)
+        return fail(VCT_EINVAL, fn, "grid dtype = %d is not VCT_F32, VCT_F16 or VCT_BF16", g->dtype);
+    for (int i = 0; i < 3; ++i)
+        if (!finite(g->origin[i])) return fail(VCT_EINVAL, fn, "grid origin[%d] is not finite", i);
+    if (!finite(g->extent) || !(g->extent > 0.f))
+        return fail(VCT_EINVAL, fn, "grid extent must be finite and > 0");
+    return VCT_OK;
+}
+
+int check_gbuffer(const char* fn, const vct_gbuffer* gb) {
+    if (!gb) return fail(VCT_EINVAL, fn, "gbuffer is null");
+    if (gb->b < 0 || gb->h < 0 || gb->w < 0)
+        return fail(VCT_EINVAL, fn, "gbuffer shape (%d, %d, %d) has a negative extent", gb->b, gb->h, gb->w);
+    if (gb->h > 32768 || gb->w > 32768 || gb->b > 4096)
+        return fail(VCT_EINVAL, fn, "gbuffer shape (%d, %d, %d) exceeds (4096, 32768, 32768)", gb->b, gb->h, gb->w);
+    long long np = (long long)gb->b * gb->h * gb->w;
+    if (np > (1ll << 30)) return fail(VCT_EINVAL, fn, "gbuffer has %lld pixels, more than 2^30", np);
+    if (np > 0 && (!gb->pos_rough || !gb->normal || !gb->cam_pos))
+        return fail(VCT_EINVAL, fn, "gbuffer pos_rough, normal and cam_pos must be non-null");
+    return VCT_OK;
+}
+
+int check_params(const char* fn, const vct_grid* g, const vct_cone_params* p) {
+    if (!p) return fail(VCT_EINVAL, fn, "params is null");
+    if (p->n_diffuse < 0 || p->n_diffuse > VCT_MAX_DIFFUSE)
+        return fail(VCT_EINVAL, fn, "n_diffuse = %d must be in [0, %d]", p->n_diffuse, VCT_MAX_DIFFUSE);
+    for (int q = 0; q < p->n_diffuse; ++q) {
+        for (int i = 0; i < 3; ++i)
+            if (!finite(p->diffuse_dir[q][i])) return fail(VCT_EINVAL, fn, "diffuse_dir[%d] is not finite", q);
+        float l2 = p->diffuse_dir[q][0] * p->diffuse_dir[q][0] + p->diffuse_dir[q][1] * p->diffuse_dir[q][1] +
+                   p->diffuse_dir[q][2] * p->diffuse_dir[q][2];
+        if (!(l2 > 0.f)) return fail(VCT_EINVAL, fn, "diffuse_dir[%d] is the zero vector", q);
+        if (!finite(p->diffuse_weight[q])) return fail(VCT_EINVAL, fn, "diffuse_weight[%d] is not finite", q);
+    }
+    struct {
+        const char* name;
+        float v;
+    } nonneg[] = {{"diffuse_aperture", p->diffuse_aperture},
+                  {"spec_aperture_scale", p->spec_aperture_scale},
+                  {"occ_aperture", p->occ_aperture},
+                  {"t0", p->t0}};
+    for (auto& e : nonneg)
+        if (!finite(e.v) || e.v < 0.f) return fail(VCT_EINVAL, fn, "%s must be finite and >= 0", e.name);
+    for (int i = 0; i < 3; ++i)
+        if (!finite(p->light_pos[i])) return fail(VCT_EINVAL, fn, "light_pos[%d] is not finite", i);
+    if (!finite(p->normal_offset)) return fail(VCT_EINVAL, fn, "normal_offset is not finite");
+    if (!finite(p->step_factor) || !(p->step_factor > 0.f))
+        return fail(VCT_EINVAL, fn, "step_factor must be finite and > 0");
+    if (!finite(p->max_dist) || !(p->max_dist > 0.f)) return fail(VCT_EINVAL, fn, "max_dist must be finite and > 0");
+    if (!finite(p->alpha_thresh) || !(p->alpha_thresh > 0.f))
+        return fail(VCT_EINVAL, fn, "alpha_thresh must be finite and > 0");
+    double voxel = (double)g->extent / g->n;
+    double steps = (double)p->max_dist / ((double)p->step_factor * voxel);
+    if (steps > VCT_MAX_STEPS)
+        return fail(VCT_EINVAL, fn, "max_dist / (step_factor * voxel) = %.3g exceeds %d samples per cone", steps,
+                    VCT_MAX_STEPS);
+    return VCT_OK;
+}
+
+void split(double v, float& hi, float& lo) {
+    hi = (float)v;
+    lo = (float)(v - (double)hi);
+}
+
+TraceArgs make_args(const vct_grid* g, const PyrLayout& L, const void* pyr, const vct_gbuffer* gb,
+                    const vct_cone_params* p) {
+    TraceArgs a{};
+    a.n = g->n;
+    a.levels = g->levels;
+    for (int i = 0; i < 3; ++i) a.origin[i] = g->origin[i];
+    double scale = (double)g->n / (double)g->extent;
+    split(scale, a.scale_hi, a.scale_lo);
+    a.voxel = (float)((double)g->extent / g->n);
+    for (int l = 0; l < VCT_MAX_LEVELS; ++l) {
+        if (l < g->levels) {
+            a.lv[l].n = g->n >> l;
+            a.lv[l].nb = L.nb[l];
+            a.lv[l].off = (uint32_t)L.off[l];
+        } else {
+            a.lv[l].n = 1;
+            a.lv[l].nb = 1;
+            a.lv[l].off = 0;
+        }
+    }
+    a.pyr = pyr;
+    a.b = gb->b;
+    a.h = gb->h;
+    a.w = gb->w;
+    a.tiles_x = (gb->w + 15) / 16;
+    a.tiles_y = (gb->h + 15) / 16;
+    a.n_tiles = a.tiles_x * a.tiles_y * gb->b;
+    a.pos_rough = reinterpret_cast<const float4*>(gb->pos_rough);
+    a.normal = reinterpret_cast<const float4*>(gb->normal);
+    a.cam_pos = gb->cam_pos;
+    a.n_diffuse = p->n_diffuse;
+    a.enable_spec = p->enable_spec ? 1 : 0;
+    a.enable_occ = p->enable_occ ? 1 : 0;
+    for (int q = 0; q < p->n_diffuse; ++q) {
+        for (int i = 0; i < 3; ++i) a.dir[q][i] = p->diffuse_dir[q][i];
+        a.weight[q] = p->diffuse_weight[q];
+    }
+    a.diffuse_aperture = p->diffuse_aperture;
+    a.spec_aperture_scale = p->spec_aperture_scale;
+    a.occ_aperture = p->occ_aperture;
+    for (int i = 0; i < 3; ++i) {
+        double lt = ((double)p->light_pos[i] - (double)g->origin[i]) * scale;
+        split(lt, a.light_tex[i][0], a.light_tex[i][1]);
+    }
+    a.step_factor = p->step_factor;
+    a.t0 = p->t0;
+    a.normal_offset = p->normal_offset;
+    a.max_dist = p->max_dist;
+    a.alpha_thresh = p->alpha_thresh;
+    double voxel = (double)g->extent / g->n;
+    a.max_steps = (int)ceil((double)p->max_dist / ((double)p->step_factor * voxel)) + 2;
+    return a;
+}
+
+int device_error(const char* fn, hipError_t e) {
+    return fail(VCT_EDEVICE, fn, "HIP error %d (%s)", (int)e, hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+int vct_pyramid_bytes(const vct_grid* grid, size_t* bytes) {
+    const char* fn = "vct_pyramid_bytes";
+    if (int r = check_grid(fn, grid)) return r;
+    if (!bytes) return fail(VCT_EINVAL, fn, "bytes is null");
+    *bytes = (size_t)vct_make_layout(grid->n, grid->levels, grid->dtype).bytes;
+    ok();
+    return VCT_OK;
+}
+
+int vct_build_mips(const vct_grid* grid, const float* base, void* pyramid, size_t pyramid_bytes,
+                   hipStream_t stream) {
+    const char* fn = "vct_build_mips";
+    if (int r = check_grid(fn, grid)) return r;
+    if (!base || !pyramid) return fail(VCT_EINVAL, fn, "base and pyramid must be non-null");
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    if (pyramid_bytes < (size_t)L.bytes)
+        return fail(VCT_EWORKSPACE, fn, "pyramid buffer has %zu bytes, needs %lld", pyramid_bytes,
+                    (long long)L.bytes);
+    hipError_t e = vct_launch_build_mips(L, base, pyramid, stream);
+    if (e != hipSuccess) return device_error(fn, e);
+    ok();
+    return VCT_OK;
+}
+
+int vct_unpack_level(const vct_grid* grid, const void* pyramid, int32_t level, float* out, hipStream_t stream) {
+    const char* fn = "vct_unpack_level";
+    if (int r = check_grid(fn, grid)) return r;
+    if (!pyramid || !out) return fail(VCT_EINVAL, fn, "pyramid and out must be non-null");
+    if (level < 0 || level >= grid->levels)
+        return fail(VCT_EINVAL, fn, "level = %d must be in [0, %d]", level, grid->levels - 1);
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    hipError_t e = vct_launch_unpack(L, pyramid, level, out, stream);
+    if (e != hipSuccess) return device_error(fn, e);
+    ok();
+    return VCT_OK;
+}
+
+static int trace_common(const char* fn, const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                        const vct_cone_params* params, float* out, unsigned long long* count, bool counting,
+                        hipStream_t stream) {
+    if (int r = check_grid(fn, grid)) return r;
+    if (int r = check_gbuffer(fn, gbuf)) return r;
+    if (int r = check_params(fn, grid, params)) return r;
+    long long np = (long long)gbuf->b * gbuf->h * gbuf->w;
+    if (counting && !count) return fail(VCT_EINVAL, fn, "count is null");
+    if (!counting && !out && np > 0) return fail(VCT_EINVAL, fn, "out is null");
+    if (!pyramid) return fail(VCT_EINVAL, fn, "pyramid is null");
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    TraceArgs a = make_args(grid, L, pyramid, gbuf, params);
+    if (a.n_tiles == 0 && !count) {
+        ok();
+        return VCT_OK;
+    }
+    hipError_t e = vct_launch_trace(a, grid->dtype, out, count, stream);
+    if (e != hipSuccess) return device_error(fn, e);
+    ok();
+    return VCT_OK;
+}
+
+int vct_trace(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf, const vct_cone_params* params,
+              float* out, hipStream_t stream) {
+    return trace_common("vct_trace", grid, pyramid, gbuf, params, out, nullptr, false, stream);
+}
+
+int vct_count_samples(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                      const vct_cone_params* params, unsigned long long* count, hipStream_t stream) {
+    return trace_common("vct_count_samples", grid, pyramid, gbuf, params, nullptr, count, true, stream);
+}
+
+int vct_backward_workspace_bytes(const vct_grid* grid, const vct_gbuffer* gbuf, const vct_cone_params* params,
+                                 size_t* bytes) {
+    const char* fn = "vct_backward_workspace_bytes";
+    if (int r = check_grid(fn, grid)) return r;
+    if (int r = check_gbuffer(fn, gbuf)) return r;
+    if (int r = check_params(fn, grid, params)) return r;
+    if (!bytes) return fail(VCT_EINVAL, fn, "bytes is null");
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    TraceArgs a = make_args(grid, L, nullptr, gbuf, params);
+    *bytes = (size_t)vct_plan_backward(L, a).bytes;
+    ok();
+    return VCT_OK;
+}
+
+int vct_trace_backward(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                       const vct_cone_params* params, const float* grad_out, float* grad_base, void* workspace,
+                       size_t workspace_bytes, hipStream_t stream) {
+    const char* fn = "vct_trace_backward";
+    if (int r = check_grid(fn, grid)) return r;
+    if (int r = check_gbuffer(fn, gbuf)) return r;
+    if (int r = check_params(fn, grid, params)) return r;
+    if (!(params->alpha_thresh <= 1.0f))
+        return fail(VCT_EINVAL, fn, "alpha_thresh = %g: the adjoint needs alpha_thresh <= 1 (transmittance of a "
+                    "continuing cone must stay positive)", (double)params->alpha_thresh);
+    if (!pyramid || !grad_base || !workspace)
+        return fail(VCT_EINVAL, fn, "pyramid, grad_base and workspace must be non-null");
+    long long np = (long long)gbuf->b * gbuf->h * gbuf->w;
+    if (np > 0 && !grad_out) return fail(VCT_EINVAL, fn, "grad_out is null");
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    TraceArgs a = make_args(grid, L, pyramid, gbuf, params);
+    BackwardPlan P = vct_plan_backward(L, a);
+    if (workspace_bytes < (size_t)P.bytes)
+        return fail(VCT_EWORKSPACE, fn, "workspace has %zu bytes, needs %lld", workspace_bytes, (long long)P.bytes);
+    hipError_t e = vct_launch_backward(L, a, P, grad_out, grad_base, workspace, stream);
+    if (e != hipSuccess) return device_error(fn, e);
+    ok();
+    return VCT_OK;
+}
+
+const char* vct_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

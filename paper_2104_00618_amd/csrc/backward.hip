@@ -1,0 +1,213 @@
+// Adjoint of the cone trace with respect to the base grid (step counts held
+// fixed), transmittance recomputed by re-marching instead of stored.
+//
+// Per cone with samples s_k = (c_k, a_k), T_k = 1 - A_k and totals (C_K, A_K):
+//   dL/dc_k = T_k dL/dC
+//   dL/da_k = -T_k (dL/dC . (C_K - C_{k+1}) - dL/dA T_K) / T_{k+1}   (k < K-1)
+//   dL/da_{K-1} = T_{K-1} dL/dA
+// (derivatives of the front-to-back recurrences of Section 4.3.2).  While a
+// cone continues, A_{k+1} < alpha_thresh, so T_{k+1} > 1 - alpha_thresh and,
+// since T is computed as 1 - A in float32, T_{k+1} >= 2^-24 in any case.
+// C is accumulated as a double-float in both passes so that C_K - C_{k+1} is
+// accurate to ~1e-14 of C_K.
+//
+// Deterministic reduction: every tap contribution g * w is converted to a
+// 64-bit fixed-point integer with a per-call power-of-two scale 2^E (level l
+// uses 2^(E - 3l), folding the 1/8 of each mip level into the scale) and added
+// with integer atomics.  Integer addition is exact and associative, so the
+// result is bitwise independent of execution order.  E is chosen from a bound
+// on the sum of |contributions| computed in pass 1 so that no partial sum can
+// exceed 2^62.  The mip adjoint (each child receives 1/8 of its parent's
+// gradient) is then a gather: grad_base[x] = 2^-E * sum_l acc_l[ancestor_l(x)].
+//
+// Kernels, in stream order:
+//   k_fill_zero   clear the accumulator
+//   k_bwd_pass1   per pixel: re-march every cone, store (C_K, A_K, K), and the
+//                 workgroup's sum of per-cone contribution bounds
+//   k_bwd_scale   one workgroup: fixed-order sum of the bounds -> E
+//   k_bwd_pass2   per pixel: re-march, emit fixed-point tap gradients
+//   k_mip_adjoint per base texel: gather over levels, convert to float32
+#include "bwd_pixel.h"
+
+namespace {
+
+using namespace vct;
+
+constexpr int kThreads = 256;
+
+template <int DT>
+__global__ __launch_bounds__(kThreads) void k_bwd_pass1(TraceArgs a, const float4* __restrict__ gout,
+                                                        LaneState* __restrict__ state, float* __restrict__ part) {
+    __shared__ LevelTable T;
+    __shared__ float s_part[kThreads / 64];
+    load_level_table(a, &T);
+    __syncthreads();
+    const int tile = xcd_tile(blockIdx.x, a.n_tiles);
+    int view, y, x;
+    tile_pixel(a, tile, threadIdx.x, view, y, x);
+    float bound = 0.f;
+    if (x < a.w && y < a.h) bound = pass1_pixel<DT>(a, T, gout, state, view, ((size_t)view * a.h + y) * a.w + x);
+    // fixed-order workgroup sum
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) bound += __shfl_xor(bound, o, 64);
+    if (lane == 0) s_part[wv] = bound;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
+}
+
+// ctl[0] = E, ctl[1] = 1 if the bound is not finite
+__global__ __launch_bounds__(kThreads) void k_bwd_scale(const float* __restrict__ part, int n, int* __restrict__ ctl) {
+    __shared__ float s[kThreads];
+    float acc = 0.f;
+    for (int i = threadIdx.x; i < n; i += kThreads) acc += part[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float total = s[0];
+        int E = 0, bad = 0;
+        if (!isfinite(total)) {
+            bad = 1;
+        } else if (total > 0.f) {
+            int ex;
+            frexpf(total, &ex);     // total < 2^ex
+            E = 61 - ex;            // total * 2^E < 2^61
+        }
+        ctl[0] = E;
+        ctl[1] = bad;
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(kThreads) void k_bwd_pass2(TraceArgs a, const float4* __restrict__ gout,
+                                                        const LaneState* __restrict__ state,
+                                                        const int* __restrict__ ctl,
+                                                        unsigned long long* __restrict__ acc) {
+    __shared__ LevelTable T;
+    load_level_table(a, &T);
+    __syncthreads();
+    const int E = ctl[0];
+    const int tile = xcd_tile(blockIdx.x, a.n_tiles);
+    int view, y, x;
+    tile_pixel(a, tile, threadIdx.x, view, y, x);
+    if (x < a.w && y < a.h) pass2_pixel<DT>(a, T, gout, state, E, acc, view, ((size_t)view * a.h + y) * a.w + x);
+}
+
+__global__ void k_fill_zero(uint4* __restrict__ p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+struct AdjArgs {
+    int32_t n, levels;
+    int32_t nb[VCT_MAX_LEVELS];
+    uint32_t off[VCT_MAX_LEVELS];
+};
+
+__global__ __launch_bounds__(256) void k_mip_adjoint(AdjArgs m, const long long* __restrict__ acc,
+                                                     const int* __restrict__ ctl, float4* __restrict__ grad) {
+    const int E = ctl[0];
+    const bool bad = ctl[1] != 0;
+    const uint32_t n = m.n;
+    const uint32_t total = n * n * n;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+        int x = t % n, y = (t / n) % n, z = t / (n * n);
+        long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+        for (int l = 0; l < VCT_MAX_LEVELS; ++l) {
+            if (l < m.levels) {
+                uint32_t idx = m.off[l] + vct_brick_index(x >> l, y >> l, z >> l, m.nb[l]);
+                const long long* p = acc + (size_t)idx * 4;
+                longlong2 u = reinterpret_cast<const longlong2*>(p)[0];
+                longlong2 v = reinterpret_cast<const longlong2*>(p)[1];
+                s0 += u.x;
+                s1 += u.y;
+                s2 += v.x;
+                s3 += v.y;
+            }
+        }
+        float4 g;
+        if (bad) {
+            g = make_float4(__int_as_float(0x7fc00000), __int_as_float(0x7fc00000), __int_as_float(0x7fc00000),
+                            __int_as_float(0x7fc00000));
+        } else {
+            g = make_float4(ldexpf((float)s0, -E), ldexpf((float)s1, -E), ldexpf((float)s2, -E),
+                            ldexpf((float)s3, -E));
+        }
+        grad[t] = g;
+    }
+}
+
+template <int DT>
+hipError_t run_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPlan& P, const float* grad_out,
+                        float* grad_base, void* ws, hipStream_t s) {
+    char* w = static_cast<char*>(ws);
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(w + P.acc_off);
+    LaneState* state = reinterpret_cast<LaneState*>(w + P.state_off);
+    float* part = reinterpret_cast<float*>(w + P.part_off);
+    int* ctl = reinterpret_cast<int*>(w + P.ctl_off);
+    size_t n16 = (size_t)P.acc_bytes / 16;
+    int fb = (int)((n16 + 255) / 256);
+    if (fb > 8192) fb = 8192;
+    hipLaunchKernelGGL(k_fill_zero, dim3(fb), dim3(256), 0, s, reinterpret_cast<uint4*>(acc), n16);
+    const float4* g4 = reinterpret_cast<const float4*>(grad_out);
+    if (a.n_tiles > 0) {
+        hipLaunchKernelGGL(k_bwd_pass1<DT>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, part);
+    }
+    hipLaunchKernelGGL(k_bwd_scale, dim3(1), dim3(kThreads), 0, s, part, (int)P.n_blocks, ctl);
+    if (a.n_tiles > 0) {
+        hipLaunchKernelGGL(k_bwd_pass2<DT>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, ctl, acc);
+    }
+    AdjArgs m{};
+    m.n = L.n;
+    m.levels = L.levels;
+    for (int l = 0; l < L.levels; ++l) {
+        m.nb[l] = L.nb[l];
+        m.off[l] = (uint32_t)L.off[l];
+    }
+    uint32_t total = (uint32_t)L.n * L.n * L.n;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_mip_adjoint, dim3(blocks), dim3(256), 0, s, m, reinterpret_cast<const long long*>(acc), ctl,
+                       reinterpret_cast<float4*>(grad_base));
+    return hipGetLastError();
+}
+
+int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
+
+}  // namespace
+
+BackwardPlan vct_plan_backward(const PyrLayout& L, const TraceArgs& a) {
+    BackwardPlan P{};
+    int64_t npix = (int64_t)a.b * a.h * a.w;
+    int nslots = a.n_diffuse + 2;
+    P.n_lanes = npix * nslots;
+    P.n_blocks = a.n_tiles;
+    int64_t off = 0;
+    P.acc_off = off;
+    P.acc_bytes = align256(L.total_texels * 32);
+    off += P.acc_bytes;
+    P.state_off = off;
+    P.state_bytes = align256(P.n_lanes * (int64_t)sizeof(LaneState));
+    off += P.state_bytes;
+    P.part_off = off;
+    P.part_bytes = align256(P.n_blocks * 4 + 4);
+    off += P.part_bytes;
+    P.ctl_off = off;
+    P.ctl_bytes = 256;
+    off += P.ctl_bytes;
+    P.bytes = off;
+    return P;
+}
+
+hipError_t vct_launch_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPlan& P, const float* grad_out,
+                               float* grad_base, void* ws, hipStream_t s) {
+    switch (L.dtype) {
+        case VCT_F32: return run_backward<VCT_F32>(L, a, P, grad_out, grad_base, ws, s);
+        case VCT_F16: return run_backward<VCT_F16>(L, a, P, grad_out, grad_base, ws, s);
+        default: return run_backward<VCT_BF16>(L, a, P, grad_out, grad_base, ws, s);
+    }
+}

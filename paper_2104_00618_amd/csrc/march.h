@@ -1,0 +1,382 @@
+// Per-lane cone setup, quadrilinear sampler and front-to-back march shared by
+// the forward and backward kernels (Section 4.3.2 cone-trace function,
+// Section 4.5 colour supersampler, Sections 4.2 / 5.4.4 cone set).
+//
+// Precision.  Tap weights are frac(p * N_l - 1/2), so a world-space position
+// error dp becomes a weight error dp * N_l.  Float32 positions near 1 carry
+// 6e-8 of rounding, i.e. ~1.5e-5 texel at N = 256, too much for 1e-5 parity at
+// hard 0/1 opacity edges.  The march therefore keeps the distance t and the
+// texel-space origin as double-floats (hi + lo float pairs, Knuth's TwoSum and
+// Dekker's TwoProduct via fma) and forms texel coordinates U = O + t W as a
+// double-float before floor/frac.  Directions stay float32: once the LOD
+// follows the cone diameter, a direction error dw moves a tap by only
+// dw / (2 tan(aperture / 2)) texels of the sampled level.
+#pragma once
+
+#include "texel.h"
+#include "vct_internal.h"
+
+namespace vct {
+
+struct df {
+    float hi, lo;
+};
+
+__device__ __forceinline__ df two_sum(float a, float b) {
+#pragma clang fp contract(off)
+    float s = a + b;
+    float bp = s - a;
+    float e = (a - (s - bp)) + (b - bp);
+    return {s, e};
+}
+
+__device__ __forceinline__ df fast_two_sum(float a, float b) {
+#pragma clang fp contract(off)
+    float s = a + b;
+    float e = b - (s - a);
+    return {s, e};
+}
+
+__device__ __forceinline__ df two_prod(float a, float b) {
+#pragma clang fp contract(off)
+    float p = a * b;
+    float e = __builtin_fmaf(a, b, -p);
+    return {p, e};
+}
+
+// a + b for a double-float a and a float b
+__device__ __forceinline__ df df_add(df a, float b) {
+#pragma clang fp contract(off)
+    df s = two_sum(a.hi, b);
+    float lo = s.lo + a.lo;
+    return fast_two_sum(s.hi, lo);
+}
+
+// O + t * W per axis (double-float O and t, float W)
+__device__ __forceinline__ df df_axis(df O, df t, float W) {
+#pragma clang fp contract(off)
+    df p = two_prod(t.hi, W);
+    float plo = __builtin_fmaf(t.lo, W, p.lo);
+    df s = two_sum(O.hi, p.hi);
+    float lo = s.lo + (O.lo + plo);
+    return fast_two_sum(s.hi, lo);
+}
+
+// a * b for a double-float a and b
+__device__ __forceinline__ df df_mul(df a, df b) {
+#pragma clang fp contract(off)
+    df p = two_prod(a.hi, b.hi);
+    float lo = p.lo + (a.hi * b.lo + a.lo * b.hi);
+    return fast_two_sum(p.hi, lo);
+}
+
+__device__ __forceinline__ float3 normalize3(float x, float y, float z) {
+    float r = sqrtf(x * x + y * y + z * z);
+    return make_float3(x / r, y / r, z / r);
+}
+
+// Shared-memory copy of the level table (per-lane levels index it).
+struct LevelTable {
+    int32_t n[VCT_MAX_LEVELS];
+    int32_t nb[VCT_MAX_LEVELS];
+    uint32_t off[VCT_MAX_LEVELS];
+};
+
+__device__ __forceinline__ void load_level_table(const TraceArgs& a, LevelTable* t) {
+#pragma unroll
+    for (int l = 0; l < VCT_MAX_LEVELS; ++l)
+        if ((int)threadIdx.x == l) {
+            t->n[l] = a.lv[l].n;
+            t->nb[l] = a.lv[l].nb;
+            t->off[l] = a.lv[l].off;
+        }
+}
+
+// Texel-space coordinate split into base tap and fraction, for level scale 2^-l.
+struct Axis {
+    int i0, i1;
+    float w1;  // weight of i1; i0 gets 1 - w1
+};
+
+__device__ __forceinline__ Axis axis_taps(df U, float sc, int nl) {
+    float u = U.hi * sc - 0.5f;          // exact: power-of-two scale, and u >= -1/4 whenever it matters
+    float ulo = U.lo * sc;
+    float fl = floorf(u);
+    float ph = (u - fl) + ulo;
+    int i = (int)fl;
+    if (ph < 0.0f) {
+        ph += 1.0f;
+        i -= 1;
+    } else if (ph >= 1.0f) {
+        ph -= 1.0f;
+        i += 1;
+    }
+    i = min(max(i, -1), nl);             // keeps i + 1 from overflowing for far-away points
+    Axis a;                              // clamp-to-edge: both taps inside [0, nl - 1]
+    a.i0 = min(max(i, 0), nl - 1);
+    a.i1 = min(max(i + 1, 0), nl - 1);
+    a.w1 = ph;
+    return a;
+}
+
+struct Taps {
+    uint32_t idx[8];
+    float w[8];
+};
+
+// The 8 taps and trilinear weights of level l at texel-space position U (level-0 texels).
+__device__ __forceinline__ void level_taps(const LevelTable& T, int l, df Ux, df Uy, df Uz, Taps& tp) {
+    const int nl = T.n[l];
+    const int nb = T.nb[l];
+    const uint32_t off = T.off[l];
+    const float sc = __int_as_float((127 - l) << 23);   // 2^-l
+    Axis ax = axis_taps(Ux, sc, nl);
+    Axis ay = axis_taps(Uy, sc, nl);
+    Axis az = axis_taps(Uz, sc, nl);
+    const float wx0 = 1.0f - ax.w1, wy0 = 1.0f - ay.w1, wz0 = 1.0f - az.w1;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        int dz = q >> 2, dy = (q >> 1) & 1, dx = q & 1;
+        int x = dx ? ax.i1 : ax.i0;
+        int y = dy ? ay.i1 : ay.i0;
+        int z = dz ? az.i1 : az.i0;
+        tp.idx[q] = off + vct_brick_index(x, y, z, nb);
+        tp.w[q] = (dx ? ax.w1 : wx0) * (dy ? ay.w1 : wy0) * (dz ? az.w1 : wz0);
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ float4 gather(const void* __restrict__ pyr, const Taps& tp) {
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        float4 v = vct_load_texel<DT>(pyr, tp.idx[q]);
+        s.x = __builtin_fmaf(tp.w[q], v.x, s.x);
+        s.y = __builtin_fmaf(tp.w[q], v.y, s.y);
+        s.z = __builtin_fmaf(tp.w[q], v.z, s.z);
+        s.w = __builtin_fmaf(tp.w[q], v.w, s.w);
+    }
+    return s;
+}
+
+// LOD of a diameter d (world units): lambda = clamp(log2(d / voxel), 0, L - 1).
+__device__ __forceinline__ float lod_of(const TraceArgs& a, float d) {
+    float lam = log2f(d * a.scale_hi);
+    return fminf(fmaxf(lam, 0.0f), (float)(a.levels - 1));
+}
+
+// One cone, fully set up.
+struct Cone {
+    df Ox, Oy, Oz;        // origin, level-0 texel units
+    float Wx, Wy, Wz;     // axis times N / extent
+    float two_tan;        // 2 tan(aperture / 2)
+    float tmax;
+};
+
+// Per-pixel setup shared by all cones of the pixel.
+struct PixelSetup {
+    df Ox, Oy, Oz;
+    float nx, ny, nz;                 // unit normal
+    float tx, ty, tz, bx, by, bz;     // tangent frame
+    float px, py, pz;                 // surface point (world)
+    float rough;
+};
+
+__device__ __forceinline__ df to_texel(const TraceArgs& a, float x, int ax) {
+    // (x - origin) * N / extent as a double-float
+    df d = two_sum(x, -a.origin[ax]);
+    df sc = {a.scale_hi, a.scale_lo};
+    return df_mul(d, sc);
+}
+
+__device__ __forceinline__ PixelSetup pixel_setup(const TraceArgs& a, float4 pr, float4 nr) {
+    PixelSetup P;
+    float3 n = normalize3(nr.x, nr.y, nr.z);
+    P.nx = n.x;
+    P.ny = n.y;
+    P.nz = n.z;
+    P.px = pr.x;
+    P.py = pr.y;
+    P.pz = pr.z;
+    P.rough = pr.w;
+    // o = x + n * normal_offset * voxel  ->  texel units: (x - origin) * N/extent + n * normal_offset
+    df X = to_texel(a, pr.x, 0), Y = to_texel(a, pr.y, 1), Z = to_texel(a, pr.z, 2);
+    P.Ox = df_add(X, n.x * a.normal_offset);
+    P.Oy = df_add(Y, n.y * a.normal_offset);
+    P.Oz = df_add(Z, n.z * a.normal_offset);
+    // tangent frame: helper axis x if the normal is near +-y, else y
+    float ax = 0.f, ay = 1.f;
+    if (fabsf(n.y) > 0.9f) {
+        ax = 1.f;
+        ay = 0.f;
+    }
+    // t = normalize(a x n) with a = (ax, ay, 0)
+    float3 t = normalize3(ay * n.z, -ax * n.z, ax * n.y - ay * n.x);
+    P.tx = t.x;
+    P.ty = t.y;
+    P.tz = t.z;
+    // b = n x t
+    P.bx = n.y * t.z - n.z * t.y;
+    P.by = n.z * t.x - n.x * t.z;
+    P.bz = n.x * t.y - n.y * t.x;
+    return P;
+}
+
+__device__ __forceinline__ Cone make_cone(const TraceArgs& a, const PixelSetup& P, float3 w, float aperture,
+                                          float tmax) {
+    Cone c;
+    c.Ox = P.Ox;
+    c.Oy = P.Oy;
+    c.Oz = P.Oz;
+    c.Wx = w.x * a.scale_hi;
+    c.Wy = w.y * a.scale_hi;
+    c.Wz = w.z * a.scale_hi;
+    c.two_tan = 2.0f * tanf(0.5f * aperture);
+    c.tmax = tmax;
+    return c;
+}
+
+// Axis of cone slot `slot` of a pixel (0..u-1 diffuse, u specular, u+1 occlusion);
+// sets aperture and t_max.
+__device__ __forceinline__ Cone cone_for_slot(const TraceArgs& a, const PixelSetup& P, int slot, float3 cam) {
+    if (slot < a.n_diffuse) {
+        float dx = a.dir[slot][0], dy = a.dir[slot][1], dz = a.dir[slot][2];
+        float3 w = normalize3(P.tx * dx + P.bx * dy + P.nx * dz, P.ty * dx + P.by * dy + P.ny * dz,
+                              P.tz * dx + P.bz * dy + P.nz * dz);
+        return make_cone(a, P, w, a.diffuse_aperture, a.max_dist);
+    }
+    if (slot == a.n_diffuse) {
+        float3 v = normalize3(P.px - cam.x, P.py - cam.y, P.pz - cam.z);
+        float vn = v.x * P.nx + v.y * P.ny + v.z * P.nz;
+        float3 r = normalize3(v.x - 2.f * vn * P.nx, v.y - 2.f * vn * P.ny, v.z - 2.f * vn * P.nz);
+        return make_cone(a, P, r, P.rough * a.spec_aperture_scale, a.max_dist);
+    }
+    // occlusion: toward the light, in texel units
+    df Lx = {a.light_tex[0][0], a.light_tex[0][1]};
+    df Ly = {a.light_tex[1][0], a.light_tex[1][1]};
+    df Lz = {a.light_tex[2][0], a.light_tex[2][1]};
+    float dx = (Lx.hi - P.Ox.hi) + (Lx.lo - P.Ox.lo);
+    float dy = (Ly.hi - P.Oy.hi) + (Ly.lo - P.Oy.lo);
+    float dz = (Lz.hi - P.Oz.hi) + (Lz.lo - P.Oz.lo);
+    float len = sqrtf(dx * dx + dy * dy + dz * dz);
+    float dist = len / a.scale_hi;
+    float3 w = len > 0.f ? make_float3(dx / len, dy / len, dz / len) : make_float3(0.f, 0.f, 0.f);
+    return make_cone(a, P, w, a.occ_aperture, fminf(a.max_dist, dist));
+}
+
+// Quadrilinear sample at distance t along the cone.
+template <int DT>
+__device__ __forceinline__ float4 sample_at(const TraceArgs& a, const LevelTable& T, const Cone& c, df t,
+                                            float lam) {
+    df Ux = df_axis(c.Ox, t, c.Wx);
+    df Uy = df_axis(c.Oy, t, c.Wy);
+    df Uz = df_axis(c.Oz, t, c.Wz);
+    int l0 = (int)lam;
+    float f = lam - (float)l0;
+    Taps tp;
+    level_taps(T, l0, Ux, Uy, Uz, tp);
+    float4 s0 = gather<DT>(a.pyr, tp);
+    if (f > 0.0f) {
+        int l1 = min(l0 + 1, a.levels - 1);
+        level_taps(T, l1, Ux, Uy, Uz, tp);
+        float4 s1 = gather<DT>(a.pyr, tp);
+        float g = 1.0f - f;
+        s0.x = __builtin_fmaf(f, s1.x, g * s0.x);
+        s0.y = __builtin_fmaf(f, s1.y, g * s0.y);
+        s0.z = __builtin_fmaf(f, s1.z, g * s0.z);
+        s0.w = __builtin_fmaf(f, s1.w, g * s0.w);
+    }
+    return s0;
+}
+
+__device__ __forceinline__ bool t_within(df t, float tmax) {
+    return t.hi < tmax || (t.hi == tmax && t.lo <= 0.0f);
+}
+
+struct MarchResult {
+    float r, g, b, a;
+    int k;
+};
+
+// Forward march of one cone (Section 4.3.2): sample while t <= t_max and
+// A < alpha_thresh; C += (1 - A) s.rgb, A += (1 - A) s.a, t += beta d.
+template <int DT>
+__device__ __forceinline__ MarchResult march(const TraceArgs& a, const LevelTable& T, const Cone& c) {
+    MarchResult m = {0.f, 0.f, 0.f, 0.f, 0};
+    df t = {a.t0, 0.0f};
+    for (int k = 0; k < a.max_steps; ++k) {
+        if (!t_within(t, c.tmax) || !(m.a < a.alpha_thresh)) break;
+        float d = fmaxf(c.two_tan * t.hi, a.voxel);
+        float lam = lod_of(a, d);
+        float4 s = sample_at<DT>(a, T, c, t, lam);
+        float tr = 1.0f - m.a;
+        m.r = __builtin_fmaf(tr, s.x, m.r);
+        m.g = __builtin_fmaf(tr, s.y, m.g);
+        m.b = __builtin_fmaf(tr, s.z, m.b);
+        m.a = __builtin_fmaf(tr, s.w, m.a);
+        m.k = k + 1;
+        t = df_add(t, a.step_factor * d);
+    }
+    return m;
+}
+
+// All cones of one pixel (slots 0..u-1 diffuse, specular, occlusion); the
+// 8-float epilogue (D.rgb, D.a, S.rgb, O) goes to o0, o1, the sample count to k.
+template <int DT>
+__device__ __forceinline__ void trace_pixel(const TraceArgs& a, const LevelTable& T, int view, size_t pix,
+                                            float4& o0, float4& o1, unsigned int& ksum) {
+    o0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    o1 = o0;
+    ksum = 0;
+    float4 nr = a.normal[pix];
+    if (nr.w == 0.0f) return;
+    float4 pr = a.pos_rough[pix];
+    PixelSetup P = pixel_setup(a, pr, nr);
+    float3 cam = make_float3(a.cam_pos[3 * view], a.cam_pos[3 * view + 1], a.cam_pos[3 * view + 2]);
+    for (int q = 0; q < a.n_diffuse; ++q) {
+        Cone c = cone_for_slot(a, P, q, cam);
+        MarchResult m = march<DT>(a, T, c);
+        float wq = a.weight[q];
+        o0.x = __builtin_fmaf(wq, m.r, o0.x);
+        o0.y = __builtin_fmaf(wq, m.g, o0.y);
+        o0.z = __builtin_fmaf(wq, m.b, o0.z);
+        o0.w = __builtin_fmaf(wq, m.a, o0.w);
+        ksum += m.k;
+    }
+    if (a.enable_spec) {
+        Cone c = cone_for_slot(a, P, a.n_diffuse, cam);
+        MarchResult m = march<DT>(a, T, c);
+        o1.x = m.r;
+        o1.y = m.g;
+        o1.z = m.b;
+        ksum += m.k;
+    }
+    if (a.enable_occ) {
+        Cone c = cone_for_slot(a, P, a.n_diffuse + 1, cam);
+        MarchResult m = march<DT>(a, T, c);
+        o1.w = m.a;
+        ksum += m.k;
+    }
+}
+
+// XCD-aware tile order: hardware dispatches workgroup i to XCD i % 8; give each
+// XCD a contiguous run of tiles so neighbouring tiles share an L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nt) {
+    int q = nt >> 3, r = nt & 7;
+    int xcd = bid & 7, k = bid >> 3;
+    return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
+
+// Pixel of thread `tid` in tile `tile`: 16x16 pixels per 256-thread workgroup,
+// each wave an 8x8 quadrant.
+__device__ __forceinline__ void tile_pixel(const TraceArgs& a, int tile, int tid, int& view, int& y, int& x) {
+    int tpv = a.tiles_x * a.tiles_y;
+    view = tile / tpv;
+    int r = tile - view * tpv;
+    int ty = r / a.tiles_x, tx = r - ty * a.tiles_x;
+    int wv = tid >> 6, lane = tid & 63;
+    x = tx * 16 + (wv & 1) * 8 + (lane & 7);
+    y = ty * 16 + (wv >> 1) * 8 + (lane >> 3);
+}
+
+}  // namespace vct

@@ -1,0 +1,178 @@
+// Mip pyramid build and level unpack (texture filtering of Section 4.3.3:
+// each level is the 2x2x2 mean of the level below; mipmaps are generated after
+// voxelization, Sections 4.5 and 5.4.4).
+//
+// One workgroup owns a B^3 block of float32 source texels (B = min(16, side)),
+// stages it in LDS, writes it as the first level of the pass (when that level
+// is not yet stored), and reduces it in LDS down to 1 texel, storing every
+// level on the way in the pyramid's storage type.  The coarsest value of each
+// block also goes to a float32 staging buffer that the next pass reads, so
+// every level is computed from float32 parents and rounded exactly once.
+// 256^3 needs two passes (levels 0-4, 4-8), 512^3 and 1024^3 three.
+#include "texel.h"
+#include "vct_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxB = 16;
+
+struct MipPass {
+    const float4* src;       // float32 logical [ns][ns][ns]
+    int32_t ns;              // source side
+    int32_t B;               // block side
+    int32_t nlev;            // levels produced after the first (<= log2 B)
+    int32_t first;           // pyramid level of the source
+    int32_t write_first;     // store the source level too
+    int32_t nblk;            // blocks a side = ns / B
+    float4* stage;           // float32 output of the coarsest level of this pass (or null)
+    void* pyr;
+    int32_t lv_nb[VCT_MAX_LEVELS];
+    uint32_t lv_off[VCT_MAX_LEVELS];
+};
+
+template <int DT>
+__device__ __forceinline__ void put(const MipPass& p, int level, int x, int y, int z, float4 v) {
+    // level is warp-uniform; unrolled select keeps the kernel-argument arrays in SGPRs
+    int nb = 1;
+    uint32_t off = 0;
+#pragma unroll
+    for (int l = 0; l < VCT_MAX_LEVELS; ++l)
+        if (l == level) {
+            nb = p.lv_nb[l];
+            off = p.lv_off[l];
+        }
+    vct_store_texel<DT>(p.pyr, off + vct_brick_index(x, y, z, nb), v);
+}
+
+template <int DT>
+__global__ __launch_bounds__(kThreads) void k_mip_block(MipPass p) {
+    __shared__ float4 bufA[kMaxB * kMaxB * kMaxB];
+    __shared__ float4 bufB[(kMaxB / 2) * (kMaxB / 2) * (kMaxB / 2)];
+    const int B = p.B;
+    const int bid = blockIdx.x;
+    const int bx = bid % p.nblk;
+    const int by = (bid / p.nblk) % p.nblk;
+    const int bz = bid / (p.nblk * p.nblk);
+    const int cnt = B * B * B;
+    for (int t = threadIdx.x; t < cnt; t += kThreads) {
+        int x = t % B, y = (t / B) % B, z = t / (B * B);
+        int gx = bx * B + x, gy = by * B + y, gz = bz * B + z;
+        float4 v = p.src[((size_t)gz * p.ns + gy) * p.ns + gx];
+        bufA[t] = v;
+        if (p.write_first) put<DT>(p, p.first, gx, gy, gz, v);
+    }
+    __syncthreads();
+    float4* cur = bufA;
+    float4* nxt = bufB;
+    int m = B;
+    for (int j = 1; j <= p.nlev; ++j) {
+        const int pm = m;
+        m >>= 1;
+        const int c = m * m * m;
+        for (int t = threadIdx.x; t < c; t += kThreads) {
+            int x = t % m, y = (t / m) % m, z = t / (m * m);
+            float4 ch[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                int dz = q >> 2, dy = (q >> 1) & 1, dx = q & 1;
+                ch[q] = cur[((2 * z + dz) * pm + (2 * y + dy)) * pm + (2 * x + dx)];
+            }
+            float4 s;
+            s.x = ((ch[0].x + ch[1].x) + (ch[2].x + ch[3].x)) + ((ch[4].x + ch[5].x) + (ch[6].x + ch[7].x));
+            s.y = ((ch[0].y + ch[1].y) + (ch[2].y + ch[3].y)) + ((ch[4].y + ch[5].y) + (ch[6].y + ch[7].y));
+            s.z = ((ch[0].z + ch[1].z) + (ch[2].z + ch[3].z)) + ((ch[4].z + ch[5].z) + (ch[6].z + ch[7].z));
+            s.w = ((ch[0].w + ch[1].w) + (ch[2].w + ch[3].w)) + ((ch[4].w + ch[5].w) + (ch[6].w + ch[7].w));
+            s.x *= 0.125f;
+            s.y *= 0.125f;
+            s.z *= 0.125f;
+            s.w *= 0.125f;
+            nxt[t] = s;
+            int gx = bx * m + x, gy = by * m + y, gz = bz * m + z;
+            put<DT>(p, p.first + j, gx, gy, gz, s);
+            if (j == p.nlev && p.stage) {
+                int side = p.nblk * m;
+                p.stage[((size_t)gz * side + gy) * side + gx] = s;
+            }
+        }
+        __syncthreads();
+        float4* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_unpack(const void* __restrict__ pyr, int nl, int nb, uint32_t off,
+                                                float4* __restrict__ out) {
+    const uint32_t total = (uint32_t)nl * nl * nl;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+        int x = t % nl, y = (t / nl) % nl, z = t / (nl * nl);
+        out[t] = vct_load_texel<DT>(pyr, off + vct_brick_index(x, y, z, nb));
+    }
+}
+
+template <int DT>
+hipError_t run_build(const PyrLayout& L, const float* base, void* pyr, hipStream_t s) {
+    MipPass p{};
+    p.pyr = pyr;
+    for (int l = 0; l < L.levels; ++l) {
+        p.lv_nb[l] = L.nb[l];
+        p.lv_off[l] = (uint32_t)L.off[l];
+    }
+    char* pb = static_cast<char*>(pyr);
+    float4* stage[2] = {reinterpret_cast<float4*>(pb + L.stage_off_bytes[0]),
+                        reinterpret_cast<float4*>(pb + L.stage_off_bytes[1])};
+    const float4* src = reinterpret_cast<const float4*>(base);
+    int ns = L.n, first = 0, write_first = 1, si = 0;
+    for (;;) {
+        int B = ns < kMaxB ? ns : kMaxB;
+        int lb = vct_log2i(B);
+        int nlev = lb < (L.levels - 1 - first) ? lb : (L.levels - 1 - first);
+        bool last = (first + nlev == L.levels - 1);
+        p.src = src;
+        p.ns = ns;
+        p.B = B;
+        p.nlev = nlev;
+        p.first = first;
+        p.write_first = write_first;
+        p.nblk = ns / B;
+        p.stage = last ? nullptr : stage[si];
+        int nblocks = p.nblk * p.nblk * p.nblk;
+        hipLaunchKernelGGL(k_mip_block<DT>, dim3(nblocks), dim3(kThreads), 0, s, p);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (last) break;
+        src = stage[si];
+        ns >>= nlev;
+        first += nlev;
+        write_first = 0;
+        si ^= 1;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t vct_launch_build_mips(const PyrLayout& L, const float* base, void* pyr, hipStream_t s) {
+    switch (L.dtype) {
+        case VCT_F32: return run_build<VCT_F32>(L, base, pyr, s);
+        case VCT_F16: return run_build<VCT_F16>(L, base, pyr, s);
+        default: return run_build<VCT_BF16>(L, base, pyr, s);
+    }
+}
+
+hipError_t vct_launch_unpack(const PyrLayout& L, const void* pyr, int level, float* out, hipStream_t s) {
+    int nl = L.n >> level;
+    uint32_t total = (uint32_t)nl * nl * nl;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    float4* o = reinterpret_cast<float4*>(out);
+    uint32_t off = (uint32_t)L.off[level];
+    switch (L.dtype) {
+        case VCT_F32: hipLaunchKernelGGL(k_unpack<VCT_F32>, dim3(blocks), dim3(256), 0, s, pyr, nl, L.nb[level], off, o); break;
+        case VCT_F16: hipLaunchKernelGGL(k_unpack<VCT_F16>, dim3(blocks), dim3(256), 0, s, pyr, nl, L.nb[level], off, o); break;
+        default: hipLaunchKernelGGL(k_unpack<VCT_BF16>, dim3(blocks), dim3(256), 0, s, pyr, nl, L.nb[level], off, o); break;
+    }
+    return hipGetLastError();
+}

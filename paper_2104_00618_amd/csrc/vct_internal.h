@@ -1,0 +1,126 @@
+// Internal layout, argument blocks and device helpers of libvct (gfx950).
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "vct.h"
+
+#define VCT_MAX_LEVELS 11   // N <= 1024
+#define VCT_BRICK 4          // bricks of 4^3 texels
+#define VCT_BRICK_TEXELS 64
+
+// ---------------------------------------------------------------------------
+// Pyramid layout.  Level l (N_l = N >> l texels a side) is stored as
+// nb_l^3 bricks, nb_l = ceil(N_l / 4), brick (bz, by, bx) at linear index
+// (bz * nb_l + by) * nb_l + bx, texels inside a brick at (z&3)*16 + (y&3)*4 + (x&3).
+// A 2x2x2 trilinear footprint therefore touches at most 8 bricks and usually
+// one, and a brick of float16 texels is 512 contiguous bytes.
+// After the last level comes a float32 staging area of two buffers of
+// (N/16)^3 texels used by the multi-pass mip build.
+// ---------------------------------------------------------------------------
+struct PyrLayout {
+    int32_t n, levels, dtype, texel_bytes;
+    int32_t nb[VCT_MAX_LEVELS];        // bricks per axis of each level
+    int64_t off[VCT_MAX_LEVELS];       // texel offset of each level
+    int64_t total_texels;              // all levels
+    int64_t stage_off_bytes[2];        // byte offsets of the two staging buffers
+    int64_t stage_texels;              // capacity of each staging buffer (float4 texels)
+    int64_t bytes;                     // whole buffer
+};
+
+static inline int vct_log2i(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+static inline PyrLayout vct_make_layout(int n, int levels, int dtype) {
+    PyrLayout p{};
+    p.n = n;
+    p.levels = levels;
+    p.dtype = dtype;
+    p.texel_bytes = dtype == VCT_F32 ? 16 : 8;
+    int64_t off = 0;
+    for (int l = 0; l < levels; ++l) {
+        int nl = n >> l;
+        int nb = (nl + VCT_BRICK - 1) / VCT_BRICK;
+        p.nb[l] = nb;
+        p.off[l] = off;
+        int64_t tex = (int64_t)nb * nb * nb * VCT_BRICK_TEXELS;
+        off += tex;
+        // keep every level 256-byte aligned (a brick is >= 512 bytes, so this holds already)
+    }
+    p.total_texels = off;
+    int64_t bytes = off * p.texel_bytes;
+    bytes = (bytes + 255) & ~int64_t(255);
+    int64_t ns = n / 16 > 0 ? n / 16 : 1;
+    p.stage_texels = ns * ns * ns;
+    p.stage_off_bytes[0] = bytes;
+    bytes += ((p.stage_texels * 16 + 255) & ~int64_t(255));
+    p.stage_off_bytes[1] = bytes;
+    bytes += ((p.stage_texels * 16 + 255) & ~int64_t(255));
+    p.bytes = bytes;
+    return p;
+}
+
+// Texel index inside a level (brick layout above).
+__host__ __device__ static inline uint32_t vct_brick_index(int x, int y, int z, int nb) {
+    return (uint32_t)((((z >> 2) * nb + (y >> 2)) * nb + (x >> 2)) << 6) +
+           (uint32_t)(((z & 3) << 4) | ((y & 3) << 2) | (x & 3));
+}
+
+// ---------------------------------------------------------------------------
+// Kernel argument blocks (passed by value).
+// ---------------------------------------------------------------------------
+struct LevelInfo {
+    int32_t n;        // texels a side
+    int32_t nb;       // bricks a side
+    uint32_t off;     // texel offset of the level in the pyramid (< 2^31 for N <= 1024)
+    int32_t pad;
+};
+
+struct TraceArgs {
+    // grid
+    int32_t n, levels;
+    float origin[3];
+    float scale_hi, scale_lo;      // N / extent as a double-float
+    float voxel;                   // extent / N (world size of a base texel)
+    LevelInfo lv[VCT_MAX_LEVELS];
+    const void* pyr;
+    // G-buffer
+    int32_t b, h, w;
+    int32_t tiles_x, tiles_y, n_tiles;   // 16x16-pixel tiles
+    const float4* pos_rough;
+    const float4* normal;
+    const float* cam_pos;
+    // cone set
+    int32_t n_diffuse, enable_spec, enable_occ;
+    float dir[VCT_MAX_DIFFUSE][3];
+    float weight[VCT_MAX_DIFFUSE];
+    float diffuse_aperture, spec_aperture_scale, occ_aperture;
+    float light_tex[3][2];         // light position in texel units, double-float per axis
+    float step_factor, t0, normal_offset, max_dist, alpha_thresh;
+    int32_t max_steps;             // hard bound on samples per cone
+};
+
+// Launch helpers implemented in the .hip files.
+hipError_t vct_launch_build_mips(const PyrLayout& L, const float* base, void* pyr, hipStream_t s);
+hipError_t vct_launch_unpack(const PyrLayout& L, const void* pyr, int level, float* out, hipStream_t s);
+hipError_t vct_launch_trace(const TraceArgs& a, int dtype, float* out, unsigned long long* count,
+                            hipStream_t s);
+
+struct BackwardPlan {
+    int64_t n_lanes;          // pixels * cones
+    int64_t acc_off, acc_bytes;       // int64 x4 accumulator over the pyramid texels
+    int64_t state_off, state_bytes;   // per-lane forward state
+    int64_t part_off, part_bytes;     // per-block bound partial sums
+    int64_t ctl_off, ctl_bytes;       // scale exponent and flags
+    int64_t n_blocks;
+    int64_t bytes;
+};
+
+BackwardPlan vct_plan_backward(const PyrLayout& L, const TraceArgs& a);
+hipError_t vct_launch_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPlan& P,
+                               const float* grad_out, float* grad_base, void* ws, hipStream_t s);

@@ -1,0 +1,220 @@
+"""Host-side tests of the C ABI: the library loads, exports every declared
+entry point, its structs match the header, sizes follow the documented layout,
+and invalid arguments are rejected before anything is enqueued.  No kernel is
+launched (empty G-buffers or invalid arguments only)."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+import paper_2104_00618_amd as vct
+from paper_2104_00618_amd import binding as B
+from scenes import cone_set, ConeParams
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vct.h")
+
+EINVAL, EWORKSPACE = -1, -2
+
+
+def _header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(vct_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_entry_points():
+    fns = _header_functions()
+    for f in ("vct_build_mips", "vct_trace", "vct_trace_backward", "vct_pyramid_bytes",
+              "vct_backward_workspace_bytes", "vct_unpack_level", "vct_count_samples", "vct_last_error"):
+        assert f in fns
+
+
+def test_library_exports_every_declared_symbol():
+    lib = vct.lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\sT\s(vct_\w+)", out))
+    for f in _header_functions():
+        assert f in exported, f
+        assert hasattr(lib, f)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "vct.h"
+int main(void) {
+  printf("%zu %zu %zu\n", sizeof(vct_grid), offsetof(vct_grid, origin), offsetof(vct_grid, extent));
+  printf("%zu %zu %zu %zu\n", sizeof(vct_gbuffer), offsetof(vct_gbuffer, pos_rough),
+         offsetof(vct_gbuffer, normal), offsetof(vct_gbuffer, cam_pos));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(vct_cone_params), offsetof(vct_cone_params, diffuse_weight),
+         offsetof(vct_cone_params, enable_spec), offsetof(vct_cone_params, light_pos),
+         offsetof(vct_cone_params, step_factor), offsetof(vct_cone_params, alpha_thresh));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    r = subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", f"-I{ROOT}/include", "-I/opt/rocm/include",
+                        str(src), "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = [list(map(int, l.split())) for l in subprocess.run([str(exe)], capture_output=True,
+                                                                 text=True).stdout.splitlines()]
+    C = ctypes
+    assert got[0] == [C.sizeof(B.CGrid), B.CGrid.origin.offset, B.CGrid.extent.offset]
+    assert got[1] == [C.sizeof(B.CGBuffer), B.CGBuffer.pos_rough.offset, B.CGBuffer.normal.offset,
+                      B.CGBuffer.cam_pos.offset]
+    P = B.CConeParams
+    assert got[2] == [C.sizeof(P), P.diffuse_weight.offset, P.enable_spec.offset, P.light_pos.offset,
+                      P.step_factor.offset, P.alpha_thresh.offset]
+
+
+def _layout_bytes(n, levels, texel):
+    total = 0
+    for l in range(levels):
+        nb = max(((n >> l) + 3) // 4, 1)
+        total += nb ** 3 * 64
+    b = (total * texel + 255) // 256 * 256
+    ns = max(n // 16, 1)
+    stage = (ns ** 3 * 16 + 255) // 256 * 256
+    return b + 2 * stage
+
+
+@pytest.mark.parametrize("n,dtype", [(1, "f32"), (2, "f16"), (8, "bf16"), (64, "f32"), (256, "f16"), (1024, "f16")])
+def test_pyramid_bytes_follow_the_layout(n, dtype):
+    g = vct.Grid(n, dtype=dtype)
+    assert vct.pyramid_bytes(g) == _layout_bytes(n, g.levels, 16 if dtype == "f32" else 8)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    ({"n": 0}, "power of two"), ({"n": 48}, "power of two"), ({"n": 2048}, "power of two"),
+    ({"n": 64, "levels": 8}, "levels"), ({"n": 64, "levels": 0}, "levels"),
+    ({"n": 64, "dtype": 7}, "dtype"), ({"n": 64, "extent": 0.0}, "extent"),
+    ({"n": 64, "extent": float("nan")}, "extent"), ({"n": 64, "origin": (0, float("inf"), 0)}, "origin"),
+])
+def test_invalid_grids_are_rejected(kw, msg):
+    g = vct.Grid(**kw)
+    n = ctypes.c_size_t()
+    rc = vct.lib().vct_pyramid_bytes(ctypes.byref(g.c()), ctypes.byref(n))
+    assert rc == EINVAL
+    err = vct.lib().vct_last_error().decode()
+    assert err.startswith("vct_pyramid_bytes:") and msg in err
+
+
+def _params(**kw):
+    d, w = cone_set("six")
+    return ConeParams(d, w, **kw)
+
+
+def _empty_gbuf():
+    g = B.CGBuffer()
+    g.b = g.h = g.w = 0
+    return g
+
+
+@pytest.mark.parametrize("kw,msg", [
+    ({"step_factor": 0.0}, "step_factor"), ({"step_factor": -1.0}, "step_factor"),
+    ({"max_dist": 0.0}, "max_dist"), ({"alpha_thresh": 0.0}, "alpha_thresh"),
+    ({"t0": -0.1}, "t0"), ({"diffuse_aperture": float("nan")}, "diffuse_aperture"),
+    ({"occ_aperture": -1.0}, "occ_aperture"), ({"light_pos": (0.0, float("nan"), 0.0)}, "light_pos"),
+    ({"max_dist": 1e6}, "samples per cone"), ({"normal_offset": float("inf")}, "normal_offset"),
+])
+def test_invalid_params_are_rejected_before_launch(kw, msg):
+    g = vct.Grid(64).c()
+    gb = _empty_gbuf()
+    p = B.cone_params(_params(**kw))
+    rc = vct.lib().vct_trace(ctypes.byref(g), None, ctypes.byref(gb), ctypes.byref(p), None, None)
+    assert rc == EINVAL
+    assert msg in vct.lib().vct_last_error().decode()
+
+
+def test_too_many_diffuse_cones_and_zero_direction():
+    g = vct.Grid(64).c()
+    gb = _empty_gbuf()
+    p = B.cone_params(_params())
+    p.n_diffuse = 17
+    rc = vct.lib().vct_trace(ctypes.byref(g), None, ctypes.byref(gb), ctypes.byref(p), None, None)
+    assert rc == EINVAL and "n_diffuse" in vct.lib().vct_last_error().decode()
+    p = B.cone_params(_params())
+    p.diffuse_dir[2][0] = p.diffuse_dir[2][1] = p.diffuse_dir[2][2] = 0.0
+    rc = vct.lib().vct_trace(ctypes.byref(g), None, ctypes.byref(gb), ctypes.byref(p), None, None)
+    assert rc == EINVAL and "zero vector" in vct.lib().vct_last_error().decode()
+
+
+def test_gbuffer_shape_and_null_pointers_are_rejected():
+    g = vct.Grid(64).c()
+    p = B.cone_params(_params())
+    gb = B.CGBuffer()
+    gb.b, gb.h, gb.w = 1, 4, 4            # pixels but null pointers
+    rc = vct.lib().vct_trace(ctypes.byref(g), None, ctypes.byref(gb), ctypes.byref(p), None, None)
+    assert rc == EINVAL and "non-null" in vct.lib().vct_last_error().decode()
+    gb.b, gb.h, gb.w = 1, -1, 4
+    rc = vct.lib().vct_trace(ctypes.byref(g), None, ctypes.byref(gb), ctypes.byref(p), None, None)
+    assert rc == EINVAL and "negative" in vct.lib().vct_last_error().decode()
+
+
+def test_null_outputs_are_rejected():
+    g = vct.Grid(64).c()
+    p = B.cone_params(_params())
+    gb = _empty_gbuf()
+    rc = vct.lib().vct_trace(ctypes.byref(g), ctypes.c_void_p(0), ctypes.byref(gb), ctypes.byref(p), None, None)
+    assert rc == EINVAL
+    rc = vct.lib().vct_count_samples(ctypes.byref(g), None, ctypes.byref(gb), ctypes.byref(p), None, None)
+    assert rc == EINVAL and "count" in vct.lib().vct_last_error().decode()
+    rc = vct.lib().vct_build_mips(ctypes.byref(g), None, None, 0, None)
+    assert rc == EINVAL and "non-null" in vct.lib().vct_last_error().decode()
+
+
+def test_backward_rejects_alpha_thresh_above_one():
+    g = vct.Grid(16).c()
+    gb = _empty_gbuf()
+    p = B.cone_params(_params(alpha_thresh=1.5))
+    rc = vct.lib().vct_trace_backward(ctypes.byref(g), None, ctypes.byref(gb), ctypes.byref(p), None, None, None,
+                                      0, None)
+    assert rc == EINVAL and "alpha_thresh" in vct.lib().vct_last_error().decode()
+
+
+def test_workspace_size_query_and_last_error_cleared_on_success():
+    g = vct.Grid(16).c()
+    gb = _empty_gbuf()
+    p = B.cone_params(_params(alpha_thresh=0.99))
+    n = ctypes.c_size_t()
+    assert vct.lib().vct_backward_workspace_bytes(ctypes.byref(g), ctypes.byref(gb), ctypes.byref(p),
+                                                  ctypes.byref(n)) == 0
+    assert n.value >= (16 ** 3 + 8 ** 3 + 4 ** 3 + 64 + 64) * 32
+    assert vct.lib().vct_last_error().decode() == ""
+
+
+@pytest.mark.skipif(os.environ.get("VCT_HOST_ONLY_DUMMY_PTRS") is None and
+                    __import__("torch").cuda.is_available(),
+                    reason="uses dummy device pointers; run on hosts without a GPU only")
+def test_undersized_buffers_give_eworkspace():
+    fake = ctypes.c_void_p(0x1000)
+    g = vct.Grid(16).c()
+    rc = vct.lib().vct_build_mips(ctypes.byref(g), fake, fake, 100, None)
+    assert rc == EWORKSPACE and "needs" in vct.lib().vct_last_error().decode()
+    gb = _empty_gbuf()
+    p = B.cone_params(_params(alpha_thresh=0.99))
+    rc = vct.lib().vct_trace_backward(ctypes.byref(g), fake, ctypes.byref(gb), ctypes.byref(p), None, fake, fake,
+                                      16, None)
+    assert rc == EWORKSPACE and "workspace" in vct.lib().vct_last_error().decode()
+
+
+def test_last_error_is_thread_local():
+    import threading
+    g = vct.Grid(48).c()
+    n = ctypes.c_size_t()
+    vct.lib().vct_pyramid_bytes(ctypes.byref(g), ctypes.byref(n))
+    seen = []
+
+    def other():
+        seen.append(vct.lib().vct_last_error().decode())
+
+    th = threading.Thread(target=other)
+    th.start()
+    th.join()
+    assert seen == [""]
+    assert "power of two" in vct.lib().vct_last_error().decode()
