@@ -81,19 +81,146 @@ __global__ __launch_bounds__(kThreads) void k_bwd_scale(const float* __restrict_
     }
 }
 
+// Lane j holds, after xpose_sum32, the sum of value index xpose_index(j)
+// (lanes j and j^1 hold the same sum).
+__device__ __forceinline__ int xpose_index(int lane) {
+    return ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 +
+           ((lane >> 1) & 1);
+}
+
+// Sum of v[0..31] over the lanes with `in` set: a transposing butterfly
+// (xor 32, 16, 8, 4, 2 halving the values each lane carries, then xor 1), 32
+// shuffles in all; the addition order is fixed, so the sum is reproducible.
+__device__ __forceinline__ float xpose_sum32(const float v[32], bool in, int lane) {
+    float r[16];
+    {
+        const bool up = (lane & 32) != 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            float keep = in ? (up ? v[16 + i] : v[i]) : 0.f;
+            float send = in ? (up ? v[i] : v[16 + i]) : 0.f;
+            r[i] = keep + __shfl_xor(send, 32);
+        }
+    }
+#pragma unroll
+    for (int s = 1; s < 5; ++s) {
+        const int m = 32 >> s, half = 16 >> s;
+        const bool up = (lane & m) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            float keep = up ? r[half + i] : r[i];
+            float send = up ? r[i] : r[half + i];
+            r[i] = keep + __shfl_xor(send, m);
+        }
+    }
+    return r[0] + __shfl_xor(r[0], 1);
+}
+
+// Emit one level's tap gradients of the wave.  Lanes whose samples share the
+// same (level, base texel) have the same 8 taps; each such group is summed
+// across the wave (fixed order) and 32 lanes then add its 8 taps x 4 channels
+// as fixed-point integers: to the workgroup's LDS table for the coarse levels
+// (side <= 8), to the global accumulator otherwise.
+__device__ __forceinline__ void emit_level(bool live, int level, const Taps& tp, float wl, const float g[4], int E,
+                                           unsigned long long* __restrict__ acc, unsigned long long* small,
+                                           uint32_t small_off, int lane) {
+    float w[8];
+    folded_weights(tp, wl, w);
+    float v[32];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) v[q * 4 + ch] = w[q] * g[ch];
+    // The 8 taps are fixed by the base texel together with which axes clamp
+    // (a clamped axis repeats the base texel instead of stepping to i0 + 1).
+    const uint32_t key = live ? tp.idx[0] : 0xffffffffu;
+    const int kcl = tp.clamp;
+    unsigned long long mask = __ballot(live);
+    const int j = xpose_index(lane), tq = j >> 2, ch = j & 3;
+    while (mask) {
+        const int leader = __builtin_ctzll(mask);
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
+        const int kc = __builtin_amdgcn_readlane(kcl, leader);
+        const bool in = live && key == k && kcl == kc;
+        const unsigned long long gm = __ballot(in);
+        const float sum = xpose_sum32(v, in, lane);
+        const int lev = __builtin_amdgcn_readlane(level, leader);
+        uint32_t idx = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            uint32_t iq = (uint32_t)__builtin_amdgcn_readlane((int)tp.idx[q], leader);
+            idx = tq == q ? iq : idx;
+        }
+        if (!(lane & 1)) {
+            const long long qv = fixed_point(sum, E - 3 * lev);
+            if (qv) {
+                VCT_CHECK_ACC(idx);
+                if (idx >= small_off)
+                    atomicAdd(&small[(idx - small_off) * 4 + ch], (unsigned long long)qv);
+                else
+                    atomicAdd(&acc[(size_t)idx * 4 + ch], (unsigned long long)qv);
+            }
+        }
+        mask &= ~gm;
+    }
+}
+
+constexpr int kSmallMax = 704;   // texels of all levels with side <= 8 (8^3 + 3 bricks of 64)
+
 template <int DT>
 __global__ __launch_bounds__(kThreads) void k_bwd_pass2(TraceArgs a, const float4* __restrict__ gout,
                                                         const LaneState* __restrict__ state,
                                                         const int* __restrict__ ctl,
-                                                        unsigned long long* __restrict__ acc) {
+                                                        unsigned long long* __restrict__ acc, uint32_t small_off,
+                                                        int small_n) {
     __shared__ LevelTable T;
+    __shared__ unsigned long long s_small[kSmallMax * 4];
     load_level_table(a, &T);
+    for (int i = threadIdx.x; i < small_n * 4; i += kThreads) s_small[i] = 0ull;
     __syncthreads();
     const int E = ctl[0];
+    const int lane = threadIdx.x & 63;
     const int tile = xcd_tile(blockIdx.x, a.n_tiles);
     int view, y, x;
     tile_pixel(a, tile, threadIdx.x, view, y, x);
-    if (x < a.w && y < a.h) pass2_pixel<DT>(a, T, gout, state, E, acc, view, ((size_t)view * a.h + y) * a.w + x);
+    const bool inb = x < a.w && y < a.h;
+    const size_t pix = ((size_t)view * a.h + y) * a.w + x;
+    bool valid = false;
+    PixelSetup P;
+    float3 cam = make_float3(0.f, 0.f, 0.f);
+    float4 g0 = make_float4(0.f, 0.f, 0.f, 0.f), g1 = g0;
+    if (inb) {
+        float4 nr = a.normal[pix];
+        valid = nr.w != 0.0f;
+        if (valid) {
+            P = pixel_setup(a, a.pos_rough[pix], nr);
+            cam = make_float3(a.cam_pos[3 * view], a.cam_pos[3 * view + 1], a.cam_pos[3 * view + 2]);
+            g0 = gout[2 * pix];
+            g1 = gout[2 * pix + 1];
+        }
+    }
+    const int nslots = a.n_diffuse + 2;
+    for (int slot = 0; slot < nslots; ++slot) {
+        if (!slot_enabled(a, slot)) continue;
+        Pass2Lane L;
+        L.K = 0;
+        if (valid) pass2_init(a, P, cam, g0, g1, state[pix * nslots + slot], slot, L);
+        int Kw = L.K;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) Kw = max(Kw, __shfl_xor(Kw, o));
+        for (int k = 0; k < Kw; ++k) {
+            const bool live = k < L.K;
+            Pass2Step st = {};
+            if (live) pass2_step<DT>(a, T, L, k, st);
+            emit_level(live, st.l0, st.tp0, 1.0f - st.f, st.g, E, acc, s_small, small_off, lane);
+            emit_level(live && st.f > 0.0f, st.l1, st.tp1, st.f, st.g, E, acc, s_small, small_off, lane);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < small_n * 4; i += kThreads) {
+        const unsigned long long v = s_small[i];
+        if (v) atomicAdd(&acc[(size_t)small_off * 4 + i], v);
+    }
 }
 
 __global__ void k_fill_zero(uint4* __restrict__ p, size_t n) {
@@ -158,8 +285,19 @@ hipError_t run_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPl
         hipLaunchKernelGGL(k_bwd_pass1<DT>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, part);
     }
     hipLaunchKernelGGL(k_bwd_scale, dim3(1), dim3(kThreads), 0, s, part, (int)P.n_blocks, ctl);
+    // coarse levels (side <= 8) accumulate per workgroup in LDS first
+    int ls = L.levels;
+    for (int l = 0; l < L.levels; ++l)
+        if ((L.n >> l) <= 8) {
+            ls = l;
+            break;
+        }
+    const uint32_t small_off = (uint32_t)(ls < L.levels ? L.off[ls] : L.total_texels);
+    const int small_n = (int)(L.total_texels - small_off);
+    if (small_n > kSmallMax) return hipErrorInvalidValue;
     if (a.n_tiles > 0) {
-        hipLaunchKernelGGL(k_bwd_pass2<DT>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, ctl, acc);
+        hipLaunchKernelGGL(k_bwd_pass2<DT>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, ctl, acc, small_off,
+                           small_n);
     }
     AdjArgs m{};
     m.n = L.n;

@@ -134,100 +134,106 @@ __device__ __forceinline__ float pass1_pixel(const TraceArgs& a, const LevelTabl
     return bound;
 }
 
-// Add round(v * 2^e) to a 64-bit fixed-point accumulator for each channel.
-__device__ __forceinline__ void emit(unsigned long long* __restrict__ acc, uint32_t idx, float wt, const float g[4],
-                                     int e) {
-    VCT_CHECK_ACC(idx);
-    unsigned long long* p = acc + (size_t)idx * 4;
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) {
-        float v = ldexpf(wt * g[ch], e);
-        long long q = (long long)rintf(v);
-        if (q) atomicAdd(p + ch, (unsigned long long)q);
-    }
+// Pass-2 state of one cone of one lane.
+struct Pass2Lane {
+    Cone c;
+    df C[3];
+    df CK[3];
+    df t;
+    float A, TK;
+    float gc[3], ga;
+    int K;
+};
+
+// Set up the re-march of cone `slot`; K = 0 when the cone receives no gradient.
+__device__ __forceinline__ void pass2_init(const TraceArgs& a, const PixelSetup& P, float3 cam, float4 g0, float4 g1,
+                                           const LaneState& S, int slot, Pass2Lane& L) {
+    slot_grads(a, slot, g0, g1, L.gc, L.ga);
+    const bool zero = L.gc[0] == 0.f && L.gc[1] == 0.f && L.gc[2] == 0.f && L.ga == 0.f;
+    L.K = zero ? 0 : min(max(__float_as_int(S.lo.w), 0), a.max_steps);
+    L.CK[0] = {S.hi.x, S.lo.x};
+    L.CK[1] = {S.hi.y, S.lo.y};
+    L.CK[2] = {S.hi.z, S.lo.z};
+    L.TK = 1.0f - S.hi.w;
+    L.c = cone_for_slot(a, P, slot, cam);
+    for (int i = 0; i < 3; ++i) L.C[i] = {0.f, 0.f};
+    L.A = 0.f;
+    L.t = {a.t0, 0.0f};
 }
 
-// Pass 2 for one pixel: re-march every cone with a nonzero output gradient
-// and scatter the fixed-point tap contributions.
+// Sample k of a pass-2 cone: its taps on one or two levels and the gradient
+// g = (dL/dc_k, dL/da_k) of the sample; advances the march.
+struct Pass2Step {
+    Taps tp0, tp1;
+    int l0, l1;
+    float f;          // weight of level l1 (0: single level)
+    float g[4];
+};
+
 template <int DT>
-__device__ __forceinline__ void pass2_pixel(const TraceArgs& a, const LevelTable& T, const float4* __restrict__ gout,
-                                            const LaneState* __restrict__ state, int E,
-                                            unsigned long long* __restrict__ acc, int view, size_t pix) {
-    float4 nr = a.normal[pix];
-    if (nr.w == 0.0f) return;
-    const int nslots = a.n_diffuse + 2;
-    float4 pr = a.pos_rough[pix];
-    float4 g0 = gout[2 * pix], g1 = gout[2 * pix + 1];
-    PixelSetup P = pixel_setup(a, pr, nr);
-    float3 cam = make_float3(a.cam_pos[3 * view], a.cam_pos[3 * view + 1], a.cam_pos[3 * view + 2]);
-    const LaneState* st = state + pix * nslots;
-    for (int slot = 0; slot < nslots; ++slot) {
-        if (!slot_enabled(a, slot)) continue;
-        float gc[3], ga;
-        slot_grads(a, slot, g0, g1, gc, ga);
-        if (gc[0] == 0.f && gc[1] == 0.f && gc[2] == 0.f && ga == 0.f) continue;
-        LaneState S = st[slot];
-        const int K = min(max(__float_as_int(S.lo.w), 0), a.max_steps);
-        const df CK[3] = {{S.hi.x, S.lo.x}, {S.hi.y, S.lo.y}, {S.hi.z, S.lo.z}};
-        const float TK = 1.0f - S.hi.w;
-        Cone c = cone_for_slot(a, P, slot, cam);
-        df C[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
-        float A = 0.f;
-        df t = {a.t0, 0.0f};
-        for (int k = 0; k < K; ++k) {
-            float d = fmaxf(c.two_tan * t.hi, a.voxel);
-            float lam = lod_of(a, d);
-            df Ux = df_axis(c.Ox, t, c.Wx);
-            df Uy = df_axis(c.Oy, t, c.Wy);
-            df Uz = df_axis(c.Oz, t, c.Wz);
-            int l0 = (int)lam;
-            float f = lam - (float)l0;
-            int l1 = min(l0 + 1, a.levels - 1);
-            Taps tp0, tp1;
-            level_taps(T, l0, Ux, Uy, Uz, tp0);
-            float4 s = gather<DT>(a.pyr, tp0);
-            if (f > 0.0f) {
-                level_taps(T, l1, Ux, Uy, Uz, tp1);
-                float4 s1 = gather<DT>(a.pyr, tp1);
-                float gg = 1.0f - f;
-                s.x = __builtin_fmaf(f, s1.x, gg * s.x);
-                s.y = __builtin_fmaf(f, s1.y, gg * s.y);
-                s.z = __builtin_fmaf(f, s1.z, gg * s.z);
-                s.w = __builtin_fmaf(f, s1.w, gg * s.w);
-            }
-            const float tr = 1.0f - A;
-            acc_colour(C[0], tr, s.x);
-            acc_colour(C[1], tr, s.y);
-            acc_colour(C[2], tr, s.z);
-            A = __builtin_fmaf(tr, s.w, A);
-            float g[4];
-            g[0] = tr * gc[0];
-            g[1] = tr * gc[1];
-            g[2] = tr * gc[2];
-            if (k == K - 1) {
-                g[3] = tr * ga;
-            } else {
-                const float tn = 1.0f - A;
-                float dot = 0.f;
+__device__ __forceinline__ void pass2_step(const TraceArgs& a, const LevelTable& T, Pass2Lane& L, int k,
+                                           Pass2Step& st) {
+    const float d = fmaxf(L.c.two_tan * L.t.hi, a.voxel);
+    const float lam = lod_of(a, d);
+    df Ux = df_axis(L.c.Ox, L.t, L.c.Wx);
+    df Uy = df_axis(L.c.Oy, L.t, L.c.Wy);
+    df Uz = df_axis(L.c.Oz, L.t, L.c.Wz);
+    st.l0 = (int)lam;
+    st.f = lam - (float)st.l0;
+    st.l1 = min(st.l0 + 1, a.levels - 1);
+    level_taps(T, st.l0, Ux, Uy, Uz, st.tp0);
+    float4 s = gather<DT>(a.pyr, st.tp0);
+    if (st.f > 0.0f) {
+        level_taps(T, st.l1, Ux, Uy, Uz, st.tp1);
+        float4 s1 = gather<DT>(a.pyr, st.tp1);
+        float gg = 1.0f - st.f;
+        s.x = __builtin_fmaf(st.f, s1.x, gg * s.x);
+        s.y = __builtin_fmaf(st.f, s1.y, gg * s.y);
+        s.z = __builtin_fmaf(st.f, s1.z, gg * s.z);
+        s.w = __builtin_fmaf(st.f, s1.w, gg * s.w);
+    }
+    const float tr = 1.0f - L.A;
+    acc_colour(L.C[0], tr, s.x);
+    acc_colour(L.C[1], tr, s.y);
+    acc_colour(L.C[2], tr, s.z);
+    L.A = __builtin_fmaf(tr, s.w, L.A);
+    st.g[0] = tr * L.gc[0];
+    st.g[1] = tr * L.gc[1];
+    st.g[2] = tr * L.gc[2];
+    if (k == L.K - 1) {
+        st.g[3] = tr * L.ga;
+    } else {
+        const float tn = 1.0f - L.A;
+        float dot = 0.f;
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    float diff = (CK[ch].hi - C[ch].hi) + (CK[ch].lo - C[ch].lo);
-                    dot = __builtin_fmaf(gc[ch], diff, dot);
+        for (int ch = 0; ch < 3; ++ch) {
+            float diff = (L.CK[ch].hi - L.C[ch].hi) + (L.CK[ch].lo - L.C[ch].lo);
+            dot = __builtin_fmaf(L.gc[ch], diff, dot);
+        }
+        st.g[3] = -tr * (dot - L.ga * L.TK) / tn;
+    }
+    L.t = df_add(L.t, a.step_factor * d);
+}
+
+// Tap weights of one level scaled by the level weight, with the taps of a
+// clamped axis (both on the same texel) folded into the first one.
+__device__ __forceinline__ void folded_weights(const Taps& tp, float wl, float w[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) w[q] = wl * tp.w[q];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if (tp.clamp & (1 << ax)) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q & (1 << ax)) {
+                    w[q - (1 << ax)] += w[q];
+                    w[q] = 0.f;
                 }
-                g[3] = -tr * (dot - ga * TK) / tn;
-            }
-            const int e0 = E - 3 * l0;
-            const float w0 = 1.0f - f;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) emit(acc, tp0.idx[q], w0 * tp0.w[q], g, e0);
-            if (f > 0.0f) {
-                const int e1 = E - 3 * l1;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) emit(acc, tp1.idx[q], f * tp1.w[q], g, e1);
-            }
-            t = df_add(t, a.step_factor * d);
         }
     }
 }
+
+// round(v * 2^e) as a 64-bit integer.
+__device__ __forceinline__ long long fixed_point(float v, int e) { return (long long)rintf(ldexpf(v, e)); }
 
 }  // namespace vct

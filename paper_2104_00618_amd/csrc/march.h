@@ -122,6 +122,7 @@ __device__ __forceinline__ Axis axis_taps(df U, float sc, int nl) {
 struct Taps {
     uint32_t idx[8];
     float w[8];
+    int clamp;   // bit a set: both taps of axis a (x, y, z) fell on the same texel
 };
 
 // The 8 taps and trilinear weights of level l at texel-space position U (level-0 texels).
@@ -134,6 +135,7 @@ __device__ __forceinline__ void level_taps(const LevelTable& T, int l, df Ux, df
     Axis ay = axis_taps(Uy, sc, nl);
     Axis az = axis_taps(Uz, sc, nl);
     const float wx0 = 1.0f - ax.w1, wy0 = 1.0f - ay.w1, wz0 = 1.0f - az.w1;
+    tp.clamp = (ax.i0 == ax.i1 ? 1 : 0) | (ay.i0 == ay.i1 ? 2 : 0) | (az.i0 == az.i1 ? 4 : 0);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         int dz = q >> 2, dy = (q >> 1) & 1, dx = q & 1;
