@@ -81,39 +81,64 @@ __global__ __launch_bounds__(kThreads) void k_bwd_scale(const float* __restrict_
     }
 }
 
-// Lane j holds, after xpose_sum32, the sum of value index xpose_index(j)
-// (lanes j and j^1 hold the same sum).
-__device__ __forceinline__ int xpose_index(int lane) {
-    return ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 +
-           ((lane >> 1) & 1);
+// Cross-lane moves of the reduction butterfly.  Each pairs lane i with
+// i ^ mask: row_mirror (^15) and row_half_mirror (^7) and quad permutes (^2,
+// ^1) are DPP modifiers of ordinary VALU instructions; ^16 is a ds_swizzle in
+// bitmask mode and ^32 a single bpermute.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+constexpr int kDppXor15 = 0x140;   // row_mirror
+constexpr int kDppXor7 = 0x141;    // row_half_mirror
+constexpr int kDppXor2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int kDppXor1 = 0xB1;     // quad_perm [1,0,3,2]
+__device__ __forceinline__ float swz_xor16(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
 }
 
-// Sum of v[0..31] over the lanes with `in` set: a transposing butterfly
-// (xor 32, 16, 8, 4, 2 halving the values each lane carries, then xor 1), 32
-// shuffles in all; the addition order is fixed, so the sum is reproducible.
-__device__ __forceinline__ float xpose_sum32(const float v[32], bool in, int lane) {
+// After xpose_sum32, lanes 0..31 hold the sums of value index
+// xpose_index(lane) (lanes j and j + 32 hold the same sum).
+__device__ __forceinline__ int xpose_index(int lane) {
+    return ((lane >> 3) & 1) * 16 + ((lane >> 2) & 1) * 8 + ((lane >> 1) & 1) * 4 + (lane & 1) * 2 +
+           ((lane >> 4) & 1);
+}
+
+// Butterfly step: pair lanes by `mask`; the lane whose `up` bit is set keeps
+// the upper half of its values, its partner the lower half.
+template <int N, typename X>
+__device__ __forceinline__ void halve(float* r, bool up, X xmove) {
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) {
+        float keep = up ? r[N / 2 + i] : r[i];
+        float send = up ? r[i] : r[N / 2 + i];
+        r[i] = keep + xmove(send);
+    }
+}
+
+// Sum over the lanes with `in` set of the 32 values w[q] * g[ch] (index
+// 4q + ch), transposed across the wave: 16 + 8 + 4 + 2 DPP moves, one swizzle
+// and one bpermute.  The masks 15, 7, 2, 1, 16, 32 each flip only bits not
+// yet used to split the values, so partners always hold the same indices;
+// the addition order is fixed, so the sums are reproducible.
+__device__ __forceinline__ float xpose_sum32(const float w[8], const float g[4], bool in, int lane) {
     float r[16];
     {
-        const bool up = (lane & 32) != 0;
+        const bool up = (lane & 8) != 0;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            float keep = in ? (up ? v[16 + i] : v[i]) : 0.f;
-            float send = in ? (up ? v[i] : v[16 + i]) : 0.f;
-            r[i] = keep + __shfl_xor(send, 32);
+            const float lo = w[i >> 2] * g[i & 3];
+            const float hi = w[(16 + i) >> 2] * g[i & 3];
+            float keep = in ? (up ? hi : lo) : 0.f;
+            float send = in ? (up ? lo : hi) : 0.f;
+            r[i] = keep + dpp<kDppXor15>(send);
         }
     }
-#pragma unroll
-    for (int s = 1; s < 5; ++s) {
-        const int m = 32 >> s, half = 16 >> s;
-        const bool up = (lane & m) != 0;
-#pragma unroll
-        for (int i = 0; i < half; ++i) {
-            float keep = up ? r[half + i] : r[i];
-            float send = up ? r[i] : r[half + i];
-            r[i] = keep + __shfl_xor(send, m);
-        }
-    }
-    return r[0] + __shfl_xor(r[0], 1);
+    halve<16>(r, (lane & 4) != 0, [](float v) { return dpp<kDppXor7>(v); });
+    halve<8>(r, (lane & 2) != 0, [](float v) { return dpp<kDppXor2>(v); });
+    halve<4>(r, (lane & 1) != 0, [](float v) { return dpp<kDppXor1>(v); });
+    halve<2>(r, (lane & 16) != 0, [](float v) { return swz_xor16(v); });
+    return r[0] + __shfl_xor(r[0], 32);
 }
 
 // Emit one level's tap gradients of the wave.  Lanes whose samples share the
@@ -126,11 +151,6 @@ __device__ __forceinline__ void emit_level(bool live, int level, const Taps& tp,
                                            uint32_t small_off, int lane) {
     float w[8];
     folded_weights(tp, wl, w);
-    float v[32];
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) v[q * 4 + ch] = w[q] * g[ch];
     // The 8 taps are fixed by the base texel together with which axes clamp
     // (a clamped axis repeats the base texel instead of stepping to i0 + 1).
     const uint32_t key = live ? tp.idx[0] : 0xffffffffu;
@@ -143,7 +163,7 @@ __device__ __forceinline__ void emit_level(bool live, int level, const Taps& tp,
         const int kc = __builtin_amdgcn_readlane(kcl, leader);
         const bool in = live && key == k && kcl == kc;
         const unsigned long long gm = __ballot(in);
-        const float sum = xpose_sum32(v, in, lane);
+        const float sum = xpose_sum32(w, g, in, lane);
         const int lev = __builtin_amdgcn_readlane(level, leader);
         uint32_t idx = 0;
 #pragma unroll
@@ -151,7 +171,7 @@ __device__ __forceinline__ void emit_level(bool live, int level, const Taps& tp,
             uint32_t iq = (uint32_t)__builtin_amdgcn_readlane((int)tp.idx[q], leader);
             idx = tq == q ? iq : idx;
         }
-        if (!(lane & 1)) {
+        if (lane < 32) {
             const long long qv = fixed_point(sum, E - 3 * lev);
             if (qv) {
                 VCT_CHECK_ACC(idx);
