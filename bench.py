@@ -25,6 +25,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("cone samples/s + ms/frame at 1080p (fwd, fwd+bwd), % HBM peak, FP16 vs FP32 storage")
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed-FP32 instructions (the library is built with
+# them disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Algorithmic FP32 operations per cone sample (FMA = 2), counted from the
+# formulas: forward sample 220 (schedule 8, position 6, per level 91 x 2 =
+# coordinates 6 + floor/frac 6 + 1-phi 3 + weights 12 + 8 taps x 4 channels FMA
+# 64, level blend 13, compositing 9, t update 2); the scatter pass re-does the
+# sample (220), forms the sample gradient (22) and the 16 taps x 4 channels
+# weighted contributions and their accumulation (128): 370.
+FLOPS_FWD_SAMPLE = 220
+FLOPS_BWD_SCATTER_SAMPLE = 370
+BWD_KERNELS = ["clear accumulator", "pass 1 (recompute)", "scale", "pass 2 (re-march + scatter)", "mip adjoint"]
 WORKLOAD = "c1"
 WORKLOAD_DESC = ("procedural Cornell box 256^3 (9 levels, 4-8 boxes and spheres), 1 view 1920x1080, "
                  "5 diffuse cones (front + 4 at 45 deg, 60 deg aperture) + specular + occlusion, "
@@ -92,7 +104,16 @@ def main():
     npix = int(np.prod(w.shape))
     log(f"{samples} cone samples per frame ({samples / npix:.1f} per pixel), workspace {ws.numel() / 2**30:.2f} GiB")
 
-    def step(ev=None):
+    # a plain copy of known size (256 MiB read + 256 MiB written): its
+    # FETCH_SIZE / WRITE_SIZE counters calibrate the byte counters of the
+    # profiled kernels
+    cal_src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    cal_dst = torch.empty_like(cal_src)
+    cal_dst.copy_(cal_src)
+    torch.cuda.synchronize()
+    del cal_src, cal_dst
+
+    def step(ev=None, kev=None):
         if ev is not None:
             ev[0].record()
         vct.build_mips(base, grid, pyr)
@@ -101,6 +122,8 @@ def main():
         vct.trace(pyr, grid, pr, nr, cam, w.params, out)
         if ev is not None:
             ev[2].record()
+        if kev is not None:
+            kev.arm()
         vct.trace_backward(pyr, grid, pr, nr, cam, w.params, gout, ws, gbase)
         if ev is not None:
             ev[3].record()
@@ -109,28 +132,35 @@ def main():
         step()
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    kevs = [vct.KernelEvents(len(BWD_KERNELS) + 1) for _ in range(args.steps)]
     log(f"timing {args.steps} steps")
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
-        step(evs[i])
+        step(evs[i], kevs[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     mips_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     fwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    bwd_k = np.mean([k.times() for k in kevs], axis=0)
     ms_step = wall * 1e3 / args.steps
-    log(f"step {ms_step:.3f} ms: mips {mips_ms:.3f}, trace {fwd_ms:.3f}, backward {bwd_ms:.3f}")
+    log(f"step {ms_step:.3f} ms: mips {mips_ms:.3f}, trace {fwd_ms:.3f}, backward {bwd_ms:.3f} "
+        f"({', '.join(f'{n} {t:.3f}' for n, t in zip(BWD_KERNELS, bwd_k))})")
 
     texel_bytes = 16 if args.dtype == "f32" else 8
     trace_bytes = samples * 16 * texel_bytes + npix * 64
-    achieved = trace_bytes / (fwd_ms * 1e-3) / 1e9
+    trace_gbs = trace_bytes / (fwd_ms * 1e-3) / 1e9
     breakdown = {
         "build_mips_ms": mips_ms, "trace_ms": fwd_ms, "trace_backward_ms": bwd_ms,
+        "trace_backward_kernels_ms": {n: float(t) for n, t in zip(BWD_KERNELS, bwd_k)},
         "fwd_ms_per_frame": mips_ms + fwd_ms, "fwd_bwd_ms_per_frame": mips_ms + fwd_ms + bwd_ms,
         "samples_per_frame": samples, "samples_per_pixel": samples / npix,
         "fwd_samples_per_s": samples / ((mips_ms + fwd_ms) * 1e-3),
         "trace_kernel_samples_per_s": samples / (fwd_ms * 1e-3),
+        "trace_kernel": {"logical_tap_GBps": trace_gbs, "frac_of_hbm_peak": trace_gbs / HBM_PEAK_GBS,
+                         "alu_TFLOPs": FLOPS_FWD_SAMPLE * samples / (fwd_ms * 1e-3) / 1e12,
+                         "frac_of_alu_peak": FLOPS_FWD_SAMPLE * samples / (fwd_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS},
     }
 
     if not args.no_compare and args.dtype == "f32":
@@ -157,6 +187,14 @@ def main():
             "trace_logical_GBps": (s16 * 128 + npix * 64) / (f16 * 1e-3) / 1e9}
         log(f"f16 storage: mips {m16:.3f} ms, trace {f16:.3f} ms ({fwd_ms / f16:.2f}x vs f32)")
 
+    # dominant kernel of the step: the backward scatter pass (issue-bound VALU work)
+    p2_ms = float(bwd_k[3])
+    p2_tflops = FLOPS_BWD_SCATTER_SAMPLE * samples / (p2_ms * 1e-3) / 1e12
+    roofline = {"kernel": "k_bwd_pass2 (re-march + deterministic tap-gradient scatter), one launch per step",
+                "bound": "alu", "achieved": p2_tflops, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": p2_tflops / ALU_PEAK_TFLOPS, "traffic": None, "launch_ms": p2_ms,
+                "flops_per_launch": FLOPS_BWD_SCATTER_SAMPLE * samples,
+                "flops_model": f"{FLOPS_BWD_SCATTER_SAMPLE} FP32 ops per cone sample x {samples} samples"}
     res = {
         "metric": METRIC,
         "value": samples / (ms_step * 1e-3),
@@ -168,12 +206,7 @@ def main():
                    "height": w.shape[1], "width": w.shape[2], "cones_per_pixel": w.params.n_diffuse + 2,
                    "step": "build_mips + trace + trace_backward"},
         "breakdown": breakdown,
-        "roofline": {"kernel": "k_trace (forward cone march, one launch per step)", "bound": "hbm",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None,
-                     "bytes_per_launch": trace_bytes,
-                     "bytes_model": f"{16 * texel_bytes} B per cone sample (16 texel reads) + 64 B per pixel "
-                                    f"(G-buffer read, output write)"},
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         log("timing the oracle on a pixel sample")

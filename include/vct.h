@@ -166,6 +166,17 @@ int vct_trace_backward(const vct_grid* grid, const void* pyramid, const vct_gbuf
                        const vct_cone_params* params, const float* grad_out, float* grad_base,
                        void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Diagnostics: per-kernel timing.  Registers `count` events (a host array of
+ * hipEvent_t created by the caller) for the NEXT enqueuing call on this thread
+ * (vct_build_mips, vct_trace, vct_count_samples or vct_trace_backward).  That
+ * call records events[i] on its stream just before its i-th kernel and, after
+ * its last kernel, records the next unused event; events beyond its kernel
+ * count are left untouched.  Kernel order of vct_trace_backward: clear
+ * accumulator, pass 1 (recompute), scale, pass 2 (re-march and scatter), mip
+ * adjoint.  The registration is consumed by that call (also if it fails).
+ * count = 0 clears it.  Recording costs one hipEventRecord per kernel. */
+int vct_record_kernel_events(hipEvent_t* events, int32_t count);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* vct_last_error(void);
 

@@ -74,10 +74,64 @@ def lib():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_int
+    L.vct_record_kernel_events.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.vct_record_kernel_events.restype = ctypes.c_int
     L.vct_last_error.argtypes = []
     L.vct_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
+
+
+_hip = None
+
+
+def _hiprt():
+    global _hip
+    if _hip is None:
+        h = ctypes.CDLL("libamdhip64.so")
+        h.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        h.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        h.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        h.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        _hip = h
+    return _hip
+
+
+class KernelEvents:
+    """Per-kernel timing of the next library call on this thread
+    (vct_record_kernel_events): arm() before the call, times() afterwards
+    gives the duration of each of its first n - 1 kernels in ms."""
+
+    def __init__(self, n):
+        h = _hiprt()
+        self.n = n
+        self.ev = (ctypes.c_void_p * n)()
+        for i in range(n):
+            e = ctypes.c_void_p()
+            if h.hipEventCreate(ctypes.byref(e)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.ev[i] = e.value
+
+    def arm(self):
+        _check(lib().vct_record_kernel_events(ctypes.cast(self.ev, ctypes.c_void_p), self.n))
+
+    def times(self):
+        h = _hiprt()
+        h.hipEventSynchronize(self.ev[self.n - 1])
+        out = []
+        for i in range(self.n - 1):
+            ms = ctypes.c_float()
+            if h.hipEventElapsedTime(ctypes.byref(ms), self.ev[i], self.ev[i + 1]) != 0:
+                raise RuntimeError("hipEventElapsedTime failed")
+            out.append(ms.value)
+        return out
+
+    def __del__(self):
+        try:
+            for i in range(self.n):
+                _hiprt().hipEventDestroy(self.ev[i])
+        except Exception:
+            pass
 
 
 def _check(rc):

@@ -15,6 +15,18 @@
 namespace {
 
 thread_local std::string g_err;
+thread_local hipEvent_t* g_events = nullptr;
+thread_local int g_n_events = 0;
+
+// The event registration (diagnostics) applies to one enqueuing call only.
+EventSink take_events() {
+    EventSink es;
+    es.ev = g_events;
+    es.n = g_n_events;
+    g_events = nullptr;
+    g_n_events = 0;
+    return es;
+}
 
 int fail(int code, const char* fn, const char* fmt, ...) {
     char buf[512];
@@ -175,13 +187,14 @@ int vct_pyramid_bytes(const vct_grid* grid, size_t* bytes) {
 int vct_build_mips(const vct_grid* grid, const float* base, void* pyramid, size_t pyramid_bytes,
                    hipStream_t stream) {
     const char* fn = "vct_build_mips";
+    EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
     if (!base || !pyramid) return fail(VCT_EINVAL, fn, "base and pyramid must be non-null");
     PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
     if (pyramid_bytes < (size_t)L.bytes)
         return fail(VCT_EWORKSPACE, fn, "pyramid buffer has %zu bytes, needs %lld", pyramid_bytes,
                     (long long)L.bytes);
-    hipError_t e = vct_launch_build_mips(L, base, pyramid, stream);
+    hipError_t e = vct_launch_build_mips(L, base, pyramid, stream, es);
     if (e != hipSuccess) return device_error(fn, e);
     ok();
     return VCT_OK;
@@ -203,6 +216,7 @@ int vct_unpack_level(const vct_grid* grid, const void* pyramid, int32_t level, f
 static int trace_common(const char* fn, const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
                         const vct_cone_params* params, float* out, unsigned long long* count, bool counting,
                         hipStream_t stream) {
+    EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
     if (int r = check_params(fn, grid, params)) return r;
@@ -216,7 +230,7 @@ static int trace_common(const char* fn, const vct_grid* grid, const void* pyrami
         ok();
         return VCT_OK;
     }
-    hipError_t e = vct_launch_trace(a, grid->dtype, out, count, stream);
+    hipError_t e = vct_launch_trace(a, grid->dtype, out, count, stream, es);
     if (e != hipSuccess) return device_error(fn, e);
     ok();
     return VCT_OK;
@@ -250,6 +264,7 @@ int vct_trace_backward(const vct_grid* grid, const void* pyramid, const vct_gbuf
                        const vct_cone_params* params, const float* grad_out, float* grad_base, void* workspace,
                        size_t workspace_bytes, hipStream_t stream) {
     const char* fn = "vct_trace_backward";
+    EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
     if (int r = check_params(fn, grid, params)) return r;
@@ -265,8 +280,18 @@ int vct_trace_backward(const vct_grid* grid, const void* pyramid, const vct_gbuf
     BackwardPlan P = vct_plan_backward(L, a);
     if (workspace_bytes < (size_t)P.bytes)
         return fail(VCT_EWORKSPACE, fn, "workspace has %zu bytes, needs %lld", workspace_bytes, (long long)P.bytes);
-    hipError_t e = vct_launch_backward(L, a, P, grad_out, grad_base, workspace, stream);
+    hipError_t e = vct_launch_backward(L, a, P, grad_out, grad_base, workspace, stream, es);
     if (e != hipSuccess) return device_error(fn, e);
+    ok();
+    return VCT_OK;
+}
+
+int vct_record_kernel_events(hipEvent_t* events, int32_t count) {
+    const char* fn = "vct_record_kernel_events";
+    if (count < 0 || count > 64) return fail(VCT_EINVAL, fn, "count = %d must be in [0, 64]", count);
+    if (count > 0 && !events) return fail(VCT_EINVAL, fn, "events is null");
+    g_events = count > 0 ? events : nullptr;
+    g_n_events = count;
     ok();
     return VCT_OK;
 }

@@ -124,15 +124,21 @@ __device__ __forceinline__ void halve(float* r, bool up, X xmove) {
 __device__ __forceinline__ float xpose_sum32(const float w[8], const float g[4], bool in, int lane) {
     float r[16];
     {
+        // First split is on the tap's z bit (value index bit 4): a lane with
+        // lane bit 3 set keeps taps 4..7, so it swaps tap q with q + 4 up front
+        // instead of selecting among the 32 products.
         const bool up = (lane & 8) != 0;
+        float wk[4], ws[4];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const float lo = w[i >> 2] * g[i & 3];
-            const float hi = w[(16 + i) >> 2] * g[i & 3];
-            float keep = in ? (up ? hi : lo) : 0.f;
-            float send = in ? (up ? lo : hi) : 0.f;
-            r[i] = keep + dpp<kDppXor15>(send);
+        for (int q = 0; q < 4; ++q) {
+            const float a = in ? w[q] : 0.f, b = in ? w[q + 4] : 0.f;
+            wk[q] = up ? b : a;
+            ws[q] = up ? a : b;
         }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) r[i] = ws[i >> 2] * g[i & 3];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) r[i] = __builtin_fmaf(wk[i >> 2], g[i & 3], dpp<kDppXor15>(r[i]));
     }
     halve<16>(r, (lane & 4) != 0, [](float v) { return dpp<kDppXor7>(v); });
     halve<8>(r, (lane & 2) != 0, [](float v) { return dpp<kDppXor2>(v); });
@@ -171,16 +177,10 @@ __device__ __forceinline__ void emit_level(bool live, int level, const Taps& tp,
             uint32_t iq = (uint32_t)__builtin_amdgcn_readlane((int)tp.idx[q], leader);
             idx = tq == q ? iq : idx;
         }
-        if (lane < 32) {
-            const long long qv = fixed_point(sum, E - 3 * lev);
-            if (qv) {
-                VCT_CHECK_ACC(idx);
-                if (idx >= small_off)
-                    atomicAdd(&small[(idx - small_off) * 4 + ch], (unsigned long long)qv);
-                else
-                    atomicAdd(&acc[(size_t)idx * 4 + ch], (unsigned long long)qv);
-            }
-        }
+        const long long qv = lane < 32 ? fixed_point(sum, E - 3 * lev) : 0;
+        VCT_CHECK_ACC(idx);
+        if (qv != 0 && idx >= small_off) atomicAdd(&small[(idx - small_off) * 4 + ch], (unsigned long long)qv);
+        if (qv != 0 && idx < small_off) atomicAdd(&acc[(size_t)idx * 4 + ch], (unsigned long long)qv);
         mask &= ~gm;
     }
 }
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void k_mip_adjoint(AdjArgs m, const long long*
 
 template <int DT>
 hipError_t run_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPlan& P, const float* grad_out,
-                        float* grad_base, void* ws, hipStream_t s) {
+                        float* grad_base, void* ws, hipStream_t s, EventSink& es) {
     char* w = static_cast<char*>(ws);
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(w + P.acc_off);
     LaneState* state = reinterpret_cast<LaneState*>(w + P.state_off);
@@ -299,11 +299,14 @@ hipError_t run_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPl
     size_t n16 = (size_t)P.acc_bytes / 16;
     int fb = (int)((n16 + 255) / 256);
     if (fb > 8192) fb = 8192;
+    es.mark(s);
     hipLaunchKernelGGL(k_fill_zero, dim3(fb), dim3(256), 0, s, reinterpret_cast<uint4*>(acc), n16);
     const float4* g4 = reinterpret_cast<const float4*>(grad_out);
+    es.mark(s);
     if (a.n_tiles > 0) {
         hipLaunchKernelGGL(k_bwd_pass1<DT>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, part);
     }
+    es.mark(s);
     hipLaunchKernelGGL(k_bwd_scale, dim3(1), dim3(kThreads), 0, s, part, (int)P.n_blocks, ctl);
     // coarse levels (side <= 8) accumulate per workgroup in LDS first
     int ls = L.levels;
@@ -315,6 +318,7 @@ hipError_t run_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPl
     const uint32_t small_off = (uint32_t)(ls < L.levels ? L.off[ls] : L.total_texels);
     const int small_n = (int)(L.total_texels - small_off);
     if (small_n > kSmallMax) return hipErrorInvalidValue;
+    es.mark(s);
     if (a.n_tiles > 0) {
         hipLaunchKernelGGL(k_bwd_pass2<DT>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, ctl, acc, small_off,
                            small_n);
@@ -329,8 +333,10 @@ hipError_t run_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPl
     uint32_t total = (uint32_t)L.n * L.n * L.n;
     int blocks = (int)((total + 255) / 256);
     if (blocks > 65536) blocks = 65536;
+    es.mark(s);
     hipLaunchKernelGGL(k_mip_adjoint, dim3(blocks), dim3(256), 0, s, m, reinterpret_cast<const long long*>(acc), ctl,
                        reinterpret_cast<float4*>(grad_base));
+    es.mark(s);
     return hipGetLastError();
 }
 
@@ -362,10 +368,10 @@ BackwardPlan vct_plan_backward(const PyrLayout& L, const TraceArgs& a) {
 }
 
 hipError_t vct_launch_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPlan& P, const float* grad_out,
-                               float* grad_base, void* ws, hipStream_t s) {
+                               float* grad_base, void* ws, hipStream_t s, EventSink& es) {
     switch (L.dtype) {
-        case VCT_F32: return run_backward<VCT_F32>(L, a, P, grad_out, grad_base, ws, s);
-        case VCT_F16: return run_backward<VCT_F16>(L, a, P, grad_out, grad_base, ws, s);
-        default: return run_backward<VCT_BF16>(L, a, P, grad_out, grad_base, ws, s);
+        case VCT_F32: return run_backward<VCT_F32>(L, a, P, grad_out, grad_base, ws, s, es);
+        case VCT_F16: return run_backward<VCT_F16>(L, a, P, grad_out, grad_base, ws, s, es);
+        default: return run_backward<VCT_BF16>(L, a, P, grad_out, grad_base, ws, s, es);
     }
 }

@@ -78,7 +78,7 @@ __device__ __forceinline__ float3 normalize3(float x, float y, float z) {
 // Shared-memory copy of the level table (per-lane levels index it).
 struct LevelTable {
     int32_t n[VCT_MAX_LEVELS];
-    int32_t nb[VCT_MAX_LEVELS];
+    int32_t lnb[VCT_MAX_LEVELS];     // log2 of bricks per axis
     uint32_t off[VCT_MAX_LEVELS];
 };
 
@@ -87,7 +87,7 @@ __device__ __forceinline__ void load_level_table(const TraceArgs& a, LevelTable*
     for (int l = 0; l < VCT_MAX_LEVELS; ++l)
         if ((int)threadIdx.x == l) {
             t->n[l] = a.lv[l].n;
-            t->nb[l] = a.lv[l].nb;
+            t->lnb[l] = 31 - __builtin_clz(a.lv[l].nb);
             t->off[l] = a.lv[l].off;
         }
 }
@@ -102,15 +102,10 @@ __device__ __forceinline__ Axis axis_taps(df U, float sc, int nl) {
     float u = U.hi * sc - 0.5f;          // exact: power-of-two scale, and u >= -1/4 whenever it matters
     float ulo = U.lo * sc;
     float fl = floorf(u);
-    float ph = (u - fl) + ulo;
-    int i = (int)fl;
-    if (ph < 0.0f) {
-        ph += 1.0f;
-        i -= 1;
-    } else if (ph >= 1.0f) {
-        ph -= 1.0f;
-        i += 1;
-    }
+    float ph = (u - fl) + ulo;           // in (-1, 2): renormalise without branches
+    float c = floorf(ph);
+    ph -= c;
+    int i = (int)fl + (int)c;
     i = min(max(i, -1), nl);             // keeps i + 1 from overflowing for far-away points
     Axis a;                              // clamp-to-edge: both taps inside [0, nl - 1]
     a.i0 = min(max(i, 0), nl - 1);
@@ -128,7 +123,7 @@ struct Taps {
 // The 8 taps and trilinear weights of level l at texel-space position U (level-0 texels).
 __device__ __forceinline__ void level_taps(const LevelTable& T, int l, df Ux, df Uy, df Uz, Taps& tp) {
     const int nl = T.n[l];
-    const int nb = T.nb[l];
+    const int lnb = T.lnb[l];
     const uint32_t off = T.off[l];
     const float sc = __int_as_float((127 - l) << 23);   // 2^-l
     Axis ax = axis_taps(Ux, sc, nl);
@@ -136,14 +131,18 @@ __device__ __forceinline__ void level_taps(const LevelTable& T, int l, df Ux, df
     Axis az = axis_taps(Uz, sc, nl);
     const float wx0 = 1.0f - ax.w1, wy0 = 1.0f - ay.w1, wz0 = 1.0f - az.w1;
     tp.clamp = (ax.i0 == ax.i1 ? 1 : 0) | (ay.i0 == ay.i1 ? 2 : 0) | (az.i0 == az.i1 ? 4 : 0);
+    // brick layout: ((bz * nb + by) * nb + bx) * 64 + (z & 3) * 16 + (y & 3) * 4 + (x & 3), nb = 2^lnb
+    const uint32_t cx[2] = {(uint32_t)(((ax.i0 >> 2) << 6) | (ax.i0 & 3)), (uint32_t)(((ax.i1 >> 2) << 6) | (ax.i1 & 3))};
+    const uint32_t cy[2] = {(uint32_t)(((ay.i0 >> 2) << (6 + lnb)) | ((ay.i0 & 3) << 2)),
+                            (uint32_t)(((ay.i1 >> 2) << (6 + lnb)) | ((ay.i1 & 3) << 2))};
+    const uint32_t cz[2] = {(uint32_t)(((az.i0 >> 2) << (6 + 2 * lnb)) | ((az.i0 & 3) << 4)),
+                            (uint32_t)(((az.i1 >> 2) << (6 + 2 * lnb)) | ((az.i1 & 3) << 4))};
+    const float wxy[4] = {wx0 * wy0, ax.w1 * wy0, wx0 * ay.w1, ax.w1 * ay.w1};
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         int dz = q >> 2, dy = (q >> 1) & 1, dx = q & 1;
-        int x = dx ? ax.i1 : ax.i0;
-        int y = dy ? ay.i1 : ay.i0;
-        int z = dz ? az.i1 : az.i0;
-        tp.idx[q] = off + vct_brick_index(x, y, z, nb);
-        tp.w[q] = (dx ? ax.w1 : wx0) * (dy ? ay.w1 : wy0) * (dz ? az.w1 : wz0);
+        tp.idx[q] = off + cx[dx] + cy[dy] + cz[dz];
+        tp.w[q] = wxy[q & 3] * (dz ? az.w1 : wz0);
     }
 }
 
@@ -162,8 +161,9 @@ __device__ __forceinline__ float4 gather(const void* __restrict__ pyr, const Tap
 }
 
 // LOD of a diameter d (world units): lambda = clamp(log2(d / voxel), 0, L - 1).
+// d >= voxel, so d / voxel >= 1 is never denormal and the hardware log2 applies directly.
 __device__ __forceinline__ float lod_of(const TraceArgs& a, float d) {
-    float lam = log2f(d * a.scale_hi);
+    float lam = __builtin_amdgcn_logf(d * a.scale_hi);
     return fminf(fmaxf(lam, 0.0f), (float)(a.levels - 1));
 }
 

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_unpack(const void* __restrict__ pyr, in
 }
 
 template <int DT>
-hipError_t run_build(const PyrLayout& L, const float* base, void* pyr, hipStream_t s) {
+hipError_t run_build(const PyrLayout& L, const float* base, void* pyr, hipStream_t s, EventSink& es) {
     MipPass p{};
     p.pyr = pyr;
     for (int l = 0; l < L.levels; ++l) {
@@ -139,10 +139,14 @@ hipError_t run_build(const PyrLayout& L, const float* base, void* pyr, hipStream
         p.nblk = ns / B;
         p.stage = last ? nullptr : stage[si];
         int nblocks = p.nblk * p.nblk * p.nblk;
+        es.mark(s);
         hipLaunchKernelGGL(k_mip_block<DT>, dim3(nblocks), dim3(kThreads), 0, s, p);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        if (last) break;
+        if (last) {
+            es.mark(s);
+            break;
+        }
         src = stage[si];
         ns >>= nlev;
         first += nlev;
@@ -154,11 +158,11 @@ hipError_t run_build(const PyrLayout& L, const float* base, void* pyr, hipStream
 
 }  // namespace
 
-hipError_t vct_launch_build_mips(const PyrLayout& L, const float* base, void* pyr, hipStream_t s) {
+hipError_t vct_launch_build_mips(const PyrLayout& L, const float* base, void* pyr, hipStream_t s, EventSink& es) {
     switch (L.dtype) {
-        case VCT_F32: return run_build<VCT_F32>(L, base, pyr, s);
-        case VCT_F16: return run_build<VCT_F16>(L, base, pyr, s);
-        default: return run_build<VCT_BF16>(L, base, pyr, s);
+        case VCT_F32: return run_build<VCT_F32>(L, base, pyr, s, es);
+        case VCT_F16: return run_build<VCT_F16>(L, base, pyr, s, es);
+        default: return run_build<VCT_BF16>(L, base, pyr, s, es);
     }
 }
 

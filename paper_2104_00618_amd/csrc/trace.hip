@@ -44,23 +44,30 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a, float4* __restrict__
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 
 template <int DT>
-hipError_t run_trace(const TraceArgs& a, float* out, unsigned long long* count, hipStream_t s) {
+hipError_t run_trace(const TraceArgs& a, float* out, unsigned long long* count, hipStream_t s, EventSink& es) {
     dim3 grid(a.n_tiles), block(256);
     if (count) {
+        es.mark(s);
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, count);
-        if (a.n_tiles > 0) hipLaunchKernelGGL((k_trace<DT, true>), grid, block, 0, s, a, nullptr, count);
+        if (a.n_tiles > 0) {
+            es.mark(s);
+            hipLaunchKernelGGL((k_trace<DT, true>), grid, block, 0, s, a, nullptr, count);
+        }
     } else if (a.n_tiles > 0) {
+        es.mark(s);
         hipLaunchKernelGGL((k_trace<DT, false>), grid, block, 0, s, a, reinterpret_cast<float4*>(out), nullptr);
     }
+    es.mark(s);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t vct_launch_trace(const TraceArgs& a, int dtype, float* out, unsigned long long* count, hipStream_t s) {
+hipError_t vct_launch_trace(const TraceArgs& a, int dtype, float* out, unsigned long long* count, hipStream_t s,
+                            EventSink& es) {
     switch (dtype) {
-        case VCT_F32: return run_trace<VCT_F32>(a, out, count, s);
-        case VCT_F16: return run_trace<VCT_F16>(a, out, count, s);
-        default: return run_trace<VCT_BF16>(a, out, count, s);
+        case VCT_F32: return run_trace<VCT_F32>(a, out, count, s, es);
+        case VCT_F16: return run_trace<VCT_F16>(a, out, count, s, es);
+        default: return run_trace<VCT_BF16>(a, out, count, s, es);
     }
 }

@@ -105,11 +105,21 @@ struct TraceArgs {
     int32_t max_steps;             // hard bound on samples per cone
 };
 
+// Optional per-kernel event recording (diagnostics): mark() records the next
+// registered event on the stream, before each kernel and after the last.
+struct EventSink {
+    hipEvent_t* ev = nullptr;
+    int n = 0, next = 0;
+    void mark(hipStream_t s) {
+        if (next < n) hipEventRecord(ev[next++], s);
+    }
+};
+
 // Launch helpers implemented in the .hip files.
-hipError_t vct_launch_build_mips(const PyrLayout& L, const float* base, void* pyr, hipStream_t s);
+hipError_t vct_launch_build_mips(const PyrLayout& L, const float* base, void* pyr, hipStream_t s, EventSink& es);
 hipError_t vct_launch_unpack(const PyrLayout& L, const void* pyr, int level, float* out, hipStream_t s);
 hipError_t vct_launch_trace(const TraceArgs& a, int dtype, float* out, unsigned long long* count,
-                            hipStream_t s);
+                            hipStream_t s, EventSink& es);
 
 struct BackwardPlan {
     int64_t n_lanes;          // pixels * cones
@@ -123,4 +133,4 @@ struct BackwardPlan {
 
 BackwardPlan vct_plan_backward(const PyrLayout& L, const TraceArgs& a);
 hipError_t vct_launch_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPlan& P,
-                               const float* grad_out, float* grad_base, void* ws, hipStream_t s);
+                               const float* grad_out, float* grad_base, void* ws, hipStream_t s, EventSink& es);

@@ -218,3 +218,12 @@ def test_last_error_is_thread_local():
     th.join()
     assert seen == [""]
     assert "power of two" in vct.lib().vct_last_error().decode()
+
+
+def test_kernel_event_registration_is_validated():
+    lib = vct.lib()
+    assert lib.vct_record_kernel_events(None, -1) == EINVAL
+    assert lib.vct_record_kernel_events(None, 65) == EINVAL
+    assert lib.vct_record_kernel_events(None, 3) == EINVAL
+    assert "events" in lib.vct_last_error().decode()
+    assert lib.vct_record_kernel_events(None, 0) == 0

@@ -135,3 +135,18 @@ def test_backward_full_launch_sparse_grad_out():
         assert not inf["ambiguous"].any(), "seeded pixel hit a termination tie"
         ref += oracle.trace_backward(mips, pr, nr, w.cam_pos[vv_:vv_ + 1], w.params, go)
     _compare(gpu, ref, "c3 128^3 8x512x512 sparse")
+
+
+def test_kernel_events_time_each_backward_kernel():
+    w, g, gout = _case_fd()
+    grid = vct.Grid(w.n)
+    pyr = vct.build_mips(dev(g), grid)
+    kev = vct.KernelEvents(6)
+    kev.arm()
+    gb = vct.trace_backward(pyr, grid, dev(w.pos_rough), dev(w.normal), dev(w.cam_pos), w.params, dev(gout))
+    t = kev.times()
+    torch.cuda.synchronize()
+    assert len(t) == 5 and all(x >= 0 for x in t)
+    # the registration is consumed: the next call records nothing and still works
+    gb2 = vct.trace_backward(pyr, grid, dev(w.pos_rough), dev(w.normal), dev(w.cam_pos), w.params, dev(gout))
+    assert torch.equal(gb, gb2)
