@@ -147,14 +147,37 @@ __device__ __forceinline__ float xpose_sum32(const float w[8], const float g[4],
     return r[0] + __shfl_xor(r[0], 32);
 }
 
+// Alpha-only variant (occlusion cones carry no colour gradient): the sum over
+// the lanes with `in` set of w[q] * ga for the 8 taps.  Lanes with bits 0, 4, 5
+// clear end with the sum of tap 4 b3 + 2 b2 + b1.
+__device__ __forceinline__ float xpose_sum8(const float w[8], float ga, bool in, int lane) {
+    float r[4];
+    {
+        const bool up = (lane & 8) != 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float a = in ? w[q] * ga : 0.f, b = in ? w[q + 4] * ga : 0.f;
+            r[q] = (up ? b : a) + dpp<kDppXor15>(up ? a : b);
+        }
+    }
+    halve<4>(r, (lane & 4) != 0, [](float v) { return dpp<kDppXor7>(v); });
+    halve<2>(r, (lane & 2) != 0, [](float v) { return dpp<kDppXor2>(v); });
+    float x = r[0] + dpp<kDppXor1>(r[0]);
+    x += swz_xor16(x);
+    return x + __shfl_xor(x, 32);
+}
+
 // Emit one level's tap gradients of the wave.  Lanes whose samples share the
 // same (level, base texel) have the same 8 taps; each such group is summed
 // across the wave (fixed order) and 32 lanes then add its 8 taps x 4 channels
 // as fixed-point integers: to the workgroup's LDS table for the coarse levels
 // (side <= 8), to the global accumulator otherwise.
-__device__ __forceinline__ void emit_level(bool live, int level, const Taps& tp, float wl, const float g[4], int E,
-                                           unsigned long long* __restrict__ acc, unsigned long long* small,
-                                           uint32_t small_off, int lane) {
+template <bool ALPHA_ONLY>
+__device__ __forceinline__ void emit_level(bool live, const LevelTable& T, int level, df Ux, df Uy, df Uz, float wl,
+                                           const float g[4], int E, unsigned long long* __restrict__ acc,
+                                           unsigned long long* small, uint32_t small_off, int lane) {
+    Taps tp;
+    level_taps(T, level, Ux, Uy, Uz, tp);
     float w[8];
     folded_weights(tp, wl, w);
     // The 8 taps are fixed by the base texel together with which axes clamp
@@ -162,14 +185,16 @@ __device__ __forceinline__ void emit_level(bool live, int level, const Taps& tp,
     const uint32_t key = live ? tp.idx[0] : 0xffffffffu;
     const int kcl = tp.clamp;
     unsigned long long mask = __ballot(live);
-    const int j = xpose_index(lane), tq = j >> 2, ch = j & 3;
+    const int j = ALPHA_ONLY ? (((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1)) : xpose_index(lane);
+    const int tq = ALPHA_ONLY ? j : (j >> 2), ch = ALPHA_ONLY ? 3 : (j & 3);
+    const bool emitter = ALPHA_ONLY ? ((lane & 0x31) == 0) : (lane < 32);
     while (mask) {
         const int leader = __builtin_ctzll(mask);
         const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
         const int kc = __builtin_amdgcn_readlane(kcl, leader);
         const bool in = live && key == k && kcl == kc;
         const unsigned long long gm = __ballot(in);
-        const float sum = xpose_sum32(w, g, in, lane);
+        const float sum = ALPHA_ONLY ? xpose_sum8(w, g[3], in, lane) : xpose_sum32(w, g, in, lane);
         const int lev = __builtin_amdgcn_readlane(level, leader);
         uint32_t idx = 0;
 #pragma unroll
@@ -177,7 +202,7 @@ __device__ __forceinline__ void emit_level(bool live, int level, const Taps& tp,
             uint32_t iq = (uint32_t)__builtin_amdgcn_readlane((int)tp.idx[q], leader);
             idx = tq == q ? iq : idx;
         }
-        const long long qv = lane < 32 ? fixed_point(sum, E - 3 * lev) : 0;
+        const long long qv = emitter ? fixed_point(sum, E - 3 * lev) : 0;
         VCT_CHECK_ACC(idx);
         if (qv != 0 && idx >= small_off) atomicAdd(&small[(idx - small_off) * 4 + ch], (unsigned long long)qv);
         if (qv != 0 && idx < small_off) atomicAdd(&acc[(size_t)idx * 4 + ch], (unsigned long long)qv);
@@ -188,7 +213,7 @@ __device__ __forceinline__ void emit_level(bool live, int level, const Taps& tp,
 constexpr int kSmallMax = 704;   // texels of all levels with side <= 8 (8^3 + 3 bricks of 64)
 
 template <int DT>
-__global__ __launch_bounds__(kThreads) void k_bwd_pass2(TraceArgs a, const float4* __restrict__ gout,
+__global__ __launch_bounds__(kThreads, 4) void k_bwd_pass2(TraceArgs a, const float4* __restrict__ gout,
                                                         const LaneState* __restrict__ state,
                                                         const int* __restrict__ ctl,
                                                         unsigned long long* __restrict__ acc, uint32_t small_off,
@@ -204,36 +229,37 @@ __global__ __launch_bounds__(kThreads) void k_bwd_pass2(TraceArgs a, const float
     int view, y, x;
     tile_pixel(a, tile, threadIdx.x, view, y, x);
     const bool inb = x < a.w && y < a.h;
-    const size_t pix = ((size_t)view * a.h + y) * a.w + x;
-    bool valid = false;
-    PixelSetup P;
-    float3 cam = make_float3(0.f, 0.f, 0.f);
-    float4 g0 = make_float4(0.f, 0.f, 0.f, 0.f), g1 = g0;
-    if (inb) {
-        float4 nr = a.normal[pix];
-        valid = nr.w != 0.0f;
-        if (valid) {
-            P = pixel_setup(a, a.pos_rough[pix], nr);
-            cam = make_float3(a.cam_pos[3 * view], a.cam_pos[3 * view + 1], a.cam_pos[3 * view + 2]);
-            g0 = gout[2 * pix];
-            g1 = gout[2 * pix + 1];
-        }
-    }
+    const size_t pix = inb ? ((size_t)view * a.h + y) * a.w + x : 0;
+    const bool valid = inb && a.normal[pix].w != 0.0f;
     const int nslots = a.n_diffuse + 2;
     for (int slot = 0; slot < nslots; ++slot) {
         if (!slot_enabled(a, slot)) continue;
         Pass2Lane L;
         L.K = 0;
-        if (valid) pass2_init(a, P, cam, g0, g1, state[pix * nslots + slot], slot, L);
+        if (valid) {
+            // pixel setup and dL/d(out) are reloaded per cone to keep registers free
+            const PixelSetup P = pixel_setup(a, a.pos_rough[pix], a.normal[pix]);
+            const float3 cam = make_float3(a.cam_pos[3 * view], a.cam_pos[3 * view + 1], a.cam_pos[3 * view + 2]);
+            pass2_init(a, P, cam, gout[2 * pix], gout[2 * pix + 1], state[pix * nslots + slot], slot, L);
+        }
         int Kw = L.K;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) Kw = max(Kw, __shfl_xor(Kw, o));
+        const bool occ = slot == a.n_diffuse + 1;
         for (int k = 0; k < Kw; ++k) {
             const bool live = k < L.K;
             Pass2Step st = {};
             if (live) pass2_step<DT>(a, T, L, k, st);
-            emit_level(live, st.l0, st.tp0, 1.0f - st.f, st.g, E, acc, s_small, small_off, lane);
-            emit_level(live && st.f > 0.0f, st.l1, st.tp1, st.f, st.g, E, acc, s_small, small_off, lane);
+            if (occ) {
+                emit_level<true>(live, T, st.l0, st.Ux, st.Uy, st.Uz, 1.0f - st.f, st.g, E, acc, s_small, small_off, lane);
+                emit_level<true>(live && st.f > 0.0f, T, st.l1, st.Ux, st.Uy, st.Uz, st.f, st.g, E, acc, s_small,
+                                 small_off, lane);
+            } else {
+                emit_level<false>(live, T, st.l0, st.Ux, st.Uy, st.Uz, 1.0f - st.f, st.g, E, acc, s_small, small_off,
+                                  lane);
+                emit_level<false>(live && st.f > 0.0f, T, st.l1, st.Ux, st.Uy, st.Uz, st.f, st.g, E, acc, s_small,
+                                  small_off, lane);
+            }
         }
     }
     __syncthreads();

@@ -164,7 +164,7 @@ __device__ __forceinline__ void pass2_init(const TraceArgs& a, const PixelSetup&
 // Sample k of a pass-2 cone: its taps on one or two levels and the gradient
 // g = (dL/dc_k, dL/da_k) of the sample; advances the march.
 struct Pass2Step {
-    Taps tp0, tp1;
+    df Ux, Uy, Uz;    // sample position, level-0 texel units
     int l0, l1;
     float f;          // weight of level l1 (0: single level)
     float g[4];
@@ -175,17 +175,18 @@ __device__ __forceinline__ void pass2_step(const TraceArgs& a, const LevelTable&
                                            Pass2Step& st) {
     const float d = fmaxf(L.c.two_tan * L.t.hi, a.voxel);
     const float lam = lod_of(a, d);
-    df Ux = df_axis(L.c.Ox, L.t, L.c.Wx);
-    df Uy = df_axis(L.c.Oy, L.t, L.c.Wy);
-    df Uz = df_axis(L.c.Oz, L.t, L.c.Wz);
+    st.Ux = df_axis(L.c.Ox, L.t, L.c.Wx);
+    st.Uy = df_axis(L.c.Oy, L.t, L.c.Wy);
+    st.Uz = df_axis(L.c.Oz, L.t, L.c.Wz);
     st.l0 = (int)lam;
     st.f = lam - (float)st.l0;
     st.l1 = min(st.l0 + 1, a.levels - 1);
-    level_taps(T, st.l0, Ux, Uy, Uz, st.tp0);
-    float4 s = gather<DT>(a.pyr, st.tp0);
+    Taps tp;
+    level_taps(T, st.l0, st.Ux, st.Uy, st.Uz, tp);
+    float4 s = gather<DT>(a.pyr, tp);
     if (st.f > 0.0f) {
-        level_taps(T, st.l1, Ux, Uy, Uz, st.tp1);
-        float4 s1 = gather<DT>(a.pyr, st.tp1);
+        level_taps(T, st.l1, st.Ux, st.Uy, st.Uz, tp);
+        float4 s1 = gather<DT>(a.pyr, tp);
         float gg = 1.0f - st.f;
         s.x = __builtin_fmaf(st.f, s1.x, gg * s.x);
         s.y = __builtin_fmaf(st.f, s1.y, gg * s.y);
