@@ -1,15 +1,17 @@
 """Benchmark of the voxel-cone-tracing hot path on one GPU.
 
-A step is one pass of the whole hot path over the 256^3 / 1920x1080 scene:
-vct_build_mips (float32 grid -> pyramid), vct_trace (5 diffuse + specular +
-occlusion cones per pixel) and vct_trace_backward (gradient into the float32
-base grid for a seeded dL/d(out)).  Inputs are resident in HBM before timing.
+A step is one pass of the whole hot path over the 256^3 / 1920x1080 scene, as
+a training step runs it: vct_build_mips (float32 grid -> pyramid),
+vct_trace_save (5 diffuse + specular + occlusion cones per pixel, keeping each
+cone's end state) and vct_trace_backward_saved (gradient into the float32 base
+grid for a seeded dL/d(out)).  Inputs are resident in HBM before timing.
 
     python bench.py [--steps K] [--warmup W] [--dtype f32|f16|bf16] [--no-cpu-baseline]
 
 Prints one JSON line.  value = forward cone samples per second of the whole
-fwd+bwd step; the breakdown also gives forward-only rates, the per-call
-times (HIP events on the stream the library launches on) and the
+fwd+bwd step; the breakdown also gives the forward-only (vct_trace) rate, the
+per-call and per-kernel times (HIP events on the stream the library launches
+on), the step through vct_trace + vct_trace_backward (no saved state) and the
 float16-storage forward for comparison.
 """
 import argparse
@@ -36,7 +38,7 @@ ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # weighted contributions and their accumulation (128): 370.
 FLOPS_FWD_SAMPLE = 220
 FLOPS_BWD_SCATTER_SAMPLE = 370
-BWD_KERNELS = ["clear accumulator", "pass 1 (recompute)", "scale", "pass 2 (re-march + scatter)", "mip adjoint"]
+BWD_KERNELS = ["clear accumulator", "bound from saved states", "scale", "pass 2 (re-march + scatter)", "mip adjoint"]
 WORKLOAD = "c1"
 WORKLOAD_DESC = ("procedural Cornell box 256^3 (9 levels, 4-8 boxes and spheres), 1 view 1920x1080, "
                  "5 diffuse cones (front + 4 at 45 deg, 60 deg aperture) + specular + occlusion, "
@@ -97,12 +99,17 @@ def main():
     grid = vct.Grid(w.n, dtype=args.dtype)
     pyr = torch.empty(vct.pyramid_bytes(grid), dtype=torch.uint8, device=dev)
     out = torch.empty(w.shape + (8,), dtype=torch.float32, device=dev)
-    ws = torch.empty(vct.backward_workspace_bytes(grid, pr, nr, cam, w.params), dtype=torch.uint8, device=dev)
+    ws_full = vct.backward_workspace_bytes(grid, pr, nr, cam, w.params)
+    st_bytes = vct.lane_state_bytes(pr, nr, cam, w.params)
+    ws = torch.empty(ws_full, dtype=torch.uint8, device=dev)
+    state = torch.empty(st_bytes, dtype=torch.uint8, device=dev)
+    ws_saved = ws[:ws_full - st_bytes]
     gbase = torch.empty_like(base)
     vct.build_mips(base, grid, pyr)
     samples = vct.count_samples(pyr, grid, pr, nr, cam, w.params)
     npix = int(np.prod(w.shape))
-    log(f"{samples} cone samples per frame ({samples / npix:.1f} per pixel), workspace {ws.numel() / 2**30:.2f} GiB")
+    log(f"{samples} cone samples per frame ({samples / npix:.1f} per pixel), workspace {ws.numel() / 2**30:.2f} GiB, "
+        f"lane states {st_bytes / 2**30:.2f} GiB")
 
     # a plain copy of known size (256 MiB read + 256 MiB written): its
     # FETCH_SIZE / WRITE_SIZE counters calibrate the byte counters of the
@@ -119,12 +126,12 @@ def main():
         vct.build_mips(base, grid, pyr)
         if ev is not None:
             ev[1].record()
-        vct.trace(pyr, grid, pr, nr, cam, w.params, out)
+        vct.trace_save(pyr, grid, pr, nr, cam, w.params, out, state)
         if ev is not None:
             ev[2].record()
         if kev is not None:
             kev.arm()
-        vct.trace_backward(pyr, grid, pr, nr, cam, w.params, gout, ws, gbase)
+        vct.trace_backward_saved(pyr, grid, pr, nr, cam, w.params, state, gout, ws_saved, gbase)
         if ev is not None:
             ev[3].record()
 
@@ -141,20 +148,39 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     mips_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    fwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    save_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
     bwd_k = np.mean([k.times() for k in kevs], axis=0)
     ms_step = wall * 1e3 / args.steps
-    log(f"step {ms_step:.3f} ms: mips {mips_ms:.3f}, trace {fwd_ms:.3f}, backward {bwd_ms:.3f} "
+    log(f"step {ms_step:.3f} ms: mips {mips_ms:.3f}, trace_save {save_ms:.3f}, backward {bwd_ms:.3f} "
         f"({', '.join(f'{n} {t:.3f}' for n, t in zip(BWD_KERNELS, bwd_k))})")
+
+    # outside the timed steps: the forward alone (inference) and the step
+    # through the entry points that keep no state
+    def timed(fn, k):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        fn()
+        e[0].record()
+        for _ in range(k):
+            fn()
+        e[1].record()
+        torch.cuda.synchronize()
+        return e[0].elapsed_time(e[1]) / k
+
+    fwd_ms = timed(lambda: vct.trace(pyr, grid, pr, nr, cam, w.params, out), args.steps)
+    recompute_bwd_ms = timed(lambda: vct.trace_backward(pyr, grid, pr, nr, cam, w.params, gout, ws, gbase),
+                             max(args.steps // 2, 1))
+    log(f"trace alone {fwd_ms:.3f} ms; recompute path step {mips_ms + fwd_ms + recompute_bwd_ms:.3f} ms")
 
     texel_bytes = 16 if args.dtype == "f32" else 8
     trace_bytes = samples * 16 * texel_bytes + npix * 64
     trace_gbs = trace_bytes / (fwd_ms * 1e-3) / 1e9
     breakdown = {
-        "build_mips_ms": mips_ms, "trace_ms": fwd_ms, "trace_backward_ms": bwd_ms,
-        "trace_backward_kernels_ms": {n: float(t) for n, t in zip(BWD_KERNELS, bwd_k)},
-        "fwd_ms_per_frame": mips_ms + fwd_ms, "fwd_bwd_ms_per_frame": mips_ms + fwd_ms + bwd_ms,
+        "build_mips_ms": mips_ms, "trace_save_ms": save_ms, "trace_backward_saved_ms": bwd_ms,
+        "trace_backward_saved_kernels_ms": {n: float(t) for n, t in zip(BWD_KERNELS, bwd_k)},
+        "trace_ms": fwd_ms, "fwd_ms_per_frame": mips_ms + fwd_ms, "fwd_bwd_ms_per_frame": mips_ms + save_ms + bwd_ms,
+        "recompute_path": {"trace_backward_ms": recompute_bwd_ms,
+                           "fwd_bwd_ms_per_frame": mips_ms + fwd_ms + recompute_bwd_ms},
         "samples_per_frame": samples, "samples_per_pixel": samples / npix,
         "fwd_samples_per_s": samples / ((mips_ms + fwd_ms) * 1e-3),
         "trace_kernel_samples_per_s": samples / (fwd_ms * 1e-3),
@@ -204,7 +230,7 @@ def main():
         "dtype": args.dtype, "data": "synthetic (seeded procedural scene and G-buffer; random dL/dout)",
         "config": {"workload": WORKLOAD_DESC, "grid": w.n, "levels": w.levels, "views": w.shape[0],
                    "height": w.shape[1], "width": w.shape[2], "cones_per_pixel": w.params.n_diffuse + 2,
-                   "step": "build_mips + trace + trace_backward"},
+                   "step": "build_mips + trace_save + trace_backward_saved"},
         "breakdown": breakdown,
         "roofline": roofline,
     }

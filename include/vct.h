@@ -166,6 +166,32 @@ int vct_trace_backward(const vct_grid* grid, const void* pyramid, const vct_gbuf
                        const vct_cone_params* params, const float* grad_out, float* grad_base,
                        void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Training path: a forward that also keeps every cone's end state so that the
+ * backward need not re-march once more to recover it.
+ *
+ * vct_lane_state_bytes: bytes of the lane-state buffer for these shapes (host
+ * only); (b*h*w) * (n_diffuse + 2) states of 48 bytes, rounded up to 256.
+ *
+ * vct_trace_save: the forward of vct_trace (same cones, same sample counts),
+ * with the colour accumulated as a double-float, so that `out` agrees with
+ * vct_trace to float32 rounding rather than bit for bit; it also writes the
+ * lane states (C_K, A_K, K and the sums the fixed-point scale of the adjoint
+ * needs) to `lane_state` (device, opaque, overwritten).  Per-sample
+ * transmittance is not stored; the backward still recomputes it.
+ *
+ * vct_trace_backward_saved: vct_trace_backward given those lane states (same
+ * grid, pyramid, G-buffer and parameters as the vct_trace_save call).  Its
+ * result is bitwise equal to vct_trace_backward's.  The workspace needs
+ * vct_backward_workspace_bytes - vct_lane_state_bytes bytes. */
+int vct_lane_state_bytes(const vct_gbuffer* gbuf, const vct_cone_params* params, size_t* bytes);
+int vct_trace_save(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                   const vct_cone_params* params, float* out, void* lane_state, size_t lane_state_bytes,
+                   hipStream_t stream);
+int vct_trace_backward_saved(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                             const vct_cone_params* params, const void* lane_state, size_t lane_state_bytes,
+                             const float* grad_out, float* grad_base, void* workspace, size_t workspace_bytes,
+                             hipStream_t stream);
+
 /* Diagnostics: per-kernel timing.  Registers `count` events (a host array of
  * hipEvent_t created by the caller) for the NEXT enqueuing call on this thread
  * (vct_build_mips, vct_trace, vct_count_samples or vct_trace_backward).  That

@@ -69,6 +69,9 @@ def lib():
         "vct_count_samples": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
         "vct_backward_workspace_bytes": [P(CGrid), P(CGBuffer), P(CConeParams), P(sz)],
         "vct_trace_backward": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp, vp, sz, vp],
+        "vct_lane_state_bytes": [P(CGBuffer), P(CConeParams), P(sz)],
+        "vct_trace_save": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp, sz, vp],
+        "vct_trace_backward_saved": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, sz, vp, vp, vp, sz, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -312,16 +315,65 @@ def trace_backward(pyramid, grid, pos_rough, normal, cam_pos, params, grad_out, 
     return grad_base
 
 
+def lane_state_bytes(pos_rough, normal, cam_pos, params):
+    gb = _gbuf(pos_rough, normal, cam_pos)
+    n = ctypes.c_size_t()
+    _check(lib().vct_lane_state_bytes(ctypes.byref(gb), ctypes.byref(cone_params(params)), ctypes.byref(n)))
+    return n.value
+
+
+def trace_save(pyramid, grid, pos_rough, normal, cam_pos, params, out=None, lane_state=None):
+    """Forward that also returns the cones' end states for trace_backward_saved."""
+    gb = _gbuf(pos_rough, normal, cam_pos)
+    dev = pos_rough.device
+    if out is None:
+        out = torch.empty(tuple(pos_rough.shape[:3]) + (8,), dtype=torch.float32, device=dev)
+    _need(out, "out", torch.float32, tuple(pos_rough.shape[:3]) + (8,), dev)
+    if lane_state is None:
+        lane_state = torch.empty(lane_state_bytes(pos_rough, normal, cam_pos, params), dtype=torch.uint8, device=dev)
+    _need(lane_state, "lane_state", torch.uint8, None, dev)
+    with torch.cuda.device(dev):
+        _check(lib().vct_trace_save(ctypes.byref(grid.c()), _ptr(pyramid), ctypes.byref(gb),
+                                    ctypes.byref(cone_params(params)), _ptr(out), _ptr(lane_state),
+                                    lane_state.numel(), _stream(dev)))
+    return out, lane_state
+
+
+def trace_backward_saved(pyramid, grid, pos_rough, normal, cam_pos, params, lane_state, grad_out, workspace=None,
+                         grad_base=None):
+    """trace_backward given the lane states of trace_save (bitwise equal result)."""
+    gb = _gbuf(pos_rough, normal, cam_pos)
+    dev = pos_rough.device
+    _need(grad_out, "grad_out", torch.float32, tuple(pos_rough.shape[:3]) + (8,), dev)
+    _need(lane_state, "lane_state", torch.uint8, None, dev)
+    nbytes = backward_workspace_bytes(grid, pos_rough, normal, cam_pos, params) - lane_state_bytes(
+        pos_rough, normal, cam_pos, params)
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    _need(workspace, "workspace", torch.uint8, None, dev)
+    if grad_base is None:
+        grad_base = torch.empty((grid.n, grid.n, grid.n, 4), dtype=torch.float32, device=dev)
+    _need(grad_base, "grad_base", torch.float32, (grid.n, grid.n, grid.n, 4), dev)
+    with torch.cuda.device(dev):
+        _check(lib().vct_trace_backward_saved(ctypes.byref(grid.c()), _ptr(pyramid), ctypes.byref(gb),
+                                              ctypes.byref(cone_params(params)), _ptr(lane_state), lane_state.numel(),
+                                              _ptr(grad_out), _ptr(grad_base), _ptr(workspace), workspace.numel(),
+                                              _stream(dev)))
+    return grad_base
+
+
 class VCTTrace(torch.autograd.Function):
-    """out = trace(build_mips(base)); backward gives dL/d(base) through
-    vct_trace_backward (hand-written adjoint, deterministic)."""
+    """out = trace(build_mips(base)); backward gives dL/d(base) through the
+    hand-written adjoint (deterministic).  The forward keeps every cone's end
+    state (trace_save) so the backward skips one re-march."""
 
     @staticmethod
     def forward(ctx, base, pos_rough, normal, cam_pos, grid, params):
         pyr = build_mips(base.contiguous(), grid)
-        out = trace(pyr, grid, pos_rough, normal, cam_pos, params)
+        out, state = trace_save(pyr, grid, pos_rough, normal, cam_pos, params)
         ctx.save_for_backward(pos_rough, normal, cam_pos)
         ctx.pyr = pyr
+        ctx.state = state
         ctx.grid = grid
         ctx.params = params
         return out
@@ -329,7 +381,8 @@ class VCTTrace(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         pos_rough, normal, cam_pos = ctx.saved_tensors
-        g = trace_backward(ctx.pyr, ctx.grid, pos_rough, normal, cam_pos, ctx.params, grad_out.contiguous())
+        g = trace_backward_saved(ctx.pyr, ctx.grid, pos_rough, normal, cam_pos, ctx.params, ctx.state,
+                                 grad_out.contiguous())
         return g, None, None, None, None, None
 
 

@@ -260,10 +260,44 @@ int vct_backward_workspace_bytes(const vct_grid* grid, const vct_gbuffer* gbuf, 
     return VCT_OK;
 }
 
-int vct_trace_backward(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
-                       const vct_cone_params* params, const float* grad_out, float* grad_base, void* workspace,
-                       size_t workspace_bytes, hipStream_t stream) {
-    const char* fn = "vct_trace_backward";
+int vct_lane_state_bytes(const vct_gbuffer* gbuf, const vct_cone_params* params, size_t* bytes) {
+    const char* fn = "vct_lane_state_bytes";
+    if (int r = check_gbuffer(fn, gbuf)) return r;
+    if (!params) return fail(VCT_EINVAL, fn, "params is null");
+    if (params->n_diffuse < 0 || params->n_diffuse > VCT_MAX_DIFFUSE)
+        return fail(VCT_EINVAL, fn, "n_diffuse = %d must be in [0, %d]", params->n_diffuse, VCT_MAX_DIFFUSE);
+    if (!bytes) return fail(VCT_EINVAL, fn, "bytes is null");
+    int64_t lanes = (int64_t)gbuf->b * gbuf->h * gbuf->w * (params->n_diffuse + 2);
+    *bytes = (size_t)vct_lane_state_bytes(lanes);
+    ok();
+    return VCT_OK;
+}
+
+int vct_trace_save(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf, const vct_cone_params* params,
+                   float* out, void* lane_state, size_t lane_state_bytes, hipStream_t stream) {
+    const char* fn = "vct_trace_save";
+    EventSink es = take_events();
+    if (int r = check_grid(fn, grid)) return r;
+    if (int r = check_gbuffer(fn, gbuf)) return r;
+    if (int r = check_params(fn, grid, params)) return r;
+    long long np = (long long)gbuf->b * gbuf->h * gbuf->w;
+    if (np > 0 && (!out || !lane_state || !pyramid))
+        return fail(VCT_EINVAL, fn, "pyramid, out and lane_state must be non-null");
+    int64_t need = vct_lane_state_bytes(np * (params->n_diffuse + 2));
+    if (lane_state_bytes < (size_t)need)
+        return fail(VCT_EWORKSPACE, fn, "lane_state has %zu bytes, needs %lld", lane_state_bytes, (long long)need);
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    TraceArgs a = make_args(grid, L, pyramid, gbuf, params);
+    hipError_t e = vct_launch_trace_save(a, grid->dtype, out, lane_state, stream, es);
+    if (e != hipSuccess) return device_error(fn, e);
+    ok();
+    return VCT_OK;
+}
+
+static int backward_common(const char* fn, const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                           const vct_cone_params* params, const void* lane_state, size_t lane_state_bytes,
+                           bool saved, const float* grad_out, float* grad_base, void* workspace,
+                           size_t workspace_bytes, hipStream_t stream) {
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
@@ -278,12 +312,35 @@ int vct_trace_backward(const vct_grid* grid, const void* pyramid, const vct_gbuf
     PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
     TraceArgs a = make_args(grid, L, pyramid, gbuf, params);
     BackwardPlan P = vct_plan_backward(L, a);
-    if (workspace_bytes < (size_t)P.bytes)
-        return fail(VCT_EWORKSPACE, fn, "workspace has %zu bytes, needs %lld", workspace_bytes, (long long)P.bytes);
-    hipError_t e = vct_launch_backward(L, a, P, grad_out, grad_base, workspace, stream, es);
+    const int64_t need = saved ? P.state_off : P.bytes;
+    if (workspace_bytes < (size_t)need)
+        return fail(VCT_EWORKSPACE, fn, "workspace has %zu bytes, needs %lld", workspace_bytes, (long long)need);
+    if (saved) {
+        if (np > 0 && !lane_state) return fail(VCT_EINVAL, fn, "lane_state is null");
+        if (lane_state_bytes < (size_t)P.state_bytes)
+            return fail(VCT_EWORKSPACE, fn, "lane_state has %zu bytes, needs %lld", lane_state_bytes,
+                        (long long)P.state_bytes);
+    }
+    hipError_t e = vct_launch_backward(L, a, P, grad_out, grad_base, workspace, saved ? lane_state : nullptr, stream,
+                                       es);
     if (e != hipSuccess) return device_error(fn, e);
     ok();
     return VCT_OK;
+}
+
+int vct_trace_backward(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                       const vct_cone_params* params, const float* grad_out, float* grad_base, void* workspace,
+                       size_t workspace_bytes, hipStream_t stream) {
+    return backward_common("vct_trace_backward", grid, pyramid, gbuf, params, nullptr, 0, false, grad_out, grad_base,
+                           workspace, workspace_bytes, stream);
+}
+
+int vct_trace_backward_saved(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                             const vct_cone_params* params, const void* lane_state, size_t lane_state_bytes,
+                             const float* grad_out, float* grad_base, void* workspace, size_t workspace_bytes,
+                             hipStream_t stream) {
+    return backward_common("vct_trace_backward_saved", grid, pyramid, gbuf, params, lane_state, lane_state_bytes,
+                           true, grad_out, grad_base, workspace, workspace_bytes, stream);
 }
 
 int vct_record_kernel_events(hipEvent_t* events, int32_t count) {

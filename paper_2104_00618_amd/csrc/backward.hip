@@ -55,6 +55,42 @@ __global__ __launch_bounds__(kThreads) void k_bwd_pass1(TraceArgs a, const float
     if (threadIdx.x == 0) part[blockIdx.x] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
 }
 
+// Forward that also saves every cone's end state (training path: the
+// backward then skips pass 1).
+template <int DT>
+__global__ __launch_bounds__(kThreads) void k_trace_save(TraceArgs a, float4* __restrict__ out,
+                                                         LaneState* __restrict__ state) {
+    __shared__ LevelTable T;
+    load_level_table(a, &T);
+    __syncthreads();
+    const int tile = xcd_tile(blockIdx.x, a.n_tiles);
+    int view, y, x;
+    tile_pixel(a, tile, threadIdx.x, view, y, x);
+    if (!(x < a.w && y < a.h)) return;
+    const size_t pix = ((size_t)view * a.h + y) * a.w + x;
+    float4 o0, o1;
+    trace_save_pixel<DT>(a, T, view, pix, state, o0, o1);
+    out[2 * pix] = o0;
+    out[2 * pix + 1] = o1;
+}
+
+// Per-workgroup bound sums from saved lane states (same tiles and summation
+// order as pass 1, so the scale exponent is the same).
+__global__ __launch_bounds__(kThreads) void k_bwd_bound(TraceArgs a, const float4* __restrict__ gout,
+                                                        const LaneState* __restrict__ state, float* __restrict__ part) {
+    __shared__ float s_part[kThreads / 64];
+    const int tile = xcd_tile(blockIdx.x, a.n_tiles);
+    int view, y, x;
+    tile_pixel(a, tile, threadIdx.x, view, y, x);
+    float bound = 0.f;
+    if (x < a.w && y < a.h) bound = saved_bound_pixel(a, gout, state, ((size_t)view * a.h + y) * a.w + x);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) bound += __shfl_xor(bound, o, 64);
+    if (lane == 0) s_part[wv] = bound;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
+}
+
 // ctl[0] = E, ctl[1] = 1 if the bound is not finite
 __global__ __launch_bounds__(kThreads) void k_bwd_scale(const float* __restrict__ part, int n, int* __restrict__ ctl) {
     __shared__ float s[kThreads];
@@ -316,10 +352,11 @@ __global__ __launch_bounds__(256) void k_mip_adjoint(AdjArgs m, const long long*
 
 template <int DT>
 hipError_t run_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPlan& P, const float* grad_out,
-                        float* grad_base, void* ws, hipStream_t s, EventSink& es) {
+                        float* grad_base, void* ws, const void* saved, hipStream_t s, EventSink& es) {
     char* w = static_cast<char*>(ws);
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(w + P.acc_off);
-    LaneState* state = reinterpret_cast<LaneState*>(w + P.state_off);
+    LaneState* state = saved ? reinterpret_cast<LaneState*>(const_cast<void*>(saved))
+                             : reinterpret_cast<LaneState*>(w + P.state_off);
     float* part = reinterpret_cast<float*>(w + P.part_off);
     int* ctl = reinterpret_cast<int*>(w + P.ctl_off);
     size_t n16 = (size_t)P.acc_bytes / 16;
@@ -330,7 +367,10 @@ hipError_t run_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPl
     const float4* g4 = reinterpret_cast<const float4*>(grad_out);
     es.mark(s);
     if (a.n_tiles > 0) {
-        hipLaunchKernelGGL(k_bwd_pass1<DT>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, part);
+        if (saved)
+            hipLaunchKernelGGL(k_bwd_bound, dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, part);
+        else
+            hipLaunchKernelGGL(k_bwd_pass1<DT>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, part);
     }
     es.mark(s);
     hipLaunchKernelGGL(k_bwd_scale, dim3(1), dim3(kThreads), 0, s, part, (int)P.n_blocks, ctl);
@@ -380,24 +420,42 @@ BackwardPlan vct_plan_backward(const PyrLayout& L, const TraceArgs& a) {
     P.acc_off = off;
     P.acc_bytes = align256(L.total_texels * 32);
     off += P.acc_bytes;
-    P.state_off = off;
-    P.state_bytes = align256(P.n_lanes * (int64_t)sizeof(LaneState));
-    off += P.state_bytes;
     P.part_off = off;
     P.part_bytes = align256(P.n_blocks * 4 + 4);
     off += P.part_bytes;
     P.ctl_off = off;
     P.ctl_bytes = 256;
     off += P.ctl_bytes;
+    P.state_off = off;            // last, so that the saved-state variant needs only state_off bytes
+    P.state_bytes = vct_lane_state_bytes(P.n_lanes);
+    off += P.state_bytes;
     P.bytes = off;
     return P;
 }
 
+int64_t vct_lane_state_bytes(int64_t n_lanes) { return align256(n_lanes * (int64_t)sizeof(LaneState)); }
+
 hipError_t vct_launch_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPlan& P, const float* grad_out,
-                               float* grad_base, void* ws, hipStream_t s, EventSink& es) {
+                               float* grad_base, void* ws, const void* saved, hipStream_t s, EventSink& es) {
     switch (L.dtype) {
-        case VCT_F32: return run_backward<VCT_F32>(L, a, P, grad_out, grad_base, ws, s, es);
-        case VCT_F16: return run_backward<VCT_F16>(L, a, P, grad_out, grad_base, ws, s, es);
-        default: return run_backward<VCT_BF16>(L, a, P, grad_out, grad_base, ws, s, es);
+        case VCT_F32: return run_backward<VCT_F32>(L, a, P, grad_out, grad_base, ws, saved, s, es);
+        case VCT_F16: return run_backward<VCT_F16>(L, a, P, grad_out, grad_base, ws, saved, s, es);
+        default: return run_backward<VCT_BF16>(L, a, P, grad_out, grad_base, ws, saved, s, es);
     }
+}
+
+hipError_t vct_launch_trace_save(const TraceArgs& a, int dtype, float* out, void* state, hipStream_t s,
+                                 EventSink& es) {
+    if (a.n_tiles > 0) {
+        es.mark(s);
+        float4* o = reinterpret_cast<float4*>(out);
+        LaneState* st = reinterpret_cast<LaneState*>(state);
+        switch (dtype) {
+            case VCT_F32: hipLaunchKernelGGL(k_trace_save<VCT_F32>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, o, st); break;
+            case VCT_F16: hipLaunchKernelGGL(k_trace_save<VCT_F16>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, o, st); break;
+            default: hipLaunchKernelGGL(k_trace_save<VCT_BF16>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, o, st); break;
+        }
+    }
+    es.mark(s);
+    return hipGetLastError();
 }

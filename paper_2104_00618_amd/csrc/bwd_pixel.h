@@ -10,9 +10,11 @@
 
 namespace vct {
 
+// End state of one cone after its forward march (48 bytes).
 struct LaneState {
     float4 hi;   // C_K.hi (rgb), A_K
     float4 lo;   // C_K.lo (rgb), K (as int bits)
+    float4 st;   // sum_k |T_k|, sum_{k<K-1} |T_k / T_{k+1}|, max_k |C_k|, T_{K-1}
 };
 
 // dL/dC (3) and dL/dA of cone `slot` from the pixel's dL/d(out) = (g0, g1).
@@ -88,6 +90,38 @@ __device__ __forceinline__ Pass1Out pass1_march(const TraceArgs& a, const LevelT
     return r;
 }
 
+__device__ __forceinline__ LaneState lane_state(const Pass1Out& r) {
+    LaneState out;
+    out.hi = make_float4(r.C[0].hi, r.C[1].hi, r.C[2].hi, r.A);
+    out.lo = make_float4(r.C[0].lo, r.C[1].lo, r.C[2].lo, __int_as_float(r.K));
+    out.st = make_float4(r.ST, r.SQ, r.MC, r.Tlast);
+    return out;
+}
+
+__device__ __forceinline__ LaneState zero_lane_state() {
+    LaneState z;
+    z.hi = make_float4(0.f, 0.f, 0.f, 0.f);
+    z.lo = z.hi;
+    z.st = z.hi;
+    return z;
+}
+
+// Bound on sum_k |dL/dc_k|_1 + |dL/da_k| of one cone from its end state:
+// |dL/dc_k| = |T_k| |dL/dC|, and for k < K-1
+// |dL/da_k| <= |T_k / T_{k+1}| (|dL/dC|_1 (|C_K| + max|C|) + |dL/dA| |T_K|);
+// the last sample gives |T_{K-1} dL/dA|.
+__device__ __forceinline__ float lane_bound(const TraceArgs& a, int slot, const LaneState& S, float4 g0, float4 g1) {
+    float gc[3], ga;
+    slot_grads(a, slot, g0, g1, gc, ga);
+    const int K = __float_as_int(S.lo.w);
+    const float gc1 = fabsf(gc[0]) + fabsf(gc[1]) + fabsf(gc[2]);
+    const float TK = 1.0f - S.hi.w;
+    const float CK = fmaxf(fabsf(S.hi.x), fmaxf(fabsf(S.hi.y), fabsf(S.hi.z)));
+    const float b = S.st.x * gc1 + S.st.y * (gc1 * (CK + S.st.z) + fabsf(ga) * fabsf(TK)) +
+                    (K > 0 ? fabsf(ga) * fabsf(S.st.w) : 0.f);
+    return b * 1.001f;
+}
+
 // Pass 1 for one pixel: stores the lane states of its cones and returns the
 // bound on sum_k |dL/dc_k|_1 + |dL/da_k| over them.
 template <int DT>
@@ -98,12 +132,7 @@ __device__ __forceinline__ float pass1_pixel(const TraceArgs& a, const LevelTabl
     float4 nr = a.normal[pix];
     float bound = 0.f;
     if (nr.w == 0.0f) {
-        for (int slot = 0; slot < nslots; ++slot) {
-            LaneState z;
-            z.hi = make_float4(0.f, 0.f, 0.f, 0.f);
-            z.lo = make_float4(0.f, 0.f, 0.f, 0.f);
-            st[slot] = z;
-        }
+        for (int slot = 0; slot < nslots; ++slot) st[slot] = zero_lane_state();
         return 0.f;
     }
     float4 pr = a.pos_rough[pix];
@@ -111,27 +140,68 @@ __device__ __forceinline__ float pass1_pixel(const TraceArgs& a, const LevelTabl
     PixelSetup P = pixel_setup(a, pr, nr);
     float3 cam = make_float3(a.cam_pos[3 * view], a.cam_pos[3 * view + 1], a.cam_pos[3 * view + 2]);
     for (int slot = 0; slot < nslots; ++slot) {
-        LaneState out;
-        out.hi = make_float4(0.f, 0.f, 0.f, 0.f);
-        out.lo = make_float4(0.f, 0.f, 0.f, 0.f);
+        LaneState out = zero_lane_state();
         if (slot_enabled(a, slot)) {
             Cone c = cone_for_slot(a, P, slot, cam);
-            Pass1Out r = pass1_march<DT>(a, T, c);
-            out.hi = make_float4(r.C[0].hi, r.C[1].hi, r.C[2].hi, r.A);
-            out.lo = make_float4(r.C[0].lo, r.C[1].lo, r.C[2].lo, __int_as_float(r.K));
-            float gc[3], ga;
-            slot_grads(a, slot, g0, g1, gc, ga);
-            float gc1 = fabsf(gc[0]) + fabsf(gc[1]) + fabsf(gc[2]);
-            float TK = 1.0f - r.A;
-            float CK = fmaxf(fabsf(r.C[0].hi), fmaxf(fabsf(r.C[1].hi), fabsf(r.C[2].hi)));
-            // sum_k |dL/dc_k|_1 + |dL/da_k| <= this; the last sample uses T_{K-1} dL/dA
-            float b = r.ST * gc1 + r.SQ * (gc1 * (CK + r.MC) + fabsf(ga) * fabsf(TK)) +
-                      (r.K > 0 ? fabsf(ga) * fabsf(r.Tlast) : 0.f);
-            bound += b * 1.001f;
+            out = lane_state(pass1_march<DT>(a, T, c));
+            bound += lane_bound(a, slot, out, g0, g1);
         }
         st[slot] = out;
     }
     return bound;
+}
+
+// Bound of one pixel's cones from saved lane states.
+__device__ __forceinline__ float saved_bound_pixel(const TraceArgs& a, const float4* __restrict__ gout,
+                                                   const LaneState* __restrict__ state, size_t pix) {
+    if (a.normal[pix].w == 0.0f) return 0.f;
+    const int nslots = a.n_diffuse + 2;
+    const float4 g0 = gout[2 * pix], g1 = gout[2 * pix + 1];
+    float bound = 0.f;
+    for (int slot = 0; slot < nslots; ++slot)
+        if (slot_enabled(a, slot)) bound += lane_bound(a, slot, state[pix * nslots + slot], g0, g1);
+    return bound;
+}
+
+// Forward for one pixel that also saves its cones' end states (for the
+// backward): the same march as pass 1, with the epilogue of trace_pixel.
+template <int DT>
+__device__ __forceinline__ void trace_save_pixel(const TraceArgs& a, const LevelTable& T, int view, size_t pix,
+                                                 LaneState* __restrict__ state, float4& o0, float4& o1) {
+    o0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    o1 = o0;
+    const int nslots = a.n_diffuse + 2;
+    LaneState* st = state + pix * nslots;
+    float4 nr = a.normal[pix];
+    if (nr.w == 0.0f) {
+        for (int slot = 0; slot < nslots; ++slot) st[slot] = zero_lane_state();
+        return;
+    }
+    PixelSetup P = pixel_setup(a, a.pos_rough[pix], nr);
+    float3 cam = make_float3(a.cam_pos[3 * view], a.cam_pos[3 * view + 1], a.cam_pos[3 * view + 2]);
+    for (int slot = 0; slot < nslots; ++slot) {
+        LaneState out = zero_lane_state();
+        if (slot_enabled(a, slot)) {
+            Cone c = cone_for_slot(a, P, slot, cam);
+            Pass1Out r = pass1_march<DT>(a, T, c);
+            out = lane_state(r);
+            const float cr = r.C[0].hi + r.C[0].lo, cg = r.C[1].hi + r.C[1].lo, cb = r.C[2].hi + r.C[2].lo;
+            if (slot < a.n_diffuse) {
+                const float wq = a.weight[slot];
+                o0.x = __builtin_fmaf(wq, cr, o0.x);
+                o0.y = __builtin_fmaf(wq, cg, o0.y);
+                o0.z = __builtin_fmaf(wq, cb, o0.z);
+                o0.w = __builtin_fmaf(wq, r.A, o0.w);
+            } else if (slot == a.n_diffuse) {
+                o1.x = cr;
+                o1.y = cg;
+                o1.z = cb;
+            } else {
+                o1.w = r.A;
+            }
+        }
+        st[slot] = out;
+    }
 }
 
 // Pass-2 state of one cone of one lane.

@@ -132,5 +132,9 @@ struct BackwardPlan {
 };
 
 BackwardPlan vct_plan_backward(const PyrLayout& L, const TraceArgs& a);
+int64_t vct_lane_state_bytes(int64_t n_lanes);
+// saved == nullptr: recompute the lane states (pass 1); else read them from `saved`
 hipError_t vct_launch_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPlan& P,
-                               const float* grad_out, float* grad_base, void* ws, hipStream_t s, EventSink& es);
+                               const float* grad_out, float* grad_base, void* ws, const void* saved, hipStream_t s,
+                               EventSink& es);
+hipError_t vct_launch_trace_save(const TraceArgs& a, int dtype, float* out, void* state, hipStream_t s, EventSink& es);

@@ -154,24 +154,29 @@ def _solid_and_albedo(sc):
 
 def _shadow(solid, start, light, n):
     """Hard shadow: march from ``start`` toward the light in steps of half a
-    voxel, looking up the nearest voxel; returns 1 where nothing solid is hit."""
-    light = np.asarray(light, dtype=np.float64)
-    vis = np.ones(len(start), dtype=bool)
-    delta = light[None, :] - start
-    dist = np.linalg.norm(delta, axis=1)
-    dirn = delta / np.maximum(dist, 1e-12)[:, None]
+    voxel, looking up the nearest voxel; returns 1 where nothing solid is hit.
+    Elementwise float64 torch ops on the CPU (multi-threaded, deterministic)."""
+    import torch
+
+    light = torch.tensor(np.asarray(light, dtype=np.float64))
+    st = torch.from_numpy(np.ascontiguousarray(start, dtype=np.float64))
+    occ = torch.from_numpy(np.ascontiguousarray(solid)).reshape(-1)
+    delta = light[None, :] - st
+    dist = torch.linalg.vector_norm(delta, dim=1)
+    dirn = delta / torch.clamp(dist, min=1e-12)[:, None]
     step = 0.5 / n
-    idx = np.arange(len(start))
-    t = np.zeros(len(start))
+    vis = torch.ones(len(st), dtype=torch.bool)
+    idx = torch.arange(len(st))
+    t = torch.zeros(len(st), dtype=torch.float64)
     while len(idx):
-        p = start[idx] + t[idx, None] * dirn[idx]
-        ijk = np.clip(np.floor(p * n).astype(np.int64), 0, n - 1)
-        hit = solid[ijk[:, 2], ijk[:, 1], ijk[:, 0]]
+        p = st[idx] + t[idx, None] * dirn[idx]
+        ijk = torch.clamp(torch.floor(p * n).to(torch.int64), 0, n - 1)
+        hit = occ[(ijk[:, 2] * n + ijk[:, 1]) * n + ijk[:, 0]]
         vis[idx[hit]] = False
         t[idx] += step
         keep = (~hit) & (t[idx] < dist[idx])
         idx = idx[keep]
-    return vis
+    return vis.numpy()
 
 
 def voxelize_scene(sc):
@@ -252,61 +257,64 @@ def _planes(sc):
 
 def render_gbuffer(sc, eye, target, h, w, fov_deg=60.0):
     """Analytic G-buffer: (pos_rough [h,w,4], normal [h,w,4]) float32.
-    pos_rough = (x, y, z, roughness); normal = (nx, ny, nz, valid)."""
-    o, d = camera_rays(eye, target, h, w, fov_deg)
+    pos_rough = (x, y, z, roughness); normal = (nx, ny, nz, valid).
+    Elementwise float64 torch ops on the CPU (multi-threaded, deterministic)."""
+    import torch
+
+    o_np, d_np = camera_rays(eye, target, h, w, fov_deg)
+    o = torch.tensor(o_np, dtype=torch.float64)
+    d = torch.from_numpy(d_np)
     m = d.shape[0]
-    best_t = np.full(m, np.inf)
-    best_n = np.zeros((m, 3))
-    best_r = np.zeros(m)
-    best_plane = np.zeros(m, dtype=bool)
+    best_t = torch.full((m,), float("inf"), dtype=torch.float64)
+    best_n = torch.zeros((m, 3), dtype=torch.float64)
+    best_r = torch.zeros(m, dtype=torch.float64)
+    best_plane = torch.zeros(m, dtype=torch.bool)
     eps = 1e-9
     for ax, val, sgn, rlo, rhi, rough in _planes(sc):
         dd = d[:, ax]
-        with np.errstate(divide="ignore", invalid="ignore"):
-            t = (val - o[ax]) / dd
+        t = (float(val) - o[ax]) / dd
         facing = dd * sgn < 0
-        p = o[None, :] + t[:, None] * d
-        inside = np.ones(m, dtype=bool)
+        inside = torch.ones(m, dtype=torch.bool)
         for a2 in range(3):
             if a2 == ax:
                 continue
-            inside &= (p[:, a2] >= rlo[a2] - eps) & (p[:, a2] <= rhi[a2] + eps)
+            pa = o[a2] + t * d[:, a2]
+            inside &= (pa >= float(rlo[a2]) - eps) & (pa <= float(rhi[a2]) + eps)
         ok = facing & inside & (t > 1e-9) & (t < best_t)
-        best_t[ok] = t[ok]
-        nv = np.zeros(3)
+        best_t = torch.where(ok, t, best_t)
+        nv = torch.zeros(3, dtype=torch.float64)
         nv[ax] = sgn
         best_n[ok] = nv
-        best_r[ok] = rough
+        best_r[ok] = float(rough)
         best_plane[ok] = True
     for s in sc.spheres:
-        oc = o[None, :] - s.centre[None, :]
-        bq = np.sum(oc * d, axis=1)
-        cq = np.sum(oc * oc, axis=1) - s.radius ** 2
+        c = torch.tensor(s.centre, dtype=torch.float64)
+        oc = o - c
+        bq = d @ oc
+        cq = float(oc @ oc) - s.radius ** 2
         disc = bq * bq - cq
-        with np.errstate(invalid="ignore"):
-            t = -bq - np.sqrt(disc)
+        t = -bq - torch.sqrt(torch.clamp(disc, min=0.0))
         ok = (disc >= 0) & (t > 1e-9) & (t < best_t)
-        best_t[ok] = t[ok]
+        best_t = torch.where(ok, t, best_t)
         p = o[None, :] + t[ok, None] * d[ok]
-        nv = (p - s.centre[None, :]) / s.radius
-        best_n[ok] = nv / np.linalg.norm(nv, axis=1, keepdims=True)
+        nv = (p - c[None, :]) / s.radius
+        best_n[ok] = nv / torch.linalg.vector_norm(nv, dim=1, keepdim=True)
         best_r[ok] = s.roughness
         best_plane[ok] = False
-    valid = np.isfinite(best_t)
-    pos = np.zeros((m, 3))
-    pos[valid] = o[None, :] + best_t[valid, None] * d[valid]
-    # snap plane hits exactly onto their plane (removes ray-cast rounding)
-    pr = np.zeros((m, 4), dtype=np.float32)
-    nr = np.zeros((m, 4), dtype=np.float32)
-    pr[:, 0:3] = pos.astype(np.float32)
-    pr[:, 3] = np.where(valid, best_r, 0.0).astype(np.float32)
-    nr[:, 0:3] = best_n.astype(np.float32)
-    nr[:, 3] = valid.astype(np.float32)
+    valid = torch.isfinite(best_t)
+    pos = torch.where(valid[:, None], o[None, :] + torch.where(valid, best_t, 0.0)[:, None] * d,
+                      torch.zeros((), dtype=torch.float64))
+    pr = torch.zeros((m, 4), dtype=torch.float32)
+    nr = torch.zeros((m, 4), dtype=torch.float32)
+    pr[:, 0:3] = pos.to(torch.float32)
+    pr[:, 3] = torch.where(valid, best_r, 0.0).to(torch.float32)
+    nr[:, 0:3] = best_n.to(torch.float32)
+    nr[:, 3] = valid.to(torch.float32)
+    # plane hits lie exactly on their (voxel-face) plane: snap away the ray-cast rounding
     for ax in range(3):
-        on_plane = valid & best_plane & (np.abs(best_n[:, ax]) == 1.0)
-        # plane coordinate is the plane value exactly; recompute from the snapped geometry
-        pr[on_plane, ax] = np.float32(np.rint(pos[on_plane, ax] * sc.n) / sc.n)
-    return pr.reshape(h, w, 4), nr.reshape(h, w, 4)
+        on_plane = valid & best_plane & (best_n[:, ax].abs() == 1.0)
+        pr[on_plane, ax] = (torch.round(pos[on_plane, ax] * sc.n) / sc.n).to(torch.float32)
+    return pr.numpy().reshape(h, w, 4), nr.numpy().reshape(h, w, 4)
 
 
 def random_camera(seed):

@@ -227,3 +227,55 @@ def test_kernel_event_registration_is_validated():
     assert lib.vct_record_kernel_events(None, 3) == EINVAL
     assert "events" in lib.vct_last_error().decode()
     assert lib.vct_record_kernel_events(None, 0) == 0
+
+
+def test_lane_state_size_query_follows_the_layout():
+    p = B.cone_params(_params(alpha_thresh=0.99))
+    gb = B.CGBuffer()
+    gb.b, gb.h, gb.w = 2, 3, 5
+    gb.pos_rough = gb.normal = gb.cam_pos = 0x1000     # never dereferenced by a size query
+    n = ctypes.c_size_t()
+    assert vct.lib().vct_lane_state_bytes(ctypes.byref(gb), ctypes.byref(p), ctypes.byref(n)) == 0
+    assert n.value == (2 * 3 * 5 * (6 + 2) * 48 + 255) // 256 * 256
+    p.n_diffuse = 17
+    assert vct.lib().vct_lane_state_bytes(ctypes.byref(gb), ctypes.byref(p), ctypes.byref(n)) == EINVAL
+    assert "n_diffuse" in vct.lib().vct_last_error().decode()
+
+
+def test_saved_path_rejects_bad_arguments_before_launch():
+    lib = vct.lib()
+    g = vct.Grid(16).c()
+    p = B.cone_params(_params(alpha_thresh=0.99))
+    gb = B.CGBuffer()
+    gb.b, gb.h, gb.w = 1, 4, 4            # pixels but null pointers
+    rc = lib.vct_trace_save(ctypes.byref(g), None, ctypes.byref(gb), ctypes.byref(p), None, None, 0, None)
+    assert rc == EINVAL and "non-null" in lib.vct_last_error().decode()
+    gb = _empty_gbuf()
+    bad = B.cone_params(_params(alpha_thresh=1.5))
+    rc = lib.vct_trace_backward_saved(ctypes.byref(g), None, ctypes.byref(gb), ctypes.byref(bad), None, 0, None,
+                                      None, None, 0, None)
+    assert rc == EINVAL and "alpha_thresh" in lib.vct_last_error().decode()
+    bad = B.cone_params(_params(step_factor=0.0))
+    rc = lib.vct_trace_save(ctypes.byref(g), None, ctypes.byref(gb), ctypes.byref(bad), None, None, 0, None)
+    assert rc == EINVAL and "step_factor" in lib.vct_last_error().decode()
+
+
+@pytest.mark.skipif(os.environ.get("VCT_HOST_ONLY_DUMMY_PTRS") is None and
+                    __import__("torch").cuda.is_available(),
+                    reason="uses dummy device pointers; run on hosts without a GPU only")
+def test_saved_path_undersized_buffers_give_eworkspace():
+    lib = vct.lib()
+    fake = ctypes.c_void_p(0x1000)
+    g = vct.Grid(16).c()
+    p = B.cone_params(_params(alpha_thresh=0.99))
+    gb = B.CGBuffer()
+    gb.b, gb.h, gb.w = 1, 4, 4
+    gb.pos_rough = gb.normal = gb.cam_pos = 0x1000
+    rc = lib.vct_trace_save(ctypes.byref(g), fake, ctypes.byref(gb), ctypes.byref(p), fake, fake, 100, None)
+    assert rc == EWORKSPACE and "lane_state" in lib.vct_last_error().decode()
+    rc = lib.vct_trace_backward_saved(ctypes.byref(g), fake, ctypes.byref(gb), ctypes.byref(p), fake, 100, fake,
+                                      fake, fake, 1 << 30, None)
+    assert rc == EWORKSPACE and "lane_state" in lib.vct_last_error().decode()
+    rc = lib.vct_trace_backward_saved(ctypes.byref(g), fake, ctypes.byref(gb), ctypes.byref(p), fake, 1 << 20, fake,
+                                      fake, fake, 16, None)
+    assert rc == EWORKSPACE and "workspace" in lib.vct_last_error().decode()

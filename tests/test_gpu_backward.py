@@ -150,3 +150,47 @@ def test_kernel_events_time_each_backward_kernel():
     # the registration is consumed: the next call records nothing and still works
     gb2 = vct.trace_backward(pyr, grid, dev(w.pos_rough), dev(w.normal), dev(w.cam_pos), w.params, dev(gout))
     assert torch.equal(gb, gb2)
+
+
+def _saved_vs_recompute(base, n, pr, nr, cam, params, gout, dtype="f32"):
+    g = vct.Grid(n, dtype=dtype)
+    pyr = vct.build_mips(dev(base), g)
+    t = (dev(pr), dev(nr), dev(cam))
+    out, state = vct.trace_save(pyr, g, *t, params)
+    saved = vct.trace_backward_saved(pyr, g, *t, params, state, dev(gout))
+    plain = vct.trace_backward(pyr, g, *t, params, dev(gout))
+    fwd = vct.trace(pyr, g, *t, params)
+    torch.cuda.synchronize()
+    assert torch.equal(saved, plain)
+    assert saved.abs().max() > 0
+    return out.cpu().numpy(), fwd.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_saved_state_backward_equals_recompute_and_forward_matches_oracle(dtype):
+    """trace_save + trace_backward_saved give the gradient of trace_backward bit
+    for bit; the saved forward's output meets the forward's parity bar."""
+    from tests.parity import fmt, range_errors, worst
+    w, g, gout = _case_fd()
+    out, fwd = _saved_vs_recompute(g, w.n, w.pos_rough, w.normal, w.cam_pos, w.params, gout, dtype)
+    if dtype == "f32":
+        ref, info = oracle.render(g, w.pos_rough, w.normal, w.cam_pos, w.params, return_info=True)
+        e = range_errors(out, ref, ~info["ambiguous"].reshape(-1))
+        print(f"trace_save c3fd: {fmt(e)}", flush=True)
+        assert worst(e)[0] <= 1e-5
+    e = range_errors(out, fwd)
+    assert worst(e)[0] <= 1e-5
+
+
+def test_saved_state_backward_random_ragged_and_full_launch():
+    n = 32
+    rng = np.random.default_rng(15)
+    a = rng.uniform(0, 0.25, size=(n, n, n, 1))
+    base = np.concatenate([rng.uniform(0, 1, size=(n, n, n, 3)) * a, a], -1).astype(np.float32)
+    pr, nr, cam = random_gbuffer(2, 21, 37, seed=16, n=n)
+    d, wt = cone_set("five")
+    p = ConeParams(d, wt, alpha_thresh=0.95, light_pos=(0.2, 0.7, 0.4))
+    _saved_vs_recompute(base, n, pr, nr, cam, p, rng.normal(size=(2, 21, 37, 8)).astype(np.float32))
+    w = workload("c3gt")
+    gout = (rng.normal(size=w.shape + (8,)) * 1e-2).astype(np.float32)
+    _saved_vs_recompute(w.base, w.n, w.pos_rough, w.normal, w.cam_pos, w.params, gout)
