@@ -118,9 +118,9 @@ __global__ __launch_bounds__(kThreads) void k_bwd_scale(const float* __restrict_
 }
 
 // Cross-lane moves of the reduction butterfly.  Each pairs lane i with
-// i ^ mask: row_mirror (^15) and row_half_mirror (^7) and quad permutes (^2,
-// ^1) are DPP modifiers of ordinary VALU instructions; ^16 is a ds_swizzle in
-// bitmask mode and ^32 a single bpermute.
+// i ^ mask: row_mirror (^15), row_half_mirror (^7) and the quad permutes (^2,
+// ^1) are DPP modifiers of ordinary VALU instructions; ^16 and ^32 are the
+// permlane16 / permlane32 swaps of gfx950.
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
@@ -129,115 +129,161 @@ constexpr int kDppXor15 = 0x140;   // row_mirror
 constexpr int kDppXor7 = 0x141;    // row_half_mirror
 constexpr int kDppXor2 = 0x4E;     // quad_perm [2,3,0,1]
 constexpr int kDppXor1 = 0xB1;     // quad_perm [1,0,3,2]
-__device__ __forceinline__ float swz_xor16(float v) {
-    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+
+// Given lo and hi, lanes with bit 4 clear return lo[i] + lo[i ^ 16] and lanes
+// with bit 4 set hi[i ^ 16] + hi[i] (the swap exchanges the odd 16-lane rows
+// of its first operand with the even rows of its second).
+__device__ __forceinline__ float split16(float lo, float hi) {
+    const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+// v[i] + v[i ^ 16] and v[i] + v[i ^ 32] in every lane.
+__device__ __forceinline__ float sum16(float v) { return split16(v, v); }
+__device__ __forceinline__ float sum32(float v) {
+    const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
 }
 
-// After xpose_sum32, lanes 0..31 hold the sums of value index
-// xpose_index(lane) (lanes j and j + 32 hold the same sum).
-__device__ __forceinline__ int xpose_index(int lane) {
-    return ((lane >> 3) & 1) * 16 + ((lane >> 2) & 1) * 8 + ((lane >> 1) & 1) * 4 + (lane & 1) * 2 +
-           ((lane >> 4) & 1);
+// Role of a lane in the tap-gradient butterfly.  The 32 values of a sample
+// are w[q] * g[c] (tap q = 4 z + 2 y + x, channel c).  Lane i keeps the value
+// (q, c) in register slot 4 (q ^ qm) + (c ^ cm), where every bit of the masks
+// is the parity of a set of lane bits: z = i3, y = i2 ^ i3, x = i1 ^ i2 and
+// channel bit 1 = i0 ^ i2.  Each of these parities flips under the lane mask
+// of the butterfly stage that splits on its bit (15, 7, 2, 1) and under no
+// earlier or later stage, so partners always hold the same value in the same
+// slot and every stage adds the partner's upper half to the own lower half,
+// with no per-lane selects.  The final split (^16) is a permlane16 swap, after
+// which lane i holds tap qm, channel cm + i4; lanes i and i ^ 32 agree.
+struct EmitLane {
+    bool xf, yf, zf;        // tap bits of the sum this lane ends with
+    bool cf;                // channel bit 1 of that sum
+    uint32_t xm, ym, zm;    // all-ones where xf / yf / zf
+    int ch;                 // channel of that sum
+};
+
+__device__ __forceinline__ EmitLane emit_lane(int lane) {
+    const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1, b4 = (lane >> 4) & 1;
+    EmitLane e;
+    e.zf = b3;
+    e.yf = b2 ^ b3;
+    e.xf = b1 ^ b2;
+    e.cf = b0 ^ b2;
+    e.xm = e.xf ? ~0u : 0u;
+    e.ym = e.yf ? ~0u : 0u;
+    e.zm = e.zf ? ~0u : 0u;
+    e.ch = (b0 ^ b2) * 2 + b4;
+    return e;
 }
 
-// Butterfly step: pair lanes by `mask`; the lane whose `up` bit is set keeps
-// the upper half of its values, its partner the lower half.
-template <int N, typename X>
-__device__ __forceinline__ void halve(float* r, bool up, X xmove) {
+// Sum over the wave of w[q] * g[c] for this lane's (q, c) (see EmitLane):
+// wp = the lane's weights in slot order, wpart[k] = wp[k + 4] of the ^15
+// partner, g = the lane's gradient in slot order (zero outside the group).
+// 4 DPP moves, 32 multiply-adds, 14 DPP adds and two permlane swaps; the
+// addition order is fixed, so the sums are reproducible.
+__device__ __forceinline__ float bfly32(const float wp[8], const float wpart[4], const float g[4]) {
+    float gpart[4];
 #pragma unroll
-    for (int i = 0; i < N / 2; ++i) {
-        float keep = up ? r[N / 2 + i] : r[i];
-        float send = up ? r[i] : r[N / 2 + i];
-        r[i] = keep + xmove(send);
-    }
-}
-
-// Sum over the lanes with `in` set of the 32 values w[q] * g[ch] (index
-// 4q + ch), transposed across the wave: 16 + 8 + 4 + 2 DPP moves, one swizzle
-// and one bpermute.  The masks 15, 7, 2, 1, 16, 32 each flip only bits not
-// yet used to split the values, so partners always hold the same indices;
-// the addition order is fixed, so the sums are reproducible.
-__device__ __forceinline__ float xpose_sum32(const float w[8], const float g[4], bool in, int lane) {
+    for (int m = 0; m < 4; ++m) gpart[m] = dpp<kDppXor15>(g[m]);
     float r[16];
-    {
-        // First split is on the tap's z bit (value index bit 4): a lane with
-        // lane bit 3 set keeps taps 4..7, so it swaps tap q with q + 4 up front
-        // instead of selecting among the 32 products.
-        const bool up = (lane & 8) != 0;
-        float wk[4], ws[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float a = in ? w[q] : 0.f, b = in ? w[q + 4] : 0.f;
-            wk[q] = up ? b : a;
-            ws[q] = up ? a : b;
-        }
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) r[i] = ws[i >> 2] * g[i & 3];
+        for (int m = 0; m < 4; ++m) r[4 * k + m] = __builtin_fmaf(wp[k], g[m], wpart[k] * gpart[m]);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) r[i] = __builtin_fmaf(wk[i >> 2], g[i & 3], dpp<kDppXor15>(r[i]));
-    }
-    halve<16>(r, (lane & 4) != 0, [](float v) { return dpp<kDppXor7>(v); });
-    halve<8>(r, (lane & 2) != 0, [](float v) { return dpp<kDppXor2>(v); });
-    halve<4>(r, (lane & 1) != 0, [](float v) { return dpp<kDppXor1>(v); });
-    halve<2>(r, (lane & 16) != 0, [](float v) { return swz_xor16(v); });
-    return r[0] + __shfl_xor(r[0], 32);
+    for (int i = 0; i < 8; ++i) r[i] += dpp<kDppXor7>(r[i + 8]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[i] += dpp<kDppXor2>(r[i + 4]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) r[i] += dpp<kDppXor1>(r[i + 2]);
+    return sum32(split16(r[0], r[1]));
 }
 
-// Alpha-only variant (occlusion cones carry no colour gradient): the sum over
-// the lanes with `in` set of w[q] * ga for the 8 taps.  Lanes with bits 0, 4, 5
-// clear end with the sum of tap 4 b3 + 2 b2 + b1.
-__device__ __forceinline__ float xpose_sum8(const float w[8], float ga, bool in, int lane) {
+// Alpha-only variant (occlusion cones carry no colour gradient): the sum of
+// w[q] * ga for q = qm; lanes with bits 0, 4 and 5 clear emit it.
+__device__ __forceinline__ float bfly8(const float wp[8], const float wpart[4], float g) {
+    const float gpart = dpp<kDppXor15>(g);
     float r[4];
-    {
-        const bool up = (lane & 8) != 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float a = in ? w[q] * ga : 0.f, b = in ? w[q + 4] * ga : 0.f;
-            r[q] = (up ? b : a) + dpp<kDppXor15>(up ? a : b);
-        }
-    }
-    halve<4>(r, (lane & 4) != 0, [](float v) { return dpp<kDppXor7>(v); });
-    halve<2>(r, (lane & 2) != 0, [](float v) { return dpp<kDppXor2>(v); });
-    float x = r[0] + dpp<kDppXor1>(r[0]);
-    x += swz_xor16(x);
-    return x + __shfl_xor(x, 32);
+    for (int k = 0; k < 4; ++k) r[k] = __builtin_fmaf(wp[k], g, wpart[k] * gpart);
+    r[0] += dpp<kDppXor7>(r[2]);
+    r[1] += dpp<kDppXor7>(r[3]);
+    r[0] += dpp<kDppXor2>(r[1]);
+    r[0] += dpp<kDppXor1>(r[0]);
+    return sum32(sum16(r[0]));
+}
+
+// Base texel, per-axis index steps and the lane's slot-ordered weights of one
+// level's 8 taps (level weight wl folded in).  An axis that clamps has step 0:
+// its two taps are the same texel and both carry their own weight.
+__device__ __forceinline__ void emit_taps(const LevelTable& T, int l, df Ux, df Uy, df Uz, float wl, const EmitLane& e,
+                                          uint32_t& base, uint32_t d[3], float wp[8]) {
+    const int nl = T.n[l];
+    const int lnb = T.lnb[l];
+    const float sc = __int_as_float((127 - l) << 23);   // 2^-l
+    const Axis ax = axis_taps(Ux, sc, nl);
+    const Axis ay = axis_taps(Uy, sc, nl);
+    const Axis az = axis_taps(Uz, sc, nl);
+    // brick layout: ((bz * nb + by) * nb + bx) * 64 + (z & 3) * 16 + (y & 3) * 4 + (x & 3), nb = 2^lnb
+    const uint32_t cx0 = ((ax.i0 >> 2) << 6) | (ax.i0 & 3), cx1 = ((ax.i1 >> 2) << 6) | (ax.i1 & 3);
+    const uint32_t cy0 = ((ay.i0 >> 2) << (6 + lnb)) | ((ay.i0 & 3) << 2);
+    const uint32_t cy1 = ((ay.i1 >> 2) << (6 + lnb)) | ((ay.i1 & 3) << 2);
+    const uint32_t cz0 = ((az.i0 >> 2) << (6 + 2 * lnb)) | ((az.i0 & 3) << 4);
+    const uint32_t cz1 = ((az.i1 >> 2) << (6 + 2 * lnb)) | ((az.i1 & 3) << 4);
+    base = T.off[l] + cx0 + cy0 + cz0;
+    d[0] = cx1 - cx0;
+    d[1] = cy1 - cy0;
+    d[2] = cz1 - cz0;
+    // per-axis weights (i0, i1), swapped where the lane's slot order flips the axis
+    const float x0 = 1.0f - ax.w1, y0 = 1.0f - ay.w1, z0 = 1.0f - az.w1;
+    const float xa = e.xf ? ax.w1 : x0, xb = e.xf ? x0 : ax.w1;
+    const float ya = e.yf ? ay.w1 : y0, yb = e.yf ? y0 : ay.w1;
+    const float za = e.zf ? az.w1 : z0, zb = e.zf ? z0 : az.w1;
+    const float wxy[4] = {xa * ya, xb * ya, xa * yb, xb * yb};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) wp[k] = wl * (wxy[k & 3] * ((k >> 2) ? zb : za));
 }
 
 // Emit one level's tap gradients of the wave.  Lanes whose samples share the
-// same (level, base texel) have the same 8 taps; each such group is summed
-// across the wave (fixed order) and 32 lanes then add its 8 taps x 4 channels
-// as fixed-point integers: to the workgroup's LDS table for the coarse levels
-// (side <= 8), to the global accumulator otherwise.
+// same base texel and clamp pattern have the same 8 taps; each such group is
+// summed across the wave (fixed order) and 32 lanes (8 for alpha only) then
+// add its taps x channels as fixed-point integers: to the workgroup's LDS
+// table for the coarse levels (side <= 8), to the global accumulator otherwise.
 template <bool ALPHA_ONLY>
 __device__ __forceinline__ void emit_level(bool live, const LevelTable& T, int level, df Ux, df Uy, df Uz, float wl,
-                                           const float g[4], int E, unsigned long long* __restrict__ acc,
-                                           unsigned long long* small, uint32_t small_off, int lane) {
-    Taps tp;
-    level_taps(T, level, Ux, Uy, Uz, tp);
-    float w[8];
-    folded_weights(tp, wl, w);
-    // The 8 taps are fixed by the base texel together with which axes clamp
-    // (a clamped axis repeats the base texel instead of stepping to i0 + 1).
-    const uint32_t key = live ? tp.idx[0] : 0xffffffffu;
-    const int kcl = tp.clamp;
-    unsigned long long mask = __ballot(live);
-    const int j = ALPHA_ONLY ? (((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1)) : xpose_index(lane);
-    const int tq = ALPHA_ONLY ? j : (j >> 2), ch = ALPHA_ONLY ? 3 : (j & 3);
+                                           const float gs[4], const EmitLane& e, int E,
+                                           unsigned long long* __restrict__ acc, unsigned long long* small,
+                                           uint32_t small_off, int lane) {
+    uint32_t base, d[3];
+    float wp[8];
+    emit_taps(T, level, Ux, Uy, Uz, wl, e, base, d, wp);
+    float wpart[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wpart[k] = dpp<kDppXor15>(wp[k + 4]);
+    const uint32_t key = live ? base : 0xffffffffu;
+    const int kcl = (d[0] == 0 ? 1 : 0) | (d[1] == 0 ? 2 : 0) | (d[2] == 0 ? 4 : 0);
     const bool emitter = ALPHA_ONLY ? ((lane & 0x31) == 0) : (lane < 32);
+    const int ch = ALPHA_ONLY ? 3 : e.ch;
+    unsigned long long mask = __ballot(live);
     while (mask) {
         const int leader = __builtin_ctzll(mask);
         const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
         const int kc = __builtin_amdgcn_readlane(kcl, leader);
         const bool in = live && key == k && kcl == kc;
         const unsigned long long gm = __ballot(in);
-        const float sum = ALPHA_ONLY ? xpose_sum8(w, g[3], in, lane) : xpose_sum32(w, g, in, lane);
-        const int lev = __builtin_amdgcn_readlane(level, leader);
-        uint32_t idx = 0;
+        float sum;
+        if (ALPHA_ONLY) {
+            sum = bfly8(wp, wpart, in ? gs[3] : 0.f);
+        } else {
+            float g[4];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            uint32_t iq = (uint32_t)__builtin_amdgcn_readlane((int)tp.idx[q], leader);
-            idx = tq == q ? iq : idx;
+            for (int m = 0; m < 4; ++m) g[m] = in ? gs[m] : 0.f;
+            sum = bfly32(wp, wpart, g);
         }
+        const int lev = __builtin_amdgcn_readlane(level, leader);
+        const uint32_t dx = (uint32_t)__builtin_amdgcn_readlane((int)d[0], leader);
+        const uint32_t dy = (uint32_t)__builtin_amdgcn_readlane((int)d[1], leader);
+        const uint32_t dz = (uint32_t)__builtin_amdgcn_readlane((int)d[2], leader);
+        const uint32_t idx = k + (dx & e.xm) + (dy & e.ym) + (dz & e.zm);
         const long long qv = emitter ? fixed_point(sum, E - 3 * lev) : 0;
         VCT_CHECK_ACC(idx);
         if (qv != 0 && idx >= small_off) atomicAdd(&small[(idx - small_off) * 4 + ch], (unsigned long long)qv);
@@ -268,6 +314,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_bwd_pass2(TraceArgs a, const fl
     const size_t pix = inb ? ((size_t)view * a.h + y) * a.w + x : 0;
     const bool valid = inb && a.normal[pix].w != 0.0f;
     const int nslots = a.n_diffuse + 2;
+    const EmitLane e = emit_lane(lane);
     for (int slot = 0; slot < nslots; ++slot) {
         if (!slot_enabled(a, slot)) continue;
         Pass2Lane L;
@@ -287,13 +334,18 @@ __global__ __launch_bounds__(kThreads, 4) void k_bwd_pass2(TraceArgs a, const fl
             Pass2Step st = {};
             if (live) pass2_step<DT>(a, T, L, k, st);
             if (occ) {
-                emit_level<true>(live, T, st.l0, st.Ux, st.Uy, st.Uz, 1.0f - st.f, st.g, E, acc, s_small, small_off, lane);
-                emit_level<true>(live && st.f > 0.0f, T, st.l1, st.Ux, st.Uy, st.Uz, st.f, st.g, E, acc, s_small,
+                emit_level<true>(live, T, st.l0, st.Ux, st.Uy, st.Uz, 1.0f - st.f, st.g, e, E, acc, s_small, small_off,
+                                 lane);
+                emit_level<true>(live && st.f > 0.0f, T, st.l1, st.Ux, st.Uy, st.Uz, st.f, st.g, e, E, acc, s_small,
                                  small_off, lane);
             } else {
-                emit_level<false>(live, T, st.l0, st.Ux, st.Uy, st.Uz, 1.0f - st.f, st.g, E, acc, s_small, small_off,
+                // gradient in the lane's slot order (channel bit 1 flipped where cf)
+                float gs[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) gs[m] = e.cf ? st.g[m ^ 2] : st.g[m];
+                emit_level<false>(live, T, st.l0, st.Ux, st.Uy, st.Uz, 1.0f - st.f, gs, e, E, acc, s_small, small_off,
                                   lane);
-                emit_level<false>(live && st.f > 0.0f, T, st.l1, st.Ux, st.Uy, st.Uz, st.f, st.g, E, acc, s_small,
+                emit_level<false>(live && st.f > 0.0f, T, st.l1, st.Ux, st.Uy, st.Uz, st.f, gs, e, E, acc, s_small,
                                   small_off, lane);
             }
         }

@@ -286,24 +286,6 @@ __device__ __forceinline__ void pass2_step(const TraceArgs& a, const LevelTable&
     L.t = df_add(L.t, a.step_factor * d);
 }
 
-// Tap weights of one level scaled by the level weight, with the taps of a
-// clamped axis (both on the same texel) folded into the first one.
-__device__ __forceinline__ void folded_weights(const Taps& tp, float wl, float w[8]) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) w[q] = wl * tp.w[q];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        if (tp.clamp & (1 << ax)) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (q & (1 << ax)) {
-                    w[q - (1 << ax)] += w[q];
-                    w[q] = 0.f;
-                }
-        }
-    }
-}
-
 // round(v * 2^e) as a 64-bit integer.
 __device__ __forceinline__ long long fixed_point(float v, int e) { return (long long)rintf(ldexpf(v, e)); }
 
