@@ -212,32 +212,14 @@ __device__ __forceinline__ float bfly8(const float wp[8], const float wpart[4], 
     return sum32(sum16(r[0]));
 }
 
-// Base texel, per-axis index steps and the lane's slot-ordered weights of one
-// level's 8 taps (level weight wl folded in).  An axis that clamps has step 0:
-// its two taps are the same texel and both carry their own weight.
-__device__ __forceinline__ void emit_taps(const LevelTable& T, int l, df Ux, df Uy, df Uz, float wl, const EmitLane& e,
-                                          uint32_t& base, uint32_t d[3], float wp[8]) {
-    const int nl = T.n[l];
-    const int lnb = T.lnb[l];
-    const float sc = __int_as_float((127 - l) << 23);   // 2^-l
-    const Axis ax = axis_taps(Ux, sc, nl);
-    const Axis ay = axis_taps(Uy, sc, nl);
-    const Axis az = axis_taps(Uz, sc, nl);
-    // brick layout: ((bz * nb + by) * nb + bx) * 64 + (z & 3) * 16 + (y & 3) * 4 + (x & 3), nb = 2^lnb
-    const uint32_t cx0 = ((ax.i0 >> 2) << 6) | (ax.i0 & 3), cx1 = ((ax.i1 >> 2) << 6) | (ax.i1 & 3);
-    const uint32_t cy0 = ((ay.i0 >> 2) << (6 + lnb)) | ((ay.i0 & 3) << 2);
-    const uint32_t cy1 = ((ay.i1 >> 2) << (6 + lnb)) | ((ay.i1 & 3) << 2);
-    const uint32_t cz0 = ((az.i0 >> 2) << (6 + 2 * lnb)) | ((az.i0 & 3) << 4);
-    const uint32_t cz1 = ((az.i1 >> 2) << (6 + 2 * lnb)) | ((az.i1 & 3) << 4);
-    base = T.off[l] + cx0 + cy0 + cz0;
-    d[0] = cx1 - cx0;
-    d[1] = cy1 - cy0;
-    d[2] = cz1 - cz0;
-    // per-axis weights (i0, i1), swapped where the lane's slot order flips the axis
-    const float x0 = 1.0f - ax.w1, y0 = 1.0f - ay.w1, z0 = 1.0f - az.w1;
-    const float xa = e.xf ? ax.w1 : x0, xb = e.xf ? x0 : ax.w1;
-    const float ya = e.yf ? ay.w1 : y0, yb = e.yf ? y0 : ay.w1;
-    const float za = e.zf ? az.w1 : z0, zb = e.zf ? z0 : az.w1;
+// The lane's slot-ordered weights of one level's 8 taps, level weight wl
+// folded in (an axis that clamps has both taps on one texel, each with its
+// own weight).
+__device__ __forceinline__ void emit_weights(const LevelGeom& g, float wl, const EmitLane& e, float wp[8]) {
+    const float x0 = 1.0f - g.wx, y0 = 1.0f - g.wy, z0 = 1.0f - g.wz;
+    const float xa = e.xf ? g.wx : x0, xb = e.xf ? x0 : g.wx;
+    const float ya = e.yf ? g.wy : y0, yb = e.yf ? y0 : g.wy;
+    const float za = e.zf ? g.wz : z0, zb = e.zf ? z0 : g.wz;
     const float wxy[4] = {xa * ya, xb * ya, xa * yb, xb * yb};
 #pragma unroll
     for (int k = 0; k < 8; ++k) wp[k] = wl * (wxy[k & 3] * ((k >> 2) ? zb : za));
@@ -249,18 +231,16 @@ __device__ __forceinline__ void emit_taps(const LevelTable& T, int l, df Ux, df 
 // add its taps x channels as fixed-point integers: to the workgroup's LDS
 // table for the coarse levels (side <= 8), to the global accumulator otherwise.
 template <bool ALPHA_ONLY>
-__device__ __forceinline__ void emit_level(bool live, const LevelTable& T, int level, df Ux, df Uy, df Uz, float wl,
-                                           const float gs[4], const EmitLane& e, int E,
-                                           unsigned long long* __restrict__ acc, unsigned long long* small,
-                                           uint32_t small_off, int lane) {
-    uint32_t base, d[3];
+__device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, float wl, const float gs[4],
+                                           const EmitLane& e, int E, unsigned long long* __restrict__ acc,
+                                           unsigned long long* small, uint32_t small_off, int lane) {
     float wp[8];
-    emit_taps(T, level, Ux, Uy, Uz, wl, e, base, d, wp);
+    emit_weights(geo, wl, e, wp);
     float wpart[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) wpart[k] = dpp<kDppXor15>(wp[k + 4]);
-    const uint32_t key = live ? base : 0xffffffffu;
-    const int kcl = (d[0] == 0 ? 1 : 0) | (d[1] == 0 ? 2 : 0) | (d[2] == 0 ? 4 : 0);
+    const uint32_t key = live ? geo.base : 0xffffffffu;
+    const int kcl = (geo.dx == 0 ? 1 : 0) | (geo.dy == 0 ? 2 : 0) | (geo.dz == 0 ? 4 : 0);
     const bool emitter = ALPHA_ONLY ? ((lane & 0x31) == 0) : (lane < 32);
     const int ch = ALPHA_ONLY ? 3 : e.ch;
     unsigned long long mask = __ballot(live);
@@ -279,10 +259,10 @@ __device__ __forceinline__ void emit_level(bool live, const LevelTable& T, int l
             for (int m = 0; m < 4; ++m) g[m] = in ? gs[m] : 0.f;
             sum = bfly32(wp, wpart, g);
         }
-        const int lev = __builtin_amdgcn_readlane(level, leader);
-        const uint32_t dx = (uint32_t)__builtin_amdgcn_readlane((int)d[0], leader);
-        const uint32_t dy = (uint32_t)__builtin_amdgcn_readlane((int)d[1], leader);
-        const uint32_t dz = (uint32_t)__builtin_amdgcn_readlane((int)d[2], leader);
+        const int lev = __builtin_amdgcn_readlane(geo.level, leader);
+        const uint32_t dx = (uint32_t)__builtin_amdgcn_readlane((int)geo.dx, leader);
+        const uint32_t dy = (uint32_t)__builtin_amdgcn_readlane((int)geo.dy, leader);
+        const uint32_t dz = (uint32_t)__builtin_amdgcn_readlane((int)geo.dz, leader);
         const uint32_t idx = k + (dx & e.xm) + (dy & e.ym) + (dz & e.zm);
         const long long qv = emitter ? fixed_point(sum, E - 3 * lev) : 0;
         VCT_CHECK_ACC(idx);
@@ -334,19 +314,15 @@ __global__ __launch_bounds__(kThreads, 4) void k_bwd_pass2(TraceArgs a, const fl
             Pass2Step st = {};
             if (live) pass2_step<DT>(a, T, L, k, st);
             if (occ) {
-                emit_level<true>(live, T, st.l0, st.Ux, st.Uy, st.Uz, 1.0f - st.f, st.g, e, E, acc, s_small, small_off,
-                                 lane);
-                emit_level<true>(live && st.f > 0.0f, T, st.l1, st.Ux, st.Uy, st.Uz, st.f, st.g, e, E, acc, s_small,
-                                 small_off, lane);
+                emit_level<true>(live, st.g0, 1.0f - st.f, st.g, e, E, acc, s_small, small_off, lane);
+                emit_level<true>(live && st.f > 0.0f, st.g1, st.f, st.g, e, E, acc, s_small, small_off, lane);
             } else {
-                // gradient in the lane's slot order (channel bit 1 flipped where cf)
-                float gs[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) gs[m] = e.cf ? st.g[m ^ 2] : st.g[m];
-                emit_level<false>(live, T, st.l0, st.Ux, st.Uy, st.Uz, 1.0f - st.f, gs, e, E, acc, s_small, small_off,
-                                  lane);
-                emit_level<false>(live && st.f > 0.0f, T, st.l1, st.Ux, st.Uy, st.Uz, st.f, gs, e, E, acc, s_small,
-                                  small_off, lane);
+                // gradient in the lane's slot order (channel bit 1 flipped where cf);
+                // selects on values: an index select would move st to scratch memory
+                const float g0 = st.g[0], g1 = st.g[1], g2 = st.g[2], g3 = st.g[3];
+                const float gs[4] = {e.cf ? g2 : g0, e.cf ? g3 : g1, e.cf ? g0 : g2, e.cf ? g1 : g3};
+                emit_level<false>(live, st.g0, 1.0f - st.f, gs, e, E, acc, s_small, small_off, lane);
+                emit_level<false>(live && st.f > 0.0f, st.g1, st.f, gs, e, E, acc, s_small, small_off, lane);
             }
         }
     }

@@ -231,12 +231,65 @@ __device__ __forceinline__ void pass2_init(const TraceArgs& a, const PixelSetup&
     L.t = {a.t0, 0.0f};
 }
 
+// One level's 8 taps in factored form: base texel (tap 0), the index steps to
+// the +x / +y / +z neighbours (0 on an axis that clamps) and the per-axis
+// weights of the upper taps.
+struct LevelGeom {
+    uint32_t base, dx, dy, dz;
+    float wx, wy, wz;
+    int level;
+};
+
+__device__ __forceinline__ LevelGeom level_geom(const LevelTable& T, int l, df Ux, df Uy, df Uz) {
+    const int nl = T.n[l];
+    const int lnb = T.lnb[l];
+    const float sc = __int_as_float((127 - l) << 23);   // 2^-l
+    const Axis ax = axis_taps(Ux, sc, nl);
+    const Axis ay = axis_taps(Uy, sc, nl);
+    const Axis az = axis_taps(Uz, sc, nl);
+    // brick layout: ((bz * nb + by) * nb + bx) * 64 + (z & 3) * 16 + (y & 3) * 4 + (x & 3), nb = 2^lnb
+    const uint32_t cx0 = ((ax.i0 >> 2) << 6) | (ax.i0 & 3), cx1 = ((ax.i1 >> 2) << 6) | (ax.i1 & 3);
+    const uint32_t cy0 = ((ay.i0 >> 2) << (6 + lnb)) | ((ay.i0 & 3) << 2);
+    const uint32_t cy1 = ((ay.i1 >> 2) << (6 + lnb)) | ((ay.i1 & 3) << 2);
+    const uint32_t cz0 = ((az.i0 >> 2) << (6 + 2 * lnb)) | ((az.i0 & 3) << 4);
+    const uint32_t cz1 = ((az.i1 >> 2) << (6 + 2 * lnb)) | ((az.i1 & 3) << 4);
+    LevelGeom g;
+    g.base = T.off[l] + cx0 + cy0 + cz0;
+    g.dx = cx1 - cx0;
+    g.dy = cy1 - cy0;
+    g.dz = cz1 - cz0;
+    g.wx = ax.w1;
+    g.wy = ay.w1;
+    g.wz = az.w1;
+    g.level = l;
+    return g;
+}
+
+// The level's sample: the same taps, weights and products as level_taps +
+// gather of the forward, so the recomputed samples equal the forward's.
+template <int DT>
+__device__ __forceinline__ float4 gather_geom(const void* __restrict__ pyr, const LevelGeom& g) {
+    const float wx0 = 1.0f - g.wx, wy0 = 1.0f - g.wy, wz0 = 1.0f - g.wz;
+    const float wxy[4] = {wx0 * wy0, g.wx * wy0, wx0 * g.wy, g.wx * g.wy};
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t idx = g.base + ((q & 1) ? g.dx : 0u) + ((q & 2) ? g.dy : 0u) + ((q & 4) ? g.dz : 0u);
+        const float w = wxy[q & 3] * ((q & 4) ? g.wz : wz0);
+        float4 v = vct_load_texel<DT>(pyr, idx);
+        s.x = __builtin_fmaf(w, v.x, s.x);
+        s.y = __builtin_fmaf(w, v.y, s.y);
+        s.z = __builtin_fmaf(w, v.z, s.z);
+        s.w = __builtin_fmaf(w, v.w, s.w);
+    }
+    return s;
+}
+
 // Sample k of a pass-2 cone: its taps on one or two levels and the gradient
 // g = (dL/dc_k, dL/da_k) of the sample; advances the march.
 struct Pass2Step {
-    df Ux, Uy, Uz;    // sample position, level-0 texel units
-    int l0, l1;
-    float f;          // weight of level l1 (0: single level)
+    LevelGeom g0, g1;   // levels l0 and l1 (g1 only when f > 0)
+    float f;            // weight of level l1 (0: single level)
     float g[4];
 };
 
@@ -245,18 +298,16 @@ __device__ __forceinline__ void pass2_step(const TraceArgs& a, const LevelTable&
                                            Pass2Step& st) {
     const float d = fmaxf(L.c.two_tan * L.t.hi, a.voxel);
     const float lam = lod_of(a, d);
-    st.Ux = df_axis(L.c.Ox, L.t, L.c.Wx);
-    st.Uy = df_axis(L.c.Oy, L.t, L.c.Wy);
-    st.Uz = df_axis(L.c.Oz, L.t, L.c.Wz);
-    st.l0 = (int)lam;
-    st.f = lam - (float)st.l0;
-    st.l1 = min(st.l0 + 1, a.levels - 1);
-    Taps tp;
-    level_taps(T, st.l0, st.Ux, st.Uy, st.Uz, tp);
-    float4 s = gather<DT>(a.pyr, tp);
+    const df Ux = df_axis(L.c.Ox, L.t, L.c.Wx);
+    const df Uy = df_axis(L.c.Oy, L.t, L.c.Wy);
+    const df Uz = df_axis(L.c.Oz, L.t, L.c.Wz);
+    const int l0 = (int)lam;
+    st.f = lam - (float)l0;
+    st.g0 = level_geom(T, l0, Ux, Uy, Uz);
+    float4 s = gather_geom<DT>(a.pyr, st.g0);
     if (st.f > 0.0f) {
-        level_taps(T, st.l1, st.Ux, st.Uy, st.Uz, tp);
-        float4 s1 = gather<DT>(a.pyr, tp);
+        st.g1 = level_geom(T, min(l0 + 1, a.levels - 1), Ux, Uy, Uz);
+        float4 s1 = gather_geom<DT>(a.pyr, st.g1);
         float gg = 1.0f - st.f;
         s.x = __builtin_fmaf(st.f, s1.x, gg * s.x);
         s.y = __builtin_fmaf(st.f, s1.y, gg * s.y);
