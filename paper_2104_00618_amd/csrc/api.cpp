@@ -134,6 +134,7 @@ TraceArgs make_args(const vct_grid* g, const PyrLayout& L, const void* pyr, cons
         }
     }
     a.pyr = pyr;
+    a.rsrc = vct_pyr_rsrc(pyr, g->dtype == VCT_F32 ? 16 : 8, (uint32_t)L.total_texels);
     a.b = gb->b;
     a.h = gb->h;
     a.w = gb->w;

@@ -311,7 +311,11 @@ __global__ __launch_bounds__(kThreads, 4) void k_bwd_pass2(TraceArgs a, const fl
         const bool occ = slot == a.n_diffuse + 1;
         for (int k = 0; k < Kw; ++k) {
             const bool live = k < L.K;
-            Pass2Step st = {};
+            // lanes past their K only need finite weights for the butterfly
+            Pass2Step st;
+            st.f = 0.f;
+            st.g0.wx = st.g0.wy = st.g0.wz = 0.f;
+            st.g1.wx = st.g1.wy = st.g1.wz = 0.f;
             if (live) pass2_step<DT>(a, T, L, k, st);
             if (occ) {
                 emit_level<true>(live, st.g0, 1.0f - st.f, st.g, e, E, acc, s_small, small_off, lane);

@@ -241,12 +241,12 @@ struct LevelGeom {
 };
 
 __device__ __forceinline__ LevelGeom level_geom(const LevelTable& T, int l, df Ux, df Uy, df Uz) {
-    const int nl = T.n[l];
+    const float top = T.top[l];
     const int lnb = T.lnb[l];
     const float sc = __int_as_float((127 - l) << 23);   // 2^-l
-    const Axis ax = axis_taps(Ux, sc, nl);
-    const Axis ay = axis_taps(Uy, sc, nl);
-    const Axis az = axis_taps(Uz, sc, nl);
+    const Axis ax = axis_taps(Ux, sc, top);
+    const Axis ay = axis_taps(Uy, sc, top);
+    const Axis az = axis_taps(Uz, sc, top);
     // brick layout: ((bz * nb + by) * nb + bx) * 64 + (z & 3) * 16 + (y & 3) * 4 + (x & 3), nb = 2^lnb
     const uint32_t cx0 = ((ax.i0 >> 2) << 6) | (ax.i0 & 3), cx1 = ((ax.i1 >> 2) << 6) | (ax.i1 & 3);
     const uint32_t cy0 = ((ay.i0 >> 2) << (6 + lnb)) | ((ay.i0 & 3) << 2);
@@ -268,7 +268,7 @@ __device__ __forceinline__ LevelGeom level_geom(const LevelTable& T, int l, df U
 // The level's sample: the same taps, weights and products as level_taps +
 // gather of the forward, so the recomputed samples equal the forward's.
 template <int DT>
-__device__ __forceinline__ float4 gather_geom(const void* __restrict__ pyr, const LevelGeom& g) {
+__device__ __forceinline__ float4 gather_geom(const vct_v4i& rsrc, const LevelGeom& g) {
     const float wx0 = 1.0f - g.wx, wy0 = 1.0f - g.wy, wz0 = 1.0f - g.wz;
     const float wxy[4] = {wx0 * wy0, g.wx * wy0, wx0 * g.wy, g.wx * g.wy};
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -276,7 +276,7 @@ __device__ __forceinline__ float4 gather_geom(const void* __restrict__ pyr, cons
     for (int q = 0; q < 8; ++q) {
         const uint32_t idx = g.base + ((q & 1) ? g.dx : 0u) + ((q & 2) ? g.dy : 0u) + ((q & 4) ? g.dz : 0u);
         const float w = wxy[q & 3] * ((q & 4) ? g.wz : wz0);
-        float4 v = vct_load_texel<DT>(pyr, idx);
+        float4 v = vct_fetch_texel<DT>(rsrc, idx);
         s.x = __builtin_fmaf(w, v.x, s.x);
         s.y = __builtin_fmaf(w, v.y, s.y);
         s.z = __builtin_fmaf(w, v.z, s.z);
@@ -304,10 +304,10 @@ __device__ __forceinline__ void pass2_step(const TraceArgs& a, const LevelTable&
     const int l0 = (int)lam;
     st.f = lam - (float)l0;
     st.g0 = level_geom(T, l0, Ux, Uy, Uz);
-    float4 s = gather_geom<DT>(a.pyr, st.g0);
+    float4 s = gather_geom<DT>(a.rsrc, st.g0);
     if (st.f > 0.0f) {
         st.g1 = level_geom(T, min(l0 + 1, a.levels - 1), Ux, Uy, Uz);
-        float4 s1 = gather_geom<DT>(a.pyr, st.g1);
+        float4 s1 = gather_geom<DT>(a.rsrc, st.g1);
         float gg = 1.0f - st.f;
         s.x = __builtin_fmaf(st.f, s1.x, gg * s.x);
         s.y = __builtin_fmaf(st.f, s1.y, gg * s.y);
@@ -332,12 +332,13 @@ __device__ __forceinline__ void pass2_step(const TraceArgs& a, const LevelTable&
             float diff = (L.CK[ch].hi - L.C[ch].hi) + (L.CK[ch].lo - L.C[ch].lo);
             dot = __builtin_fmaf(L.gc[ch], diff, dot);
         }
-        st.g[3] = -tr * (dot - L.ga * L.TK) / tn;
+        st.g[3] = -tr * (dot - L.ga * L.TK) * __builtin_amdgcn_rcpf(tn);   // tn >= 2^-24: rcp is 1 ulp
     }
     L.t = df_add(L.t, a.step_factor * d);
 }
 
-// round(v * 2^e) as a 64-bit integer.
+// round(v * 2^e) as a 64-bit integer (float32 ops only: the float64 units of
+// gfx950 run at a fraction of the float32 rate).
 __device__ __forceinline__ long long fixed_point(float v, int e) { return (long long)rintf(ldexpf(v, e)); }
 
 }  // namespace vct

@@ -77,7 +77,7 @@ __device__ __forceinline__ float3 normalize3(float x, float y, float z) {
 
 // Shared-memory copy of the level table (per-lane levels index it).
 struct LevelTable {
-    int32_t n[VCT_MAX_LEVELS];
+    float top[VCT_MAX_LEVELS];       // index of the last texel per axis (side - 1), as a float
     int32_t lnb[VCT_MAX_LEVELS];     // log2 of bricks per axis
     uint32_t off[VCT_MAX_LEVELS];
 };
@@ -86,7 +86,7 @@ __device__ __forceinline__ void load_level_table(const TraceArgs& a, LevelTable*
 #pragma unroll
     for (int l = 0; l < VCT_MAX_LEVELS; ++l)
         if ((int)threadIdx.x == l) {
-            t->n[l] = a.lv[l].n;
+            t->top[l] = (float)(a.lv[l].n - 1);
             t->lnb[l] = 31 - __builtin_clz(a.lv[l].nb);
             t->off[l] = a.lv[l].off;
         }
@@ -98,18 +98,19 @@ struct Axis {
     float w1;  // weight of i1; i0 gets 1 - w1
 };
 
-__device__ __forceinline__ Axis axis_taps(df U, float sc, int nl) {
+__device__ __forceinline__ Axis axis_taps(df U, float sc, float top) {
     float u = U.hi * sc - 0.5f;          // exact: power-of-two scale, and u >= -1/4 whenever it matters
     float ulo = U.lo * sc;
     float fl = floorf(u);
     float ph = (u - fl) + ulo;           // in (-1, 2): renormalise without branches
     float c = floorf(ph);
     ph -= c;
-    int i = (int)fl + (int)c;
-    i = min(max(i, -1), nl);             // keeps i + 1 from overflowing for far-away points
-    Axis a;                              // clamp-to-edge: both taps inside [0, nl - 1]
-    a.i0 = min(max(i, 0), nl - 1);
-    a.i1 = min(max(i + 1, 0), nl - 1);
+    // clamp-to-edge in float before converting: both taps inside [0, top]; an
+    // integer-valued fi is exact below 2^24 and clamps to an edge above
+    const float fi = fl + c;
+    Axis a;
+    a.i0 = (int)__builtin_amdgcn_fmed3f(fi, 0.0f, top);
+    a.i1 = (int)__builtin_amdgcn_fmed3f(fi + 1.0f, 0.0f, top);
     a.w1 = ph;
     return a;
 }
@@ -122,13 +123,13 @@ struct Taps {
 
 // The 8 taps and trilinear weights of level l at texel-space position U (level-0 texels).
 __device__ __forceinline__ void level_taps(const LevelTable& T, int l, df Ux, df Uy, df Uz, Taps& tp) {
-    const int nl = T.n[l];
+    const float top = T.top[l];
     const int lnb = T.lnb[l];
     const uint32_t off = T.off[l];
     const float sc = __int_as_float((127 - l) << 23);   // 2^-l
-    Axis ax = axis_taps(Ux, sc, nl);
-    Axis ay = axis_taps(Uy, sc, nl);
-    Axis az = axis_taps(Uz, sc, nl);
+    Axis ax = axis_taps(Ux, sc, top);
+    Axis ay = axis_taps(Uy, sc, top);
+    Axis az = axis_taps(Uz, sc, top);
     const float wx0 = 1.0f - ax.w1, wy0 = 1.0f - ay.w1, wz0 = 1.0f - az.w1;
     tp.clamp = (ax.i0 == ax.i1 ? 1 : 0) | (ay.i0 == ay.i1 ? 2 : 0) | (az.i0 == az.i1 ? 4 : 0);
     // brick layout: ((bz * nb + by) * nb + bx) * 64 + (z & 3) * 16 + (y & 3) * 4 + (x & 3), nb = 2^lnb
@@ -147,11 +148,11 @@ __device__ __forceinline__ void level_taps(const LevelTable& T, int l, df Ux, df
 }
 
 template <int DT>
-__device__ __forceinline__ float4 gather(const void* __restrict__ pyr, const Taps& tp) {
+__device__ __forceinline__ float4 gather(const vct_v4i& rsrc, const Taps& tp) {
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        float4 v = vct_load_texel<DT>(pyr, tp.idx[q]);
+        float4 v = vct_fetch_texel<DT>(rsrc, tp.idx[q]);
         s.x = __builtin_fmaf(tp.w[q], v.x, s.x);
         s.y = __builtin_fmaf(tp.w[q], v.y, s.y);
         s.z = __builtin_fmaf(tp.w[q], v.z, s.z);
@@ -277,11 +278,11 @@ __device__ __forceinline__ float4 sample_at(const TraceArgs& a, const LevelTable
     float f = lam - (float)l0;
     Taps tp;
     level_taps(T, l0, Ux, Uy, Uz, tp);
-    float4 s0 = gather<DT>(a.pyr, tp);
+    float4 s0 = gather<DT>(a.rsrc, tp);
     if (f > 0.0f) {
         int l1 = min(l0 + 1, a.levels - 1);
         level_taps(T, l1, Ux, Uy, Uz, tp);
-        float4 s1 = gather<DT>(a.pyr, tp);
+        float4 s1 = gather<DT>(a.rsrc, tp);
         float g = 1.0f - f;
         s0.x = __builtin_fmaf(f, s1.x, g * s0.x);
         s0.y = __builtin_fmaf(f, s1.y, g * s0.y);

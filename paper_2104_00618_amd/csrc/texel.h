@@ -7,6 +7,36 @@
 #include "vct.h"
 
 typedef _Float16 vct_half4 __attribute__((ext_vector_type(4)));
+typedef int32_t vct_v4i __attribute__((ext_vector_type(4)));
+typedef int32_t vct_v2i __attribute__((ext_vector_type(2)));
+typedef float vct_v4f __attribute__((ext_vector_type(4)));
+
+// Buffer resource (V#) words of a structured buffer over the pyramid: one
+// record of `texel_bytes` per texel and `n_texels` records, so a load takes the
+// 32-bit texel index and the hardware forms the 64-bit address; an index past
+// the last record reads as zero.  Word 3 is the untyped 32-bit data format of
+// the CDNA buffer descriptor.
+inline vct_v4i vct_pyr_rsrc(const void* pyr, int texel_bytes, uint32_t n_texels) {
+    const uint64_t base = (uint64_t)(uintptr_t)pyr;
+    vct_v4i r;
+    r.x = (int32_t)(uint32_t)base;
+    r.y = (int32_t)((uint32_t)(base >> 32) & 0xffffu) | (texel_bytes << 16);
+    r.z = (int32_t)n_texels;
+    r.w = 0x00020000;
+    return r;
+}
+
+#ifndef VCT_HOST_EMULATION
+// buffer_load_dwordx4 / _dwordx2 with idxen (vindex = record index)
+__device__ vct_v4f vct_struct_load_v4f32(vct_v4i rsrc, int32_t vindex, int32_t voffset, int32_t soffset,
+                                         int32_t aux) __asm("llvm.amdgcn.struct.buffer.load.v4f32");
+__device__ vct_v2i vct_struct_load_v2i32(vct_v4i rsrc, int32_t vindex, int32_t voffset, int32_t soffset,
+                                         int32_t aux) __asm("llvm.amdgcn.struct.buffer.load.v2i32");
+#else
+// host-side verification builds supply these
+vct_v4f vct_struct_load_v4f32(vct_v4i rsrc, int32_t vindex, int32_t voffset, int32_t soffset, int32_t aux);
+vct_v2i vct_struct_load_v2i32(vct_v4i rsrc, int32_t vindex, int32_t voffset, int32_t soffset, int32_t aux);
+#endif
 
 // Index hook for host-side verification builds (empty in the library).
 #ifndef VCT_CHECK_TEXEL
@@ -33,6 +63,25 @@ __device__ __forceinline__ float4 vct_load_texel(const void* __restrict__ pyr, u
         uint2 v = reinterpret_cast<const uint2*>(pyr)[idx];
         return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
                            __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
+    }
+}
+
+// Texel `idx` through the pyramid's buffer resource.
+template <int DT>
+__device__ __forceinline__ float4 vct_fetch_texel(const vct_v4i& rsrc, uint32_t idx) {
+    VCT_CHECK_TEXEL(idx);
+    if constexpr (DT == VCT_F32) {
+        const vct_v4f v = vct_struct_load_v4f32(rsrc, (int32_t)idx, 0, 0, 0);
+        return make_float4(v.x, v.y, v.z, v.w);
+    } else if constexpr (DT == VCT_F16) {
+        const vct_v2i u = vct_struct_load_v2i32(rsrc, (int32_t)idx, 0, 0, 0);
+        vct_half4 h = __builtin_bit_cast(vct_half4, u);
+        return make_float4((float)h.x, (float)h.y, (float)h.z, (float)h.w);
+    } else {
+        const vct_v2i u = vct_struct_load_v2i32(rsrc, (int32_t)idx, 0, 0, 0);
+        const uint32_t x = (uint32_t)u.x, y = (uint32_t)u.y;
+        return make_float4(__uint_as_float(x << 16), __uint_as_float(x & 0xffff0000u), __uint_as_float(y << 16),
+                           __uint_as_float(y & 0xffff0000u));
     }
 }
 

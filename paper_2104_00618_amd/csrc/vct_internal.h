@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "texel.h"
 #include "vct.h"
 
 #define VCT_MAX_LEVELS 11   // N <= 1024
@@ -89,6 +90,7 @@ struct TraceArgs {
     float voxel;                   // extent / N (world size of a base texel)
     LevelInfo lv[VCT_MAX_LEVELS];
     const void* pyr;
+    vct_v4i rsrc;                  // structured buffer resource over pyr (one record per texel)
     // G-buffer
     int32_t b, h, w;
     int32_t tiles_x, tiles_y, n_tiles;   // 16x16-pixel tiles
