@@ -17,6 +17,7 @@ float16-storage forward for comparison.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -54,6 +55,35 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the float16-storage forward comparison")
     return ap.parse_args()
+
+
+# Sources that define the scatter pass; HBM traffic measured by rocprofv3 is
+# reported only while their digest matches the one recorded with the counters.
+PASS2_SOURCES = ["backward.hip", "bwd_pixel.h", "march.h", "texel.h", "vct_internal.h"]
+PROFILE = os.path.join(ROOT, "profiles", "cone_trace_256cubed_1080p_f32.md")
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PASS2_SOURCES:
+        with open(os.path.join(ROOT, "paper_2104_00618_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_pass2_traffic():
+    """(bytes per launch, note) from the committed profile, or (None, reason)."""
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None, "no profile"
+    m = re.search(r"traffic k_bwd_pass2: fetch_bytes=(\d+) write_bytes=(\d+) sources=([0-9a-f]+)", text)
+    if not m:
+        return None, "no traffic line in the profile"
+    if m.group(3) != kernel_source_digest():
+        return None, "kernel sources changed since the counters were taken"
+    return int(m.group(1)) + int(m.group(2)), f"FETCH_SIZE + WRITE_SIZE (calibrated) from {os.path.basename(PROFILE)}"
 
 
 def log(msg):
@@ -216,9 +246,12 @@ def main():
     # dominant kernel of the step: the backward scatter pass (issue-bound VALU work)
     p2_ms = float(bwd_k[3])
     p2_tflops = FLOPS_BWD_SCATTER_SAMPLE * samples / (p2_ms * 1e-3) / 1e12
+    p2_traffic, p2_traffic_note = measured_pass2_traffic() if (args.dtype == "f32" and WORKLOAD == "c1") else (
+        None, "counters were taken on the float32 1080p workload only")
     roofline = {"kernel": "k_bwd_pass2 (re-march + deterministic tap-gradient scatter), one launch per step",
                 "bound": "alu", "achieved": p2_tflops, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": p2_tflops / ALU_PEAK_TFLOPS, "traffic": None, "launch_ms": p2_ms,
+                "frac": p2_tflops / ALU_PEAK_TFLOPS, "traffic": p2_traffic, "traffic_note": p2_traffic_note,
+                "launch_ms": p2_ms,
                 "flops_per_launch": FLOPS_BWD_SCATTER_SAMPLE * samples,
                 "flops_model": f"{FLOPS_BWD_SCATTER_SAMPLE} FP32 ops per cone sample x {samples} samples"}
     res = {
