@@ -198,9 +198,17 @@ def main():
         return e[0].elapsed_time(e[1]) / k
 
     fwd_ms = timed(lambda: vct.trace(pyr, grid, pr, nr, cam, w.params, out), args.steps)
+    # final shading with the thesis's cone variants (first-hit diffuse, occlusion
+    # falloff, angular-grace specular), one and three lights
+    from scenes import random_material, scene_lights
+    mat = T(random_material(w.shape, seed=11))
+    shade_out = torch.empty(w.shape + (4,), dtype=torch.float32, device=dev)
+    shade_ms = {f"{nl}_lights": timed(lambda nl=nl: vct.shade(pyr, grid, pr, nr, cam, mat, w.params, scene_lights(nl),
+                                                                shade_out), args.steps) for nl in (1, 3)}
     recompute_bwd_ms = timed(lambda: vct.trace_backward(pyr, grid, pr, nr, cam, w.params, gout, ws, gbase),
                              max(args.steps // 2, 1))
-    log(f"trace alone {fwd_ms:.3f} ms; recompute path step {mips_ms + fwd_ms + recompute_bwd_ms:.3f} ms")
+    log(f"trace alone {fwd_ms:.3f} ms; recompute path step {mips_ms + fwd_ms + recompute_bwd_ms:.3f} ms; "
+        f"shade {', '.join(f'{k} {v:.3f} ms' for k, v in shade_ms.items())}")
 
     texel_bytes = 16 if args.dtype == "f32" else 8
     trace_bytes = samples * 16 * texel_bytes + npix * 64
@@ -208,7 +216,8 @@ def main():
     breakdown = {
         "build_mips_ms": mips_ms, "trace_save_ms": save_ms, "trace_backward_saved_ms": bwd_ms,
         "trace_backward_saved_kernels_ms": {n: float(t) for n, t in zip(BWD_KERNELS, bwd_k)},
-        "trace_ms": fwd_ms, "fwd_ms_per_frame": mips_ms + fwd_ms, "fwd_bwd_ms_per_frame": mips_ms + save_ms + bwd_ms,
+        "trace_ms": fwd_ms, "fwd_ms_per_frame": mips_ms + fwd_ms,
+        "shade_ms": shade_ms, "fwd_bwd_ms_per_frame": mips_ms + save_ms + bwd_ms,
         "recompute_path": {"trace_backward_ms": recompute_bwd_ms,
                            "fwd_bwd_ms_per_frame": mips_ms + fwd_ms + recompute_bwd_ms},
         "samples_per_frame": samples, "samples_per_pixel": samples / npix,

@@ -52,6 +52,7 @@ extern "C" {
 #define VCT_MAX_DIFFUSE 16
 #define VCT_MAX_N 1024
 #define VCT_MAX_STEPS (1 << 20) /* bound on max_dist / (step_factor * voxel size) */
+#define VCT_MAX_LIGHTS 8
 
 /* Storage type of the mip pyramid.  Sampling, compositing and gradients are
  * always float32; reduced-precision pyramids are rounded to nearest even. */
@@ -97,6 +98,30 @@ typedef struct {
     float max_dist;                              /* > 0: samples only at t <= max_dist */
     float alpha_thresh;                          /* > 0: samples only while accumulated alpha < alpha_thresh */
 } vct_cone_params;
+
+/* Lights, specular colour and cone-variant flags of the final shading pass
+ * (Section 5.4.4, "Cone Tracing": the modified occlusion, specular and
+ * diffuse cones of the implementation and the shading equation that combines
+ * them with a Lambert + Phong direct term per light). */
+typedef struct {
+    int32_t n_lights;                            /* 0..8; each light gets an occlusion cone */
+    float light_pos[VCT_MAX_LIGHTS][3];          /* point lights, world units */
+    float light_diffuse[VCT_MAX_LIGHTS][3];      /* i_d per light (rgb) */
+    float light_specular[VCT_MAX_LIGHTS][3];     /* i_s per light (rgb) */
+    float specular_color[3];                     /* c_s of the Phong term (rgb) */
+    int32_t diffuse_first_hit;                   /* nonzero: a diffuse cone stops at the first sample with
+                                                    alpha > first_hit_alpha and returns its colour */
+    float first_hit_alpha;                       /* in [0, 1); 0.01 in the thesis */
+    int32_t occlusion_falloff;                   /* nonzero: each occlusion sample's alpha is scaled by
+                                                    smoothstep(0, max_dist, sqrt(t) * shadow_strength) */
+    float shadow_strength;                       /* >= 0 */
+    int32_t specular_brdf;                       /* nonzero: the specular cone is weighted per light by
+                                                    (1 - max(0, gamma - grace * shininess) / pi)^falloff,
+                                                    gamma the angle between its axis and the light;
+                                                    zero: added once with weight 1 */
+    float grace_per_shininess;                   /* >= 0; 0.008 pi in the thesis */
+    float shininess_falloff;                     /* exponent q >= 0 */
+} vct_shade_params;
 
 /* Bytes of the opaque pyramid buffer for `grid` (host only, enqueues nothing).
  * Layout (informative): each level stored as 4^3-texel bricks in the storage
@@ -191,6 +216,25 @@ int vct_trace_backward_saved(const vct_grid* grid, const void* pyramid, const vc
                              const vct_cone_params* params, const void* lane_state, size_t lane_state_bytes,
                              const float* grad_out, float* grad_base, void* workspace, size_t workspace_bytes,
                              hipStream_t stream);
+
+/* Shaded radiance with the thesis's cone variants (Section 5.4.4, "Cone
+ * Tracing", the implemented shading equation):
+ *   L = o_min * sum_q w_q C_diff,q + sum_s f_spec,s C_spec
+ *       + sum_s V_s (c_d i_d,s max(0, L_s . N) + c_s i_s,s max(0, R_s . w)^shininess)
+ * with the u diffuse cones of `params` (first-hit or accumulated), one specular
+ * cone along the reflection axis (aperture roughness * spec_aperture_scale),
+ * one occlusion cone per light (aperture occ_aperture, t_max = min(max_dist,
+ * distance), with or without falloff), V_s = 1 - its alpha, o_min = min_s V_s
+ * (1 with no light), L_s the unit direction to light s, R_s = reflect(-L_s, N)
+ * and w the unit direction to the camera.  `params`'s light_pos and enable
+ * flags are not used here; its march parameters are.
+ *   material  device [b][h][w][4] = (c_d.r, c_d.g, c_d.b, shininess)
+ *   out       device [b][h][w][4] = (L.r, L.g, L.b, o_min), overwritten; 0 for background pixels
+ * Errors: VCT_EINVAL for a null pointer with pixels present, n_lights outside
+ * 0..8, a non-finite light or flag parameter, first_hit_alpha outside [0, 1)
+ * or a negative strength, grace or falloff. */
+int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf, const float* material,
+              const vct_cone_params* params, const vct_shade_params* shade, float* out, hipStream_t stream);
 
 /* Diagnostics: per-kernel timing.  Registers `count` events (a host array of
  * hipEvent_t created by the caller) for the NEXT enqueuing call on this thread

@@ -67,6 +67,7 @@ def lib():
         "vct_unpack_level": [P(CGrid), vp, ctypes.c_int32, vp, vp],
         "vct_trace": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
         "vct_count_samples": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
+        "vct_shade": [P(CGrid), vp, P(CGBuffer), vp, P(CConeParams), P(CShadeParams), vp, vp],
         "vct_backward_workspace_bytes": [P(CGrid), P(CGBuffer), P(CConeParams), P(sz)],
         "vct_trace_backward": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp, vp, sz, vp],
         "vct_lane_state_bytes": [P(CGBuffer), P(CConeParams), P(sz)],
@@ -165,6 +166,45 @@ class Grid:
             g.origin[i] = self.origin[i]
         g.extent = self.extent
         return g
+
+
+MAX_LIGHTS = 8
+
+
+class CShadeParams(ctypes.Structure):
+    _fields_ = [("n_lights", ctypes.c_int32),
+                ("light_pos", (ctypes.c_float * 3) * MAX_LIGHTS),
+                ("light_diffuse", (ctypes.c_float * 3) * MAX_LIGHTS),
+                ("light_specular", (ctypes.c_float * 3) * MAX_LIGHTS),
+                ("specular_color", ctypes.c_float * 3),
+                ("diffuse_first_hit", ctypes.c_int32), ("first_hit_alpha", ctypes.c_float),
+                ("occlusion_falloff", ctypes.c_int32), ("shadow_strength", ctypes.c_float),
+                ("specular_brdf", ctypes.c_int32), ("grace_per_shininess", ctypes.c_float),
+                ("shininess_falloff", ctypes.c_float)]
+
+
+def shade_params(p):
+    """C struct from any object with the fields of scenes.configs.ShadeParams."""
+    c = CShadeParams()
+    pos = [tuple(map(float, v)) for v in p.light_pos]
+    if len(pos) > MAX_LIGHTS or len(p.light_diffuse) != len(pos) or len(p.light_specular) != len(pos):
+        raise ValueError("light_pos / light_diffuse / light_specular: at most 8 lights, one row per light")
+    c.n_lights = len(pos)
+    for l in range(len(pos)):
+        for i in range(3):
+            c.light_pos[l][i] = pos[l][i]
+            c.light_diffuse[l][i] = float(p.light_diffuse[l][i])
+            c.light_specular[l][i] = float(p.light_specular[l][i])
+    for i in range(3):
+        c.specular_color[i] = float(p.specular_color[i])
+    c.diffuse_first_hit = int(bool(p.diffuse_first_hit))
+    c.first_hit_alpha = float(p.first_hit_alpha)
+    c.occlusion_falloff = int(bool(p.occlusion_falloff))
+    c.shadow_strength = float(p.shadow_strength)
+    c.specular_brdf = int(bool(p.specular_brdf))
+    c.grace_per_shininess = float(p.grace_per_shininess)
+    c.shininess_falloff = float(p.shininess_falloff)
+    return c
 
 
 def cone_params(p):
@@ -275,6 +315,23 @@ def trace(pyramid, grid, pos_rough, normal, cam_pos, params, out=None):
     with torch.cuda.device(pos_rough.device):
         _check(lib().vct_trace(ctypes.byref(grid.c()), _ptr(pyramid), ctypes.byref(gb),
                                ctypes.byref(cone_params(params)), _ptr(out), _stream(pos_rough.device)))
+    return out
+
+
+def shade(pyramid, grid, pos_rough, normal, cam_pos, material, params, sparams, out=None):
+    """Final shading with the thesis's cone variants.  Returns float32
+    [b,h,w,4] = (L.rgb, o_min)."""
+    gb = _gbuf(pos_rough, normal, cam_pos)
+    dev = pos_rough.device
+    _need(pyramid, "pyramid", torch.uint8, None, dev)
+    _need(material, "material", torch.float32, tuple(pos_rough.shape), dev)
+    if out is None:
+        out = torch.empty(tuple(pos_rough.shape[:3]) + (4,), dtype=torch.float32, device=dev)
+    _need(out, "out", torch.float32, tuple(pos_rough.shape[:3]) + (4,), dev)
+    with torch.cuda.device(dev):
+        _check(lib().vct_shade(ctypes.byref(grid.c()), _ptr(pyramid), ctypes.byref(gb), _ptr(material),
+                               ctypes.byref(cone_params(params)), ctypes.byref(shade_params(sparams)), _ptr(out),
+                               _stream(dev)))
     return out
 
 

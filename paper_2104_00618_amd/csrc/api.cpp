@@ -247,6 +247,48 @@ int vct_count_samples(const vct_grid* grid, const void* pyramid, const vct_gbuff
     return trace_common("vct_count_samples", grid, pyramid, gbuf, params, nullptr, count, true, stream);
 }
 
+int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf, const float* material,
+              const vct_cone_params* params, const vct_shade_params* shade, float* out, hipStream_t stream) {
+    const char* fn = "vct_shade";
+    EventSink es = take_events();
+    if (int r = check_grid(fn, grid)) return r;
+    if (int r = check_gbuffer(fn, gbuf)) return r;
+    if (int r = check_params(fn, grid, params)) return r;
+    if (!shade) return fail(VCT_EINVAL, fn, "shade is null");
+    if (shade->n_lights < 0 || shade->n_lights > VCT_MAX_LIGHTS)
+        return fail(VCT_EINVAL, fn, "n_lights = %d must be in [0, %d]", shade->n_lights, VCT_MAX_LIGHTS);
+    for (int l = 0; l < shade->n_lights; ++l)
+        for (int i = 0; i < 3; ++i)
+            if (!finite(shade->light_pos[l][i]) || !finite(shade->light_diffuse[l][i]) ||
+                !finite(shade->light_specular[l][i]))
+                return fail(VCT_EINVAL, fn, "light %d has a non-finite position or intensity", l);
+    for (int i = 0; i < 3; ++i)
+        if (!finite(shade->specular_color[i])) return fail(VCT_EINVAL, fn, "specular_color is not finite");
+    if (!finite(shade->first_hit_alpha) || shade->first_hit_alpha < 0.f || shade->first_hit_alpha >= 1.f)
+        return fail(VCT_EINVAL, fn, "first_hit_alpha must be in [0, 1)");
+    struct {
+        const char* name;
+        float v;
+    } nonneg[] = {{"shadow_strength", shade->shadow_strength},
+                  {"grace_per_shininess", shade->grace_per_shininess},
+                  {"shininess_falloff", shade->shininess_falloff}};
+    for (auto& e : nonneg)
+        if (!finite(e.v) || e.v < 0.f) return fail(VCT_EINVAL, fn, "%s must be finite and >= 0", e.name);
+    long long np = (long long)gbuf->b * gbuf->h * gbuf->w;
+    if (np > 0 && (!pyramid || !material || !out))
+        return fail(VCT_EINVAL, fn, "pyramid, material and out must be non-null");
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    TraceArgs a = make_args(grid, L, pyramid, gbuf, params);
+    if (a.n_tiles == 0) {
+        ok();
+        return VCT_OK;
+    }
+    hipError_t e = vct_launch_shade(a, grid->dtype, shade, material, out, stream, es);
+    if (e != hipSuccess) return device_error(fn, e);
+    ok();
+    return VCT_OK;
+}
+
 int vct_backward_workspace_bytes(const vct_grid* grid, const vct_gbuffer* gbuf, const vct_cone_params* params,
                                  size_t* bytes) {
     const char* fn = "vct_backward_workspace_bytes";

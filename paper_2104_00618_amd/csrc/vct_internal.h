@@ -122,6 +122,8 @@ hipError_t vct_launch_build_mips(const PyrLayout& L, const float* base, void* py
 hipError_t vct_launch_unpack(const PyrLayout& L, const void* pyr, int level, float* out, hipStream_t s);
 hipError_t vct_launch_trace(const TraceArgs& a, int dtype, float* out, unsigned long long* count,
                             hipStream_t s, EventSink& es);
+hipError_t vct_launch_shade(const TraceArgs& a, int dtype, const vct_shade_params* p, const float* material,
+                            float* out, hipStream_t s, EventSink& es);
 
 struct BackwardPlan {
     int64_t n_lanes;          // pixels * cones

@@ -2,4 +2,5 @@
 cone-set tables).  Shared by the oracle tests and the HIP path; holds no cone
 tracing arithmetic."""
 from . import cornell, configs  # noqa: F401
-from .configs import ConeParams, Workload, make_workload, cone_set, random_grid, random_gbuffer  # noqa: F401
+from .configs import (ConeParams, ShadeParams, Workload, make_workload, cone_set, random_grid,  # noqa: F401
+                      random_gbuffer, random_material, scene_lights)

@@ -41,6 +41,49 @@ class ConeParams:
         return dataclasses.replace(self, **kw)
 
 
+@dataclasses.dataclass
+class ShadeParams:
+    """Lights, specular colour and the cone-variant flags of the final shading
+    pass (Section 5.4.4, "Cone Tracing"): occlusion falloff with a shadow
+    strength, first-hit diffuse cones with their alpha threshold, and the
+    angular-grace specular BRDF (grace = factor * shininess, exponent q)."""
+    light_pos: np.ndarray                       # float32[n, 3]
+    light_diffuse: np.ndarray                   # float32[n, 3]
+    light_specular: np.ndarray                  # float32[n, 3]
+    specular_color: tuple = (1.0, 1.0, 1.0)
+    diffuse_first_hit: bool = True
+    first_hit_alpha: float = 0.01
+    occlusion_falloff: bool = True
+    shadow_strength: float = 1.0
+    specular_brdf: bool = True
+    grace_per_shininess: float = 0.008 * math.pi
+    shininess_falloff: float = 8.0
+
+    @property
+    def n_lights(self):
+        return int(len(self.light_pos))
+
+    def replace(self, **kw):
+        return dataclasses.replace(self, **kw)
+
+
+def scene_lights(count=2, **kw):
+    """Shading parameters with `count` (<= 4) point lights: the scene light
+    (white) first, then dimmer coloured lights inside the box."""
+    pos = np.array([cornell.LIGHT_POS, (0.2, 0.6, 0.8), (0.8, 0.4, 0.3), (0.5, 0.3, 0.9)], np.float32)[:count]
+    dif = np.array([(1.0, 1.0, 1.0), (0.5, 0.4, 0.3), (0.2, 0.3, 0.5), (0.3, 0.3, 0.3)], np.float32)[:count]
+    spe = np.array([(0.5, 0.5, 0.5), (0.3, 0.3, 0.2), (0.2, 0.2, 0.3), (0.1, 0.1, 0.1)], np.float32)[:count]
+    return ShadeParams(pos, dif, spe, **kw)
+
+
+def random_material(shape, seed):
+    """Per-pixel material [b, h, w, 4] = (albedo U[0.2, 0.9]^3, shininess U[1, 64])."""
+    rng = np.random.default_rng(seed)
+    alb = rng.uniform(0.2, 0.9, size=tuple(shape) + (3,))
+    shin = rng.uniform(1.0, 64.0, size=tuple(shape) + (1,))
+    return np.concatenate([alb, shin], -1).astype(np.float32)
+
+
 def front_plus_ring(polar_deg, count, front=True):
     """Unit directions: optional front cone (the normal) plus ``count`` cones at
     ``polar_deg`` from the normal, evenly spaced in azimuth starting at 0."""

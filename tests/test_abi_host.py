@@ -279,3 +279,76 @@ def test_saved_path_undersized_buffers_give_eworkspace():
     rc = lib.vct_trace_backward_saved(ctypes.byref(g), fake, ctypes.byref(gb), ctypes.byref(p), fake, 1 << 20, fake,
                                       fake, fake, 16, None)
     assert rc == EWORKSPACE and "workspace" in lib.vct_last_error().decode()
+
+
+def test_shade_params_layout_matches_header(tmp_path):
+    src = tmp_path / "shade_layout.c"
+    src.write_text(r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "vct.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(vct_shade_params), offsetof(vct_shade_params, light_diffuse),
+         offsetof(vct_shade_params, specular_color), offsetof(vct_shade_params, diffuse_first_hit),
+         offsetof(vct_shade_params, occlusion_falloff), offsetof(vct_shade_params, specular_brdf),
+         offsetof(vct_shade_params, grace_per_shininess), offsetof(vct_shade_params, shininess_falloff));
+  return 0;
+}
+''')
+    exe = tmp_path / "shade_layout"
+    r = subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", f"-I{ROOT}/include", "-I/opt/rocm/include",
+                        str(src), "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()))
+    S = B.CShadeParams
+    assert got == [ctypes.sizeof(S), S.light_diffuse.offset, S.specular_color.offset, S.diffuse_first_hit.offset,
+                   S.occlusion_falloff.offset, S.specular_brdf.offset, S.grace_per_shininess.offset,
+                   S.shininess_falloff.offset]
+
+
+def _shade_params(**kw):
+    import numpy as np
+    from scenes.configs import ShadeParams
+    base = dict(light_pos=np.array([[0.5, 0.9, 0.5]], np.float32), light_diffuse=np.ones((1, 3), np.float32),
+                light_specular=np.ones((1, 3), np.float32))
+    base.update(kw)
+    return B.shade_params(ShadeParams(**base))
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("n_lights", 9, "n_lights"), ("n_lights", -1, "n_lights"), ("first_hit_alpha", 1.0, "first_hit_alpha"),
+    ("first_hit_alpha", float("nan"), "first_hit_alpha"), ("shadow_strength", -1.0, "shadow_strength"),
+    ("grace_per_shininess", float("inf"), "grace_per_shininess"), ("shininess_falloff", -2.0, "shininess_falloff"),
+])
+def test_shade_rejects_bad_parameters(field, value, msg):
+    g = vct.Grid(16).c()
+    gb = _empty_gbuf()
+    p = B.cone_params(_params(alpha_thresh=0.99))
+    s = _shade_params()
+    setattr(s, field, value)
+    rc = vct.lib().vct_shade(ctypes.byref(g), None, ctypes.byref(gb), None, ctypes.byref(p), ctypes.byref(s), None,
+                             None)
+    assert rc == EINVAL and msg in vct.lib().vct_last_error().decode()
+
+
+def test_shade_rejects_non_finite_lights_and_null_buffers():
+    lib = vct.lib()
+    g = vct.Grid(16).c()
+    p = B.cone_params(_params(alpha_thresh=0.99))
+    s = _shade_params()
+    s.light_pos[0][1] = float("nan")
+    gb = _empty_gbuf()
+    rc = lib.vct_shade(ctypes.byref(g), None, ctypes.byref(gb), None, ctypes.byref(p), ctypes.byref(s), None, None)
+    assert rc == EINVAL and "light 0" in lib.vct_last_error().decode()
+    s = _shade_params()
+    gb = B.CGBuffer()
+    gb.b, gb.h, gb.w = 1, 2, 2
+    gb.pos_rough = gb.normal = gb.cam_pos = 0x1000
+    rc = lib.vct_shade(ctypes.byref(g), ctypes.c_void_p(0x1000), ctypes.byref(gb), None, ctypes.byref(p),
+                       ctypes.byref(s), ctypes.c_void_p(0x1000), None)
+    assert rc == EINVAL and "material" in lib.vct_last_error().decode()
+    # no pixels and no lights: valid, nothing enqueued
+    s.n_lights = 0
+    gb = _empty_gbuf()
+    assert lib.vct_shade(ctypes.byref(g), None, ctypes.byref(gb), None, ctypes.byref(p), ctypes.byref(s), None,
+                         None) == 0
