@@ -207,8 +207,18 @@ def main():
                                                                 shade_out), args.steps) for nl in (1, 3)}
     recompute_bwd_ms = timed(lambda: vct.trace_backward(pyr, grid, pr, nr, cam, w.params, gout, ws, gbase),
                              max(args.steps // 2, 1))
+    # per-frame revoxelization: voxelize the Cornell mesh (direct-light injection) into the 256^3 base grid
+    from scenes.mesh import cornell_mesh
+    vt, vc = cornell_mesh(1)
+    vox_tris = int(vt.shape[0])
+    vt, vc = T(vt), T(vc)
+    vws = torch.empty(vct.voxelize_workspace_bytes(grid, vox_tris), dtype=torch.uint8, device=dev)
+    vbase = torch.empty_like(base)
+    vlights = [((0.5, 0.95, 0.5), (1.0, 1.0, 1.0), (1.0, 0.5, 0.25))]
+    vox_ms = timed(lambda: vct.voxelize(vt, vc, grid, vlights, base=vbase, workspace=vws), args.steps)
+    del vws
     log(f"trace alone {fwd_ms:.3f} ms; recompute path step {mips_ms + fwd_ms + recompute_bwd_ms:.3f} ms; "
-        f"shade {', '.join(f'{k} {v:.3f} ms' for k, v in shade_ms.items())}")
+        f"shade {', '.join(f'{k} {v:.3f} ms' for k, v in shade_ms.items())}; voxelize {vox_ms:.3f} ms")
 
     texel_bytes = 16 if args.dtype == "f32" else 8
     trace_bytes = samples * 16 * texel_bytes + npix * 64
@@ -217,7 +227,8 @@ def main():
         "build_mips_ms": mips_ms, "trace_save_ms": save_ms, "trace_backward_saved_ms": bwd_ms,
         "trace_backward_saved_kernels_ms": {n: float(t) for n, t in zip(BWD_KERNELS, bwd_k)},
         "trace_ms": fwd_ms, "fwd_ms_per_frame": mips_ms + fwd_ms,
-        "shade_ms": shade_ms, "fwd_bwd_ms_per_frame": mips_ms + save_ms + bwd_ms,
+        "shade_ms": shade_ms,
+        "revoxelize": {"triangles": vox_tris, "voxelize_ms": vox_ms, "voxelize_plus_mips_ms": vox_ms + mips_ms}, "fwd_bwd_ms_per_frame": mips_ms + save_ms + bwd_ms,
         "recompute_path": {"trace_backward_ms": recompute_bwd_ms,
                            "fwd_bwd_ms_per_frame": mips_ms + fwd_ms + recompute_bwd_ms},
         "samples_per_frame": samples, "samples_per_pixel": samples / npix,

@@ -123,6 +123,18 @@ typedef struct {
     float shininess_falloff;                     /* exponent q >= 0 */
 } vct_shade_params;
 
+/* Lights and material strengths of voxelization with direct-light injection
+ * (Section 4.4 "Voxelization Process", 3D texture storage: the Phong model of
+ * Section 3.2 without its glossy term, with distance attenuation). */
+typedef struct {
+    int32_t n_lights;                            /* 0..8 */
+    float light_pos[VCT_MAX_LIGHTS][3];          /* world units */
+    float light_color[VCT_MAX_LIGHTS][3];        /* rgb, finite */
+    float attenuation[VCT_MAX_LIGHTS][3];        /* (constant, linear, quadratic), >= 0, not all 0 */
+    float ambient;                               /* ambient strength, >= 0 */
+    float diffuse;                               /* diffuse strength, >= 0 */
+} vct_voxelize_params;
+
 /* Bytes of the opaque pyramid buffer for `grid` (host only, enqueues nothing).
  * Layout (informative): each level stored as 4^3-texel bricks in the storage
  * type, levels concatenated at 256-byte alignment, followed by a small float32
@@ -235,6 +247,35 @@ int vct_trace_backward_saved(const vct_grid* grid, const void* pyramid, const vc
  * or a negative strength, grace or falloff. */
 int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf, const float* material,
               const vct_cone_params* params, const vct_shade_params* shade, float* out, hipStream_t stream);
+
+/* Voxelize a triangle mesh with direct-light injection into a base grid
+ * (Section 4.4 "Voxelization Process": rasterization onto an N x N viewport,
+ * dominant axis selection, 3D texture storage; Section 5.4.4 "Voxelization").
+ * Every triangle is rasterized once along the largest component of its normal
+ * (ties to x, then y, then z; frames x: (z, y | x), y: (x, z | y), z: (x, y | z));
+ * a pixel centre inside the projected triangle is a fragment in the voxel
+ * (pixel, floor(depth)), with colour
+ *   c_tri * sum_l (ambient + diffuse max(0, N . L_l)) light_color_l / (c_l + l_l d_l + q_l d_l^2)
+ * (N the unit normal of the triangle as wound, L_l and d_l direction and
+ * distance to light l) and alpha 1.  Coverage and depth are exact: vertices
+ * snapped to 1/256 voxel (round((p - origin) * 256 N / extent) in float32),
+ * integer edge functions with the top-left rule (a centre on an edge belongs to
+ * the triangle when the counter-clockwise edge runs upward, or horizontally
+ * leftward), exact floor of the plane depth.  Fragments in one voxel are
+ * averaged (deterministic fixed-point sums and a count); other voxels are 0.
+ * Triangles with a non-finite vertex or a snapped coordinate beyond 2^19 are
+ * skipped; per-fragment colours are clamped to +-2^28.
+ *   tris       device float32 [n_tris][3][3] vertex positions, world units
+ *   colors     device float32 [n_tris][3] triangle colours
+ *   base       device float32 [N][N][N][4] premultiplied RGBA, overwritten (a vct_build_mips input)
+ *   workspace  device, vct_voxelize_workspace_bytes(grid, n_tris) bytes (32 per voxel, 160 per triangle)
+ * Errors: VCT_EINVAL for a bad grid, n_tris outside [0, 2^31), null buffers,
+ * n_lights outside 0..8, non-finite or negative light parameters or
+ * attenuation all 0; VCT_EWORKSPACE if the workspace is too small. */
+int vct_voxelize_workspace_bytes(const vct_grid* grid, int64_t n_tris, size_t* bytes);
+int vct_voxelize(const vct_grid* grid, const float* tris, const float* colors, int64_t n_tris,
+                 const vct_voxelize_params* params, float* base, void* workspace, size_t workspace_bytes,
+                 hipStream_t stream);
 
 /* Diagnostics: per-kernel timing.  Registers `count` events (a host array of
  * hipEvent_t created by the caller) for the NEXT enqueuing call on this thread

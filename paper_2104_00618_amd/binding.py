@@ -68,6 +68,8 @@ def lib():
         "vct_trace": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
         "vct_count_samples": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
         "vct_shade": [P(CGrid), vp, P(CGBuffer), vp, P(CConeParams), P(CShadeParams), vp, vp],
+        "vct_voxelize_workspace_bytes": [P(CGrid), ctypes.c_int64, P(sz)],
+        "vct_voxelize": [P(CGrid), vp, vp, ctypes.c_int64, P(CVoxelizeParams), vp, vp, sz, vp],
         "vct_backward_workspace_bytes": [P(CGrid), P(CGBuffer), P(CConeParams), P(sz)],
         "vct_trace_backward": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp, vp, sz, vp],
         "vct_lane_state_bytes": [P(CGBuffer), P(CConeParams), P(sz)],
@@ -207,6 +209,30 @@ def shade_params(p):
     return c
 
 
+class CVoxelizeParams(ctypes.Structure):
+    _fields_ = [("n_lights", ctypes.c_int32),
+                ("light_pos", (ctypes.c_float * 3) * MAX_LIGHTS),
+                ("light_color", (ctypes.c_float * 3) * MAX_LIGHTS),
+                ("attenuation", (ctypes.c_float * 3) * MAX_LIGHTS),
+                ("ambient", ctypes.c_float), ("diffuse", ctypes.c_float)]
+
+
+def voxelize_params(lights, ambient=0.1, diffuse=1.0):
+    """C struct from a sequence of (position[3], colour[3], attenuation (c, l, q))."""
+    c = CVoxelizeParams()
+    if len(lights) > MAX_LIGHTS:
+        raise ValueError("at most 8 lights")
+    c.n_lights = len(lights)
+    for l, (pos, col, att) in enumerate(lights):
+        for i in range(3):
+            c.light_pos[l][i] = float(pos[i])
+            c.light_color[l][i] = float(col[i])
+            c.attenuation[l][i] = float(att[i])
+    c.ambient = float(ambient)
+    c.diffuse = float(diffuse)
+    return c
+
+
 def cone_params(p):
     """C struct from any object with the cone-set attributes (n_diffuse taken
     from len(diffuse_dirs))."""
@@ -333,6 +359,32 @@ def shade(pyramid, grid, pos_rough, normal, cam_pos, material, params, sparams, 
                                ctypes.byref(cone_params(params)), ctypes.byref(shade_params(sparams)), _ptr(out),
                                _stream(dev)))
     return out
+
+
+def voxelize_workspace_bytes(grid, n_tris):
+    n = ctypes.c_size_t()
+    _check(lib().vct_voxelize_workspace_bytes(ctypes.byref(grid.c()), int(n_tris), ctypes.byref(n)))
+    return n.value
+
+
+def voxelize(tris, colors, grid, lights, ambient=0.1, diffuse=1.0, base=None, workspace=None):
+    """Voxelize a triangle mesh (float32 [T, 3, 3] world positions, float32
+    [T, 3] colours) with direct-light injection into a float32 base grid
+    [N, N, N, 4] (premultiplied RGBA)."""
+    dev = tris.device
+    _need(tris, "tris", torch.float32, (tris.shape[0], 3, 3), dev)
+    _need(colors, "colors", torch.float32, (tris.shape[0], 3), dev)
+    if base is None:
+        base = torch.empty((grid.n, grid.n, grid.n, 4), dtype=torch.float32, device=dev)
+    _need(base, "base", torch.float32, (grid.n, grid.n, grid.n, 4), dev)
+    if workspace is None:
+        workspace = torch.empty(voxelize_workspace_bytes(grid, tris.shape[0]), dtype=torch.uint8, device=dev)
+    _need(workspace, "workspace", torch.uint8, None, dev)
+    with torch.cuda.device(dev):
+        _check(lib().vct_voxelize(ctypes.byref(grid.c()), _ptr(tris), _ptr(colors), int(tris.shape[0]),
+                                  ctypes.byref(voxelize_params(lights, ambient, diffuse)), _ptr(base),
+                                  _ptr(workspace), workspace.numel(), _stream(dev)))
+    return base
 
 
 def count_samples(pyramid, grid, pos_rough, normal, cam_pos, params):

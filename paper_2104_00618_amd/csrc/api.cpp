@@ -289,6 +289,50 @@ int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf
     return VCT_OK;
 }
 
+int vct_voxelize_workspace_bytes(const vct_grid* grid, int64_t n_tris, size_t* bytes) {
+    const char* fn = "vct_voxelize_workspace_bytes";
+    if (int r = check_grid(fn, grid)) return r;
+    if (n_tris < 0 || n_tris >= (int64_t(1) << 31))
+        return fail(VCT_EINVAL, fn, "n_tris = %lld must be in [0, 2^31)", (long long)n_tris);
+    if (!bytes) return fail(VCT_EINVAL, fn, "bytes is null");
+    *bytes = vct_voxelize_workspace_size(grid->n, n_tris);
+    ok();
+    return VCT_OK;
+}
+
+int vct_voxelize(const vct_grid* grid, const float* tris, const float* colors, int64_t n_tris,
+                 const vct_voxelize_params* params, float* base, void* workspace, size_t workspace_bytes,
+                 hipStream_t stream) {
+    const char* fn = "vct_voxelize";
+    EventSink es = take_events();
+    if (int r = check_grid(fn, grid)) return r;
+    if (n_tris < 0 || n_tris >= (int64_t(1) << 31))
+        return fail(VCT_EINVAL, fn, "n_tris = %lld must be in [0, 2^31)", (long long)n_tris);
+    if (!params) return fail(VCT_EINVAL, fn, "params is null");
+    if (params->n_lights < 0 || params->n_lights > VCT_MAX_LIGHTS)
+        return fail(VCT_EINVAL, fn, "n_lights = %d must be in [0, %d]", params->n_lights, VCT_MAX_LIGHTS);
+    for (int l = 0; l < params->n_lights; ++l) {
+        for (int i = 0; i < 3; ++i)
+            if (!finite(params->light_pos[l][i]) || !finite(params->light_color[l][i]) ||
+                !finite(params->attenuation[l][i]) || params->attenuation[l][i] < 0.f)
+                return fail(VCT_EINVAL, fn, "light %d: position and colour must be finite, attenuation finite and >= 0",
+                            l);
+        if (!(params->attenuation[l][0] + params->attenuation[l][1] + params->attenuation[l][2] > 0.f))
+            return fail(VCT_EINVAL, fn, "light %d: attenuation terms are all 0", l);
+    }
+    if (!finite(params->ambient) || params->ambient < 0.f || !finite(params->diffuse) || params->diffuse < 0.f)
+        return fail(VCT_EINVAL, fn, "ambient and diffuse must be finite and >= 0");
+    if (!base || !workspace) return fail(VCT_EINVAL, fn, "base and workspace must be non-null");
+    if (n_tris > 0 && (!tris || !colors)) return fail(VCT_EINVAL, fn, "tris and colors must be non-null");
+    const size_t need = vct_voxelize_workspace_size(grid->n, n_tris);
+    if (workspace_bytes < need)
+        return fail(VCT_EWORKSPACE, fn, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    hipError_t e = vct_launch_voxelize(grid, tris, colors, n_tris, params, base, workspace, stream, es);
+    if (e != hipSuccess) return device_error(fn, e);
+    ok();
+    return VCT_OK;
+}
+
 int vct_backward_workspace_bytes(const vct_grid* grid, const vct_gbuffer* gbuf, const vct_cone_params* params,
                                  size_t* bytes) {
     const char* fn = "vct_backward_workspace_bytes";

@@ -1,0 +1,332 @@
+// Voxelization with direct-light injection (Section 4.4 "Voxelization
+// Process", Section 5.4.4 "Voxelization"): every triangle is rasterized once
+// along its dominant axis onto an N x N viewport; every fragment (pixel centre
+// inside the projected triangle) is the voxel (pixel, floor(depth)) and gets
+// the Phong light of the surface point without its glossy term (ambient +
+// diffuse with the triangle's own normal, distance attenuation) and alpha 1.
+//
+// Determinism: coverage and depth are decided on vertices snapped to 1/256
+// voxel by exact integer edge functions and an exact floor division (a
+// centre on an edge belongs to the triangle when the counter-clockwise edge
+// runs upward or horizontally leftward, so shared edges are covered once);
+// fragments falling into the same voxel are averaged through 64-bit
+// fixed-point sums and a count, so the result does not depend on the order in
+// which fragments arrive.
+//
+// Launch: a setup pass (one thread per triangle) writes each triangle's
+// rasterization record and its number of 256-pixel chunks, one workgroup
+// scans the chunk counts, and the raster pass hands (triangle, chunk) items to
+// waves in a grid-stride loop, so a wall-sized triangle is spread over many
+// waves.  Per voxel the workspace holds {int64 r, g, b; uint32 count; pad}
+// (32 bytes), cleared by a fill kernel (no memset, so the path can be captured
+// in a graph); a resolve pass writes the float32 base grid.
+#include "vct_internal.h"
+
+namespace {
+
+constexpr int kSub = 256;                 // subpixels per voxel
+constexpr int kCoordLimit = 1 << 19;      // |snapped coordinate| bound of the exact arithmetic
+constexpr float kFix = 4294967296.0f;     // 2^32: fixed-point scale of the colour sums
+constexpr float kFixMax = 268435456.0f;   // 2^28: per-fragment colour bound of the fixed point
+
+struct VoxArgs {
+    int32_t n;
+    float origin[3];
+    float voxel;          // extent / N
+    float snap_scale;     // 256 N / extent, float32
+    int32_t n_lights;
+    float light_pos[VCT_MAX_LIGHTS][3];
+    float light_color[VCT_MAX_LIGHTS][3];
+    float att[VCT_MAX_LIGHTS][3];
+    float ambient, diffuse;
+};
+
+struct VoxAcc {
+    unsigned long long r, g, b;
+    unsigned int count, pad;
+};
+
+__global__ void k_clear(uint4* __restrict__ p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+__device__ __forceinline__ long long floor_div(long long a, long long b) {   // b > 0
+    long long q = a / b;
+    return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
+__device__ __forceinline__ bool top_left(long long dx, long long dy) { return dy > 0 || (dy == 0 && dx < 0); }
+
+__device__ __forceinline__ unsigned long long to_fixed(float v) {
+    v = fminf(fmaxf(v, -kFixMax), kFixMax);
+    return (unsigned long long)(long long)rintf(v * kFix);
+}
+
+// Rasterization setup of one triangle: snapped, swizzled vertices (counter-
+// clockwise), plane coefficients, pixel bounding box, the unit normal of the
+// original triangle and its colour.  npx = 0 when the triangle produces nothing.
+struct TriSetup {
+    long long A[3], B[3], C[3];      // (X2, Y2, W) subpixel coordinates
+    long long nx, ny, nw;            // plane: nw W = nw A.w - nx (X - A.x) - ny (Y - A.y), nw > 0
+    int32_t i0, j0, w, npx;          // bounding box origin and width in pixels, pixel count
+    int32_t sx, sy, sw, pad;         // source axes of X2, Y2, W
+    float n[3], col[3];
+};
+
+constexpr int kChunk = 256;          // pixels per wave per work item
+
+__global__ __launch_bounds__(256) void k_tri_setup(VoxArgs a, const float* __restrict__ tris,
+                                                   const float* __restrict__ colors, long long n_tris,
+                                                   TriSetup* __restrict__ setup, unsigned long long* __restrict__ chunks) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tris) return;
+    TriSetup r{};
+    chunks[t] = 0;
+    // snapped vertices (float32 arithmetic, round half to even)
+    float vf[3][3];
+    long long s[3][3];
+    bool ok = true;
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i) {
+            const float p = tris[t * 9 + k * 3 + i];
+            vf[k][i] = p;
+            const float u = rintf((p - a.origin[i]) * a.snap_scale);
+            ok = ok && isfinite(p) && fabsf(u) <= (float)kCoordLimit;
+            s[k][i] = ok ? (long long)u : 0;
+        }
+    if (!ok) {
+        setup[t] = r;
+        return;
+    }
+    // dominant axis of the snapped normal (ties to x, then y, then z)
+    long long e1[3], e2[3];
+    for (int i = 0; i < 3; ++i) {
+        e1[i] = s[1][i] - s[0][i];
+        e2[i] = s[2][i] - s[0][i];
+    }
+    const long long nrm[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                              e1[0] * e2[1] - e1[1] * e2[0]};
+    const long long ax = nrm[0] < 0 ? -nrm[0] : nrm[0], ay = nrm[1] < 0 ? -nrm[1] : nrm[1],
+                    az = nrm[2] < 0 ? -nrm[2] : nrm[2];
+    const int dom = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+    // projection frame (X2, Y2 | W): x-dominant (z, y | x), y-dominant (x, z | y), z-dominant (x, y | z)
+    r.sx = dom == 0 ? 2 : 0;
+    r.sy = dom == 1 ? 2 : 1;
+    r.sw = dom;
+    for (int k = 0; k < 3; ++k) {
+        long long* V = k == 0 ? r.A : (k == 1 ? r.B : r.C);
+        V[0] = s[k][r.sx];
+        V[1] = s[k][r.sy];
+        V[2] = s[k][r.sw];
+    }
+    const long long area = (r.B[0] - r.A[0]) * (r.C[1] - r.A[1]) - (r.B[1] - r.A[1]) * (r.C[0] - r.A[0]);
+    if (area == 0) {
+        setup[t] = TriSetup{};
+        return;
+    }
+    if (area < 0) {
+        for (int i = 0; i < 3; ++i) {
+            const long long tmp = r.B[i];
+            r.B[i] = r.C[i];
+            r.C[i] = tmp;
+        }
+    }
+    const long long h = kSub / 2;
+    const long long minx = min(r.A[0], min(r.B[0], r.C[0])), maxx = max(r.A[0], max(r.B[0], r.C[0]));
+    const long long miny = min(r.A[1], min(r.B[1], r.C[1])), maxy = max(r.A[1], max(r.B[1], r.C[1]));
+    const long long i0 = max(0ll, -floor_div(h - minx, kSub)), i1 = min((long long)a.n - 1, floor_div(maxx - h, kSub));
+    const long long j0 = max(0ll, -floor_div(h - miny, kSub)), j1 = min((long long)a.n - 1, floor_div(maxy - h, kSub));
+    if (i1 < i0 || j1 < j0) {
+        setup[t] = TriSetup{};
+        return;
+    }
+    const long long f1[3] = {r.B[0] - r.A[0], r.B[1] - r.A[1], r.B[2] - r.A[2]};
+    const long long f2[3] = {r.C[0] - r.A[0], r.C[1] - r.A[1], r.C[2] - r.A[2]};
+    r.nx = f1[1] * f2[2] - f1[2] * f2[1];
+    r.ny = f1[2] * f2[0] - f1[0] * f2[2];
+    r.nw = f1[0] * f2[1] - f1[1] * f2[0];
+    r.i0 = (int32_t)i0;
+    r.j0 = (int32_t)j0;
+    r.w = (int32_t)(i1 - i0 + 1);
+    r.npx = (int32_t)((i1 - i0 + 1) * (j1 - j0 + 1));
+    // lighting: unit normal of the original triangle as wound
+    const float d1[3] = {vf[1][0] - vf[0][0], vf[1][1] - vf[0][1], vf[1][2] - vf[0][2]};
+    const float d2[3] = {vf[2][0] - vf[0][0], vf[2][1] - vf[0][1], vf[2][2] - vf[0][2]};
+    float tn[3] = {d1[1] * d2[2] - d1[2] * d2[1], d1[2] * d2[0] - d1[0] * d2[2], d1[0] * d2[1] - d1[1] * d2[0]};
+    const float l = sqrtf(tn[0] * tn[0] + tn[1] * tn[1] + tn[2] * tn[2]);
+    const float il = l > 0.f ? 1.0f / l : 0.f;
+    for (int i = 0; i < 3; ++i) {
+        r.n[i] = tn[i] * il;
+        r.col[i] = colors[t * 3 + i];
+    }
+    setup[t] = r;
+    chunks[t] = (unsigned long long)((r.npx + kChunk - 1) / kChunk);
+}
+
+// Exclusive prefix sum of the chunk counts, in place, one workgroup; the
+// total goes to *total.
+__global__ __launch_bounds__(256) void k_chunk_scan(unsigned long long* __restrict__ c, long long n,
+                                                    unsigned long long* __restrict__ total) {
+    __shared__ unsigned long long s[256];
+    unsigned long long carry = 0;
+    for (long long base = 0; base < n; base += 256) {
+        const long long i = base + threadIdx.x;
+        const unsigned long long v = i < n ? c[i] : 0ull;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {   // inclusive Hillis-Steele scan
+            const unsigned long long add = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0ull;
+            __syncthreads();
+            s[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < n) c[i] = carry + s[threadIdx.x] - v;
+        carry += s[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+// floor(a / b) for b > 0 from a float estimate corrected in exact int64 arithmetic
+// (|a| < 2^63, quotients here are below 2^31).
+__device__ __forceinline__ long long floor_div_est(long long a, long long b) {
+    long long q = (long long)floorf((float)a / (float)b);
+    while (q * b > a) --q;
+    while ((q + 1) * b <= a) ++q;
+    return q;
+}
+
+// Work items are (triangle, chunk of kChunk pixels); each wave takes items
+// k = wave, wave + n_waves, ... below the total and finds the triangle by a
+// binary search of the chunk offsets.
+__global__ __launch_bounds__(256) void k_raster(VoxArgs a, const TriSetup* __restrict__ setup,
+                                                const unsigned long long* __restrict__ offs, long long n_tris,
+                                                const unsigned long long* __restrict__ total_p,
+                                                VoxAcc* __restrict__ acc) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long n_waves = (unsigned long long)gridDim.x * (blockDim.x >> 6);
+    const unsigned long long total = *total_p;
+    for (unsigned long long k = (unsigned long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < total;
+         k += n_waves) {
+        long long lo = 0, hi = n_tris - 1;            // last triangle with offs[t] <= k
+        while (lo < hi) {
+            const long long mid = (lo + hi + 1) >> 1;
+            if (offs[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        const TriSetup& r = setup[lo];
+        const int first = (int)(k - offs[lo]) * kChunk;
+        const int last = min(first + kChunk, r.npx);
+        const long long h = kSub / 2;
+        const long long den = r.nw * kSub;
+        const float sub_to_world = a.voxel / (float)kSub;
+        for (int p = first + lane; p < last; p += 64) {
+            const int pj_off = (int)((unsigned)p / (unsigned)r.w);
+            const long long pi = r.i0 + (p - pj_off * r.w), pj = r.j0 + pj_off;
+            const long long PX = pi * kSub + h, PY = pj * kSub + h;
+            const long long ea = (r.B[0] - r.A[0]) * (PY - r.A[1]) - (r.B[1] - r.A[1]) * (PX - r.A[0]);
+            const long long eb = (r.C[0] - r.B[0]) * (PY - r.B[1]) - (r.C[1] - r.B[1]) * (PX - r.B[0]);
+            const long long ec = (r.A[0] - r.C[0]) * (PY - r.C[1]) - (r.A[1] - r.C[1]) * (PX - r.C[0]);
+            const bool in = (ea > 0 || (ea == 0 && top_left(r.B[0] - r.A[0], r.B[1] - r.A[1]))) &&
+                            (eb > 0 || (eb == 0 && top_left(r.C[0] - r.B[0], r.C[1] - r.B[1]))) &&
+                            (ec > 0 || (ec == 0 && top_left(r.A[0] - r.C[0], r.A[1] - r.C[1])));
+            if (!in) continue;
+            const long long wnum = r.nw * r.A[2] - r.nx * (PX - r.A[0]) - r.ny * (PY - r.A[1]);
+            if (wnum < 0) continue;                                  // depth below the grid
+            const long long layer = floor_div_est(wnum, den);
+            if (layer >= a.n) continue;
+            long long v[3];
+            v[r.sx] = pi;
+            v[r.sy] = pj;
+            v[r.sw] = layer;
+            float sub[3];
+            sub[r.sx] = (float)PX;
+            sub[r.sy] = (float)PY;
+            sub[r.sw] = (float)wnum / (float)r.nw;
+            const float pos[3] = {a.origin[0] + sub[0] * sub_to_world, a.origin[1] + sub[1] * sub_to_world,
+                                  a.origin[2] + sub[2] * sub_to_world};
+            float lr = 0.f, lg = 0.f, lb = 0.f;
+            for (int l = 0; l < a.n_lights; ++l) {
+                const float dx = a.light_pos[l][0] - pos[0], dy = a.light_pos[l][1] - pos[1],
+                            dz = a.light_pos[l][2] - pos[2];
+                const float dist = sqrtf(dx * dx + dy * dy + dz * dz);
+                const float lam = dist > 0.f ? fmaxf((dx * r.n[0] + dy * r.n[1] + dz * r.n[2]) / dist, 0.0f) : 0.0f;
+                const float at = 1.0f / (a.att[l][0] + a.att[l][1] * dist + a.att[l][2] * dist * dist);
+                const float kk = (a.ambient + a.diffuse * lam) * at;
+                lr += kk * a.light_color[l][0];
+                lg += kk * a.light_color[l][1];
+                lb += kk * a.light_color[l][2];
+            }
+            VoxAcc* q = acc + (size_t)((v[2] * a.n + v[1]) * a.n + v[0]);
+            atomicAdd(&q->r, to_fixed(lr * r.col[0]));
+            atomicAdd(&q->g, to_fixed(lg * r.col[1]));
+            atomicAdd(&q->b, to_fixed(lb * r.col[2]));
+            atomicAdd(&q->count, 1u);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_resolve(const VoxAcc* __restrict__ acc, float4* __restrict__ base,
+                                                 size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const VoxAcc q = acc[i];
+        float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (q.count) {
+            const float inv = 1.0f / ((float)q.count * kFix);
+            o = make_float4((float)(long long)q.r * inv, (float)(long long)q.g * inv, (float)(long long)q.b * inv,
+                            1.0f);
+        }
+        base[i] = o;
+    }
+}
+
+}  // namespace
+
+// Workspace: the per-voxel accumulators, then per-triangle setup records, the
+// chunk offsets and the chunk total.
+size_t vct_voxelize_acc_bytes(int n) { return (size_t)n * n * n * sizeof(VoxAcc); }
+
+size_t vct_voxelize_workspace_size(int n, long long n_tris) {
+    return vct_voxelize_acc_bytes(n) + (size_t)n_tris * (sizeof(TriSetup) + 8) + 256;
+}
+
+hipError_t vct_launch_voxelize(const vct_grid* g, const float* tris, const float* colors, long long n_tris,
+                               const vct_voxelize_params* p, float* base, void* ws, hipStream_t st, EventSink& es) {
+    VoxArgs a{};
+    a.n = g->n;
+    for (int i = 0; i < 3; ++i) a.origin[i] = g->origin[i];
+    a.voxel = (float)((double)g->extent / g->n);
+    a.snap_scale = (float)((double)kSub * g->n / (double)g->extent);
+    a.n_lights = p->n_lights;
+    for (int l = 0; l < p->n_lights; ++l)
+        for (int i = 0; i < 3; ++i) {
+            a.light_pos[l][i] = p->light_pos[l][i];
+            a.light_color[l][i] = p->light_color[l][i];
+            a.att[l][i] = p->attenuation[l][i];
+        }
+    a.ambient = p->ambient;
+    a.diffuse = p->diffuse;
+    const size_t nvox = (size_t)g->n * g->n * g->n;
+    char* w = static_cast<char*>(ws);
+    VoxAcc* acc = reinterpret_cast<VoxAcc*>(w);
+    TriSetup* setup = reinterpret_cast<TriSetup*>(w + vct_voxelize_acc_bytes(g->n));
+    unsigned long long* offs = reinterpret_cast<unsigned long long*>(setup + n_tris);
+    unsigned long long* total = offs + n_tris;
+    const int fill_blocks = (int)min((nvox * sizeof(VoxAcc) / 16 + 255) / 256, (size_t)65536);
+    es.mark(st);
+    hipLaunchKernelGGL(k_clear, dim3(fill_blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(ws),
+                       nvox * sizeof(VoxAcc) / 16);
+    es.mark(st);
+    if (n_tris > 0) {
+        hipLaunchKernelGGL(k_tri_setup, dim3((unsigned)((n_tris + 255) / 256)), dim3(256), 0, st, a, tris, colors,
+                           n_tris, setup, offs);
+        hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(256), 0, st, offs, n_tris, total);
+        hipLaunchKernelGGL(k_raster, dim3(2048), dim3(256), 0, st, a, setup, offs, n_tris, total, acc);
+    }
+    es.mark(st);
+    const int res_blocks = (int)min((nvox + 255) / 256, (size_t)65536);
+    hipLaunchKernelGGL(k_resolve, dim3(res_blocks), dim3(256), 0, st, acc, reinterpret_cast<float4*>(base), nvox);
+    es.mark(st);
+    return hipGetLastError();
+}

@@ -352,3 +352,30 @@ def test_shade_rejects_non_finite_lights_and_null_buffers():
     gb = _empty_gbuf()
     assert lib.vct_shade(ctypes.byref(g), None, ctypes.byref(gb), None, ctypes.byref(p), ctypes.byref(s), None,
                          None) == 0
+
+
+def test_voxelize_validation_and_workspace_size():
+    lib = vct.lib()
+    g = vct.Grid(32).c()
+    n = ctypes.c_size_t()
+    assert lib.vct_voxelize_workspace_bytes(ctypes.byref(g), 0, ctypes.byref(n)) == 0 and n.value >= 32 ** 3 * 32
+    n0 = n.value
+    assert lib.vct_voxelize_workspace_bytes(ctypes.byref(g), 10, ctypes.byref(n)) == 0 and n.value > n0
+    good = B.voxelize_params([((0.5, 0.9, 0.5), (1, 1, 1), (1, 0, 0))])
+    fake = ctypes.c_void_p(0x1000)
+    cases = [(dict(n_tris=-1), "n_tris"), (dict(n_tris=1 << 31), "n_tris"), (dict(base=None), "non-null"),
+             (dict(tris=None), "non-null")]
+    for kw, msg in cases:
+        args = dict(tris=fake, colors=fake, n_tris=3, base=fake, ws=fake, ws_bytes=1 << 30)
+        args.update(kw)
+        rc = lib.vct_voxelize(ctypes.byref(g), args["tris"], args["colors"], args["n_tris"], ctypes.byref(good),
+                              args["base"], args["ws"], args["ws_bytes"], None)
+        assert rc == EINVAL and msg in lib.vct_last_error().decode(), (kw, lib.vct_last_error())
+    bad = B.voxelize_params([((0.5, 0.9, 0.5), (1, 1, 1), (0, 0, 0))])
+    rc = lib.vct_voxelize(ctypes.byref(g), fake, fake, 3, ctypes.byref(bad), fake, fake, 1 << 30, None)
+    assert rc == EINVAL and "attenuation" in lib.vct_last_error().decode()
+    bad = B.voxelize_params([((0.5, 0.9, 0.5), (1, 1, 1), (1, 0, 0))], ambient=-1.0)
+    rc = lib.vct_voxelize(ctypes.byref(g), fake, fake, 3, ctypes.byref(bad), fake, fake, 1 << 30, None)
+    assert rc == EINVAL and "ambient" in lib.vct_last_error().decode()
+    rc = lib.vct_voxelize(ctypes.byref(g), fake, fake, 3, ctypes.byref(good), fake, fake, 1000, None)
+    assert rc == EWORKSPACE and "workspace" in lib.vct_last_error().decode()
