@@ -5,3 +5,4 @@ cpu_baseline leg of bench.py, never by the library or its binding."""
 from .vct_oracle import (build_mips, mip_adjoint, taps, sample, cone_lanes, march,  # noqa: F401
                          assemble, trace, trace_backward, lane_grads, render)
 from .vct_shade import f_spec, shade, smoothstep  # noqa: F401
+from .vct_bounce import MIN_NORMAL, bounce, bounces, surface_mask  # noqa: F401

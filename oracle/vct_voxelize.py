@@ -36,6 +36,10 @@ V5  Direct light per fragment: colour * sum_l (ambient + diffuse max(0, N.L_l))
     centre at depth w mapped back to world units.
 V6  Triangles with a non-finite vertex, or a snapped coordinate beyond
     +-2^19 subpixel units, are skipped (the exact arithmetic's range).
+V7  Surface attributes (for further bounces, which need a texture of surface
+    normals): per voxel the average of its fragments' unit triangle normals
+    (not renormalized) and of their triangle colours, with w = 1 where a
+    fragment landed.
 """
 from __future__ import annotations
 
@@ -121,14 +125,17 @@ def fragments(tri_snapped, n):
 
 
 def voxelize(tris, colors, n, lights, ambient=0.1, diffuse=1.0, origin=(0.0, 0.0, 0.0), extent=1.0,
-             return_counts=False):
-    """Base grid [N, N, N, 4] float64 ([z][y][x][rgba]) of the mesh.
+             return_counts=False, return_surface=False):
+    """Base grid [N, N, N, 4] float64 ([z][y][x][rgba]) of the mesh; with
+    return_surface also the normal and albedo grids (V7).
 
     lights: sequence of (position[3], colour[3], attenuation (c, l, q))."""
     snapped, ok = snap(tris, n, origin, extent)
     tris64 = np.asarray(tris, dtype=np.float32).astype(np.float64)
     cols = np.asarray(colors, dtype=np.float32).astype(np.float64)
     acc = np.zeros((n, n, n, 3))
+    nacc = np.zeros((n, n, n, 3))
+    cacc = np.zeros((n, n, n, 3))
     cnt = np.zeros((n, n, n), dtype=np.int64)
     o = np.asarray(origin, dtype=np.float32).astype(np.float64)
     v0 = float(np.float32(extent)) / n
@@ -158,9 +165,21 @@ def voxelize(tris, colors, n, lights, ambient=0.1, diffuse=1.0, origin=(0.0, 0.0
         col *= cols[t][None, :]
         z, y, x = fr["vox"][2], fr["vox"][1], fr["vox"][0]
         np.add.at(acc, (z, y, x), col)
+        np.add.at(nacc, (z, y, x), np.broadcast_to(nn, col.shape))
+        np.add.at(cacc, (z, y, x), np.broadcast_to(cols[t], col.shape))
         np.add.at(cnt, (z, y, x), 1)
     out = np.zeros((n, n, n, 4))
     hit = cnt > 0
     out[hit, 0:3] = acc[hit] / cnt[hit][:, None]
     out[hit, 3] = 1.0
-    return (out, cnt) if return_counts else out
+    res = [out]
+    if return_counts:
+        res.append(cnt)
+    if return_surface:
+        nrm = np.zeros((n, n, n, 4))
+        alb = np.zeros((n, n, n, 4))
+        nrm[hit, 0:3] = nacc[hit] / cnt[hit][:, None]
+        alb[hit, 0:3] = cacc[hit] / cnt[hit][:, None]
+        nrm[hit, 3] = alb[hit, 3] = 1.0
+        res += [nrm, alb]
+    return tuple(res) if len(res) > 1 else out
