@@ -265,26 +265,62 @@ int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf
  * averaged (deterministic fixed-point sums and a count); other voxels are 0.
  * Triangles with a non-finite vertex or a snapped coordinate beyond 2^19 are
  * skipped; per-fragment colours are clamped to +-2^28.
+ * Optional surface attributes (the further 3D texture of surface normals that
+ * more light bounces need, Section 6.2.2; albedo and normal textures of
+ * deferred voxel cone tracing, Section 5.1.3): per voxel the average of its
+ * fragments' unit triangle normals (not renormalised: opposite faces in one
+ * voxel cancel) and of their triangle colours, w = 1 where a fragment landed,
+ * else all 0; same fixed-point averaging.
  *   tris       device float32 [n_tris][3][3] vertex positions, world units
  *   colors     device float32 [n_tris][3] triangle colours
  *   base       device float32 [N][N][N][4] premultiplied RGBA, overwritten (a vct_build_mips input)
- *   workspace  device, vct_voxelize_workspace_bytes(grid, n_tris) bytes (32 per voxel, 160 per triangle)
+ *   normal     device float32 [N][N][N][4] average normal, overwritten; or null (no surface attributes)
+ *   albedo     device float32 [N][N][N][4] average colour, overwritten; null exactly when normal is
+ *   workspace  device, vct_voxelize_workspace_bytes(grid, n_tris, surface) bytes (32 per voxel, 48 more
+ *              with surface attributes, 160 per triangle); surface != 0 sizes it for normal/albedo output
  * Errors: VCT_EINVAL for a bad grid, n_tris outside [0, 2^31), null buffers,
- * n_lights outside 0..8, non-finite or negative light parameters or
- * attenuation all 0; VCT_EWORKSPACE if the workspace is too small. */
-int vct_voxelize_workspace_bytes(const vct_grid* grid, int64_t n_tris, size_t* bytes);
+ * only one of normal / albedo given, n_lights outside 0..8, non-finite or
+ * negative light parameters or attenuation all 0; VCT_EWORKSPACE if the
+ * workspace is too small. */
+int vct_voxelize_workspace_bytes(const vct_grid* grid, int64_t n_tris, int32_t surface, size_t* bytes);
 int vct_voxelize(const vct_grid* grid, const float* tris, const float* colors, int64_t n_tris,
-                 const vct_voxelize_params* params, float* base, void* workspace, size_t workspace_bytes,
-                 hipStream_t stream);
+                 const vct_voxelize_params* params, float* base, float* normal, float* albedo, void* workspace,
+                 size_t workspace_bytes, hipStream_t stream);
+
+/* One further light bounce inside the voxel grid (Section 6.2.2 "Algorithm
+ * Limitations": more bounces need a texture of average surface normals, with
+ * cones traced again from the voxels hit about that normal; Sections 6.2.4
+ * and 5.1.3: indirect light inserted into a further 3D texture).  Every
+ * surface voxel -- base alpha > 0 and |normal.xyz| >= 1/100 -- traces the
+ * diffuse cones of `params` (frame, apertures, t0, step factor, max_dist,
+ * alpha_thresh and normal_offset as in vct_trace; specular and occlusion cones
+ * are not traced) from its centre about normalize(normal.xyz), through
+ * `pyramid`, and
+ *   out.rgb = base.rgb + base.a * albedo.rgb * sum_q w_q C_q,   out.a = base.a;
+ * every other voxel gets its base value.  For k bounces call it k times with
+ * the same base (the direct light) and the pyramid of the previous result.
+ *   pyramid    built by vct_build_mips for `grid` (e.g. from base, or from the previous bounce)
+ *   base       device float32 [N][N][N][4] premultiplied direct light, read only
+ *   normal     device float32 [N][N][N][4] average surface normal (xyz; w unused), read only
+ *   albedo     device float32 [N][N][N][4] surface colour (rgb; w unused), read only
+ *   out        device float32 [N][N][N][4], overwritten; may be base itself (in place), must not
+ *              overlap normal, albedo, pyramid or workspace otherwise
+ *   workspace  device, vct_bounce_workspace_bytes(grid) bytes (about 4.2 per voxel)
+ * Errors: VCT_EINVAL for a bad grid or cone parameters or a null pointer;
+ * VCT_EWORKSPACE if the workspace is too small. */
+int vct_bounce_workspace_bytes(const vct_grid* grid, size_t* bytes);
+int vct_bounce(const vct_grid* grid, const void* pyramid, const float* base, const float* normal,
+               const float* albedo, const vct_cone_params* params, float* out, void* workspace,
+               size_t workspace_bytes, hipStream_t stream);
 
 /* Diagnostics: per-kernel timing.  Registers `count` events (a host array of
  * hipEvent_t created by the caller) for the NEXT enqueuing call on this thread
- * (vct_build_mips, vct_trace, vct_count_samples or vct_trace_backward).  That
- * call records events[i] on its stream just before its i-th kernel and, after
- * its last kernel, records the next unused event; events beyond its kernel
- * count are left untouched.  Kernel order of vct_trace_backward: clear
- * accumulator, pass 1 (recompute), scale, pass 2 (re-march and scatter), mip
- * adjoint.  The registration is consumed by that call (also if it fails).
+ * (any entry point that enqueues kernels).  That call records events[i] on its
+ * stream just before its i-th kernel and, after its last kernel, records the
+ * next unused event; events beyond its kernel count are left untouched.
+ * Kernel order of vct_trace_backward: clear accumulator, pass 1 (recompute),
+ * scale, pass 2 (re-march and scatter), mip adjoint; of vct_bounce: flag,
+ * scan, list, gather.  The registration is consumed by that call (also if it fails).
  * count = 0 clears it.  Recording costs one hipEventRecord per kernel. */
 int vct_record_kernel_events(hipEvent_t* events, int32_t count);
 

@@ -75,16 +75,18 @@ def voxel_gbuffer(mask, normal_grid, origin=(0.0, 0.0, 0.0), extent=1.0, voxels=
 
 
 def bounce(base, normal_grid, albedo_grid, params, levels=None, origin=(0.0, 0.0, 0.0), extent=1.0,
-           gather_from=None, voxels=None, return_info=False):
+           gather_from=None, mips=None, voxels=None, return_info=False):
     """One bounce (B1-B3): [N, N, N, 4] float64.
 
     gather_from: the grid whose pyramid the cones march through (default
-    base; B4 passes the previous bounce).  voxels: optional [M, 3] (z, y, x)
+    base; B4 passes the previous bounce); mips: that pyramid given directly
+    (e.g. a decoded reduced-precision one).  voxels: optional [M, 3] (z, y, x)
     list; then only those voxels are computed and the result is their [M, 4]
     values (for sampled checks of large grids)."""
     base = np.asarray(base, dtype=np.float64)
-    src = base if gather_from is None else np.asarray(gather_from, dtype=np.float64)
-    mips = build_mips(src, levels)
+    if mips is None:
+        src = base if gather_from is None else np.asarray(gather_from, dtype=np.float64)
+        mips = build_mips(src, levels)
     mask = surface_mask(base, normal_grid)
     pr, nr, (z, y, x) = voxel_gbuffer(mask, normal_grid, origin, extent, voxels)
     # surface test of sampled voxels (all listed voxels are surface ones when voxels is None)

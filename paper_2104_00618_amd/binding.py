@@ -68,8 +68,10 @@ def lib():
         "vct_trace": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
         "vct_count_samples": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
         "vct_shade": [P(CGrid), vp, P(CGBuffer), vp, P(CConeParams), P(CShadeParams), vp, vp],
-        "vct_voxelize_workspace_bytes": [P(CGrid), ctypes.c_int64, P(sz)],
-        "vct_voxelize": [P(CGrid), vp, vp, ctypes.c_int64, P(CVoxelizeParams), vp, vp, sz, vp],
+        "vct_voxelize_workspace_bytes": [P(CGrid), ctypes.c_int64, ctypes.c_int32, P(sz)],
+        "vct_voxelize": [P(CGrid), vp, vp, ctypes.c_int64, P(CVoxelizeParams), vp, vp, vp, vp, sz, vp],
+        "vct_bounce_workspace_bytes": [P(CGrid), P(sz)],
+        "vct_bounce": [P(CGrid), vp, vp, vp, vp, P(CConeParams), vp, vp, sz, vp],
         "vct_backward_workspace_bytes": [P(CGrid), P(CGBuffer), P(CConeParams), P(sz)],
         "vct_trace_backward": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp, vp, sz, vp],
         "vct_lane_state_bytes": [P(CGBuffer), P(CConeParams), P(sz)],
@@ -361,30 +363,71 @@ def shade(pyramid, grid, pos_rough, normal, cam_pos, material, params, sparams, 
     return out
 
 
-def voxelize_workspace_bytes(grid, n_tris):
+def voxelize_workspace_bytes(grid, n_tris, surface=False):
     n = ctypes.c_size_t()
-    _check(lib().vct_voxelize_workspace_bytes(ctypes.byref(grid.c()), int(n_tris), ctypes.byref(n)))
+    _check(lib().vct_voxelize_workspace_bytes(ctypes.byref(grid.c()), int(n_tris), int(bool(surface)),
+                                              ctypes.byref(n)))
     return n.value
 
 
-def voxelize(tris, colors, grid, lights, ambient=0.1, diffuse=1.0, base=None, workspace=None):
+def voxelize(tris, colors, grid, lights, ambient=0.1, diffuse=1.0, base=None, workspace=None, surface=False,
+             normal=None, albedo=None):
     """Voxelize a triangle mesh (float32 [T, 3, 3] world positions, float32
     [T, 3] colours) with direct-light injection into a float32 base grid
-    [N, N, N, 4] (premultiplied RGBA)."""
+    [N, N, N, 4] (premultiplied RGBA).  With surface=True also the average
+    normal and colour grids; returns (base, normal, albedo) then."""
     dev = tris.device
+    shape = (grid.n, grid.n, grid.n, 4)
     _need(tris, "tris", torch.float32, (tris.shape[0], 3, 3), dev)
     _need(colors, "colors", torch.float32, (tris.shape[0], 3), dev)
     if base is None:
-        base = torch.empty((grid.n, grid.n, grid.n, 4), dtype=torch.float32, device=dev)
-    _need(base, "base", torch.float32, (grid.n, grid.n, grid.n, 4), dev)
+        base = torch.empty(shape, dtype=torch.float32, device=dev)
+    _need(base, "base", torch.float32, shape, dev)
+    if surface:
+        normal = torch.empty(shape, dtype=torch.float32, device=dev) if normal is None else normal
+        albedo = torch.empty(shape, dtype=torch.float32, device=dev) if albedo is None else albedo
+        _need(normal, "normal", torch.float32, shape, dev)
+        _need(albedo, "albedo", torch.float32, shape, dev)
+    else:
+        normal = albedo = None
     if workspace is None:
-        workspace = torch.empty(voxelize_workspace_bytes(grid, tris.shape[0]), dtype=torch.uint8, device=dev)
+        workspace = torch.empty(voxelize_workspace_bytes(grid, tris.shape[0], surface), dtype=torch.uint8,
+                                device=dev)
     _need(workspace, "workspace", torch.uint8, None, dev)
     with torch.cuda.device(dev):
         _check(lib().vct_voxelize(ctypes.byref(grid.c()), _ptr(tris), _ptr(colors), int(tris.shape[0]),
                                   ctypes.byref(voxelize_params(lights, ambient, diffuse)), _ptr(base),
-                                  _ptr(workspace), workspace.numel(), _stream(dev)))
-    return base
+                                  _ptr(normal), _ptr(albedo), _ptr(workspace), workspace.numel(), _stream(dev)))
+    return (base, normal, albedo) if surface else base
+
+
+def bounce_workspace_bytes(grid):
+    n = ctypes.c_size_t()
+    _check(lib().vct_bounce_workspace_bytes(ctypes.byref(grid.c()), ctypes.byref(n)))
+    return n.value
+
+
+def bounce(pyramid, grid, base, normal, albedo, params, out=None, workspace=None):
+    """One further bounce: from every surface voxel of `base` the diffuse
+    cones of `params` march through `pyramid`; returns float32 [N, N, N, 4]
+    = base + base.a * albedo * gathered light (other voxels: base).  `out`
+    may be `base` (in place)."""
+    dev = base.device
+    shape = (grid.n, grid.n, grid.n, 4)
+    _need(pyramid, "pyramid", torch.uint8, None, dev)
+    for t, nm in ((base, "base"), (normal, "normal"), (albedo, "albedo")):
+        _need(t, nm, torch.float32, shape, dev)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=dev)
+    _need(out, "out", torch.float32, shape, dev)
+    if workspace is None:
+        workspace = torch.empty(bounce_workspace_bytes(grid), dtype=torch.uint8, device=dev)
+    _need(workspace, "workspace", torch.uint8, None, dev)
+    with torch.cuda.device(dev):
+        _check(lib().vct_bounce(ctypes.byref(grid.c()), _ptr(pyramid), _ptr(base), _ptr(normal), _ptr(albedo),
+                                ctypes.byref(cone_params(params)), _ptr(out), _ptr(workspace), workspace.numel(),
+                                _stream(dev)))
+    return out
 
 
 def count_samples(pyramid, grid, pos_rough, normal, cam_pos, params):

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvct.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "mips.hip", "trace.hip", "backward.hip", "shade.hip", "voxelize.hip"]
+SOURCES = ["api.cpp", "mips.hip", "trace.hip", "backward.hip", "shade.hip", "voxelize.hip", "bounce.hip"]
 
 COMMON = ["-std=c++17", "-O3", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function"]
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

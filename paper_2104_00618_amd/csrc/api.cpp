@@ -289,20 +289,20 @@ int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf
     return VCT_OK;
 }
 
-int vct_voxelize_workspace_bytes(const vct_grid* grid, int64_t n_tris, size_t* bytes) {
+int vct_voxelize_workspace_bytes(const vct_grid* grid, int64_t n_tris, int32_t surface, size_t* bytes) {
     const char* fn = "vct_voxelize_workspace_bytes";
     if (int r = check_grid(fn, grid)) return r;
     if (n_tris < 0 || n_tris >= (int64_t(1) << 31))
         return fail(VCT_EINVAL, fn, "n_tris = %lld must be in [0, 2^31)", (long long)n_tris);
     if (!bytes) return fail(VCT_EINVAL, fn, "bytes is null");
-    *bytes = vct_voxelize_workspace_size(grid->n, n_tris);
+    *bytes = vct_voxelize_workspace_size(grid->n, n_tris, surface != 0);
     ok();
     return VCT_OK;
 }
 
 int vct_voxelize(const vct_grid* grid, const float* tris, const float* colors, int64_t n_tris,
-                 const vct_voxelize_params* params, float* base, void* workspace, size_t workspace_bytes,
-                 hipStream_t stream) {
+                 const vct_voxelize_params* params, float* base, float* normal, float* albedo, void* workspace,
+                 size_t workspace_bytes, hipStream_t stream) {
     const char* fn = "vct_voxelize";
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
@@ -324,10 +324,14 @@ int vct_voxelize(const vct_grid* grid, const float* tris, const float* colors, i
         return fail(VCT_EINVAL, fn, "ambient and diffuse must be finite and >= 0");
     if (!base || !workspace) return fail(VCT_EINVAL, fn, "base and workspace must be non-null");
     if (n_tris > 0 && (!tris || !colors)) return fail(VCT_EINVAL, fn, "tris and colors must be non-null");
-    const size_t need = vct_voxelize_workspace_size(grid->n, n_tris);
+    if ((normal == nullptr) != (albedo == nullptr))
+        return fail(VCT_EINVAL, fn, "normal and albedo must both be null or both be non-null");
+    const bool surface = normal != nullptr;
+    const size_t need = vct_voxelize_workspace_size(grid->n, n_tris, surface);
     if (workspace_bytes < need)
         return fail(VCT_EWORKSPACE, fn, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    hipError_t e = vct_launch_voxelize(grid, tris, colors, n_tris, params, base, workspace, stream, es);
+    hipError_t e = vct_launch_voxelize(grid, tris, colors, n_tris, params, base, normal, albedo, workspace, stream,
+                                       es);
     if (e != hipSuccess) return device_error(fn, e);
     ok();
     return VCT_OK;
@@ -428,6 +432,38 @@ int vct_trace_backward_saved(const vct_grid* grid, const void* pyramid, const vc
                              hipStream_t stream) {
     return backward_common("vct_trace_backward_saved", grid, pyramid, gbuf, params, lane_state, lane_state_bytes,
                            true, grad_out, grad_base, workspace, workspace_bytes, stream);
+}
+
+int vct_bounce_workspace_bytes(const vct_grid* grid, size_t* bytes) {
+    const char* fn = "vct_bounce_workspace_bytes";
+    if (int r = check_grid(fn, grid)) return r;
+    if (!bytes) return fail(VCT_EINVAL, fn, "bytes is null");
+    *bytes = vct_bounce_workspace_size(grid->n);
+    ok();
+    return VCT_OK;
+}
+
+int vct_bounce(const vct_grid* grid, const void* pyramid, const float* base, const float* normal,
+               const float* albedo, const vct_cone_params* params, float* out, void* workspace,
+               size_t workspace_bytes, hipStream_t stream) {
+    const char* fn = "vct_bounce";
+    EventSink es = take_events();
+    if (int r = check_grid(fn, grid)) return r;
+    if (int r = check_params(fn, grid, params)) return r;
+    if (!pyramid || !base || !normal || !albedo || !out || !workspace)
+        return fail(VCT_EINVAL, fn, "pyramid, base, normal, albedo, out and workspace must be non-null");
+    const size_t need = vct_bounce_workspace_size(grid->n);
+    if (workspace_bytes < need)
+        return fail(VCT_EWORKSPACE, fn, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    const vct_gbuffer none{};
+    TraceArgs a = make_args(grid, L, pyramid, &none, params);
+    a.enable_spec = 0;
+    a.enable_occ = 0;
+    hipError_t e = vct_launch_bounce(a, grid->dtype, base, normal, albedo, out, workspace, stream, es);
+    if (e != hipSuccess) return device_error(fn, e);
+    ok();
+    return VCT_OK;
 }
 
 int vct_record_kernel_events(hipEvent_t* events, int32_t count) {

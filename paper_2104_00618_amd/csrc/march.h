@@ -192,22 +192,13 @@ __device__ __forceinline__ df to_texel(const TraceArgs& a, float x, int ax) {
     return df_mul(d, sc);
 }
 
-__device__ __forceinline__ PixelSetup pixel_setup(const TraceArgs& a, float4 pr, float4 nr) {
-    PixelSetup P;
+// Unit normal and tangent frame of a cone origin (frame helper axis x if the
+// normal is near +-y, else y).
+__device__ __forceinline__ void set_frame(PixelSetup& P, float4 nr) {
     float3 n = normalize3(nr.x, nr.y, nr.z);
     P.nx = n.x;
     P.ny = n.y;
     P.nz = n.z;
-    P.px = pr.x;
-    P.py = pr.y;
-    P.pz = pr.z;
-    P.rough = pr.w;
-    // o = x + n * normal_offset * voxel  ->  texel units: (x - origin) * N/extent + n * normal_offset
-    df X = to_texel(a, pr.x, 0), Y = to_texel(a, pr.y, 1), Z = to_texel(a, pr.z, 2);
-    P.Ox = df_add(X, n.x * a.normal_offset);
-    P.Oy = df_add(Y, n.y * a.normal_offset);
-    P.Oz = df_add(Z, n.z * a.normal_offset);
-    // tangent frame: helper axis x if the normal is near +-y, else y
     float ax = 0.f, ay = 1.f;
     if (fabsf(n.y) > 0.9f) {
         ax = 1.f;
@@ -222,6 +213,24 @@ __device__ __forceinline__ PixelSetup pixel_setup(const TraceArgs& a, float4 pr,
     P.bx = n.y * t.z - n.z * t.y;
     P.by = n.z * t.x - n.x * t.z;
     P.bz = n.x * t.y - n.y * t.x;
+}
+
+// Cone origin offset from texel-space point X along the unit normal:
+// o = x + n * normal_offset * voxel, i.e. X + n * normal_offset in texel units.
+__device__ __forceinline__ void set_origin(const TraceArgs& a, PixelSetup& P, df X, df Y, df Z) {
+    P.Ox = df_add(X, P.nx * a.normal_offset);
+    P.Oy = df_add(Y, P.ny * a.normal_offset);
+    P.Oz = df_add(Z, P.nz * a.normal_offset);
+}
+
+__device__ __forceinline__ PixelSetup pixel_setup(const TraceArgs& a, float4 pr, float4 nr) {
+    PixelSetup P;
+    set_frame(P, nr);
+    P.px = pr.x;
+    P.py = pr.y;
+    P.pz = pr.z;
+    P.rough = pr.w;
+    set_origin(a, P, to_texel(a, pr.x, 0), to_texel(a, pr.y, 1), to_texel(a, pr.z, 2));
     return P;
 }
 

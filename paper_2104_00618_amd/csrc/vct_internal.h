@@ -122,10 +122,14 @@ hipError_t vct_launch_build_mips(const PyrLayout& L, const float* base, void* py
 hipError_t vct_launch_unpack(const PyrLayout& L, const void* pyr, int level, float* out, hipStream_t s);
 hipError_t vct_launch_trace(const TraceArgs& a, int dtype, float* out, unsigned long long* count,
                             hipStream_t s, EventSink& es);
-size_t vct_voxelize_acc_bytes(int n);
-size_t vct_voxelize_workspace_size(int n, long long n_tris);
+size_t vct_voxelize_acc_bytes(int n, bool surface);
+size_t vct_voxelize_workspace_size(int n, long long n_tris, bool surface);
 hipError_t vct_launch_voxelize(const vct_grid* g, const float* tris, const float* colors, long long n_tris,
-                               const vct_voxelize_params* p, float* base, void* ws, hipStream_t s, EventSink& es);
+                               const vct_voxelize_params* p, float* base, float* normal, float* albedo, void* ws,
+                               hipStream_t s, EventSink& es);
+size_t vct_bounce_workspace_size(int n);
+hipError_t vct_launch_bounce(const TraceArgs& a, int dtype, const float* base, const float* normal,
+                             const float* albedo, float* out, void* ws, hipStream_t s, EventSink& es);
 hipError_t vct_launch_shade(const TraceArgs& a, int dtype, const vct_shade_params* p, const float* material,
                             float* out, hipStream_t s, EventSink& es);
 

@@ -13,13 +13,20 @@
 // fixed-point sums and a count, so the result does not depend on the order in
 // which fragments arrive.
 //
+// Surface attributes (optional): per voxel the average of the fragments' unit
+// triangle normals and of their triangle colours, through the same kind of
+// fixed-point sums (a further 3D texture of surface normals is what more light
+// bounces need, Section 6.2.2; deferred voxel cone tracing keeps albedo and
+// normal textures from voxelization, Section 5.1.3).
+//
 // Launch: a setup pass (one thread per triangle) writes each triangle's
 // rasterization record and its number of 256-pixel chunks, one workgroup
 // scans the chunk counts, and the raster pass hands (triangle, chunk) items to
 // waves in a grid-stride loop, so a wall-sized triangle is spread over many
 // waves.  Per voxel the workspace holds {int64 r, g, b; uint32 count; pad}
-// (32 bytes), cleared by a fill kernel (no memset, so the path can be captured
-// in a graph); a resolve pass writes the float32 base grid.
+// (32 bytes), and with surface attributes {int64 nx, ny, nz, r, g, b} (48 bytes)
+// more, cleared by a fill kernel (no memset, so the path can be captured in a
+// graph); a resolve pass writes the float32 grids.
 #include "vct_internal.h"
 
 namespace {
@@ -44,6 +51,10 @@ struct VoxArgs {
 struct VoxAcc {
     unsigned long long r, g, b;
     unsigned int count, pad;
+};
+
+struct SurfAcc {
+    unsigned long long n[3], c[3];
 };
 
 __global__ void k_clear(uint4* __restrict__ p, size_t n) {
@@ -200,10 +211,11 @@ __device__ __forceinline__ long long floor_div_est(long long a, long long b) {
 // Work items are (triangle, chunk of kChunk pixels); each wave takes items
 // k = wave, wave + n_waves, ... below the total and finds the triangle by a
 // binary search of the chunk offsets.
+template <bool SURF>
 __global__ __launch_bounds__(256) void k_raster(VoxArgs a, const TriSetup* __restrict__ setup,
                                                 const unsigned long long* __restrict__ offs, long long n_tris,
                                                 const unsigned long long* __restrict__ total_p,
-                                                VoxAcc* __restrict__ acc) {
+                                                VoxAcc* __restrict__ acc, SurfAcc* __restrict__ surf) {
     const int lane = threadIdx.x & 63;
     const unsigned long long n_waves = (unsigned long long)gridDim.x * (blockDim.x >> 6);
     const unsigned long long total = *total_p;
@@ -258,41 +270,67 @@ __global__ __launch_bounds__(256) void k_raster(VoxArgs a, const TriSetup* __res
                 lg += kk * a.light_color[l][1];
                 lb += kk * a.light_color[l][2];
             }
-            VoxAcc* q = acc + (size_t)((v[2] * a.n + v[1]) * a.n + v[0]);
+            const size_t vi = (size_t)((v[2] * a.n + v[1]) * a.n + v[0]);
+            VoxAcc* q = acc + vi;
             atomicAdd(&q->r, to_fixed(lr * r.col[0]));
             atomicAdd(&q->g, to_fixed(lg * r.col[1]));
             atomicAdd(&q->b, to_fixed(lb * r.col[2]));
             atomicAdd(&q->count, 1u);
+            if constexpr (SURF) {
+                SurfAcc* u = surf + vi;
+                for (int i = 0; i < 3; ++i) {
+                    atomicAdd(&u->n[i], to_fixed(r.n[i]));
+                    atomicAdd(&u->c[i], to_fixed(r.col[i]));
+                }
+            }
         }
     }
 }
 
-__global__ __launch_bounds__(256) void k_resolve(const VoxAcc* __restrict__ acc, float4* __restrict__ base,
-                                                 size_t n) {
+template <bool SURF>
+__global__ __launch_bounds__(256) void k_resolve(const VoxAcc* __restrict__ acc, const SurfAcc* __restrict__ surf,
+                                                 float4* __restrict__ base, float4* __restrict__ normal,
+                                                 float4* __restrict__ albedo, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const VoxAcc q = acc[i];
         float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (q.count) {
-            const float inv = 1.0f / ((float)q.count * kFix);
+        const float inv = q.count ? 1.0f / ((float)q.count * kFix) : 0.0f;
+        if (q.count)
             o = make_float4((float)(long long)q.r * inv, (float)(long long)q.g * inv, (float)(long long)q.b * inv,
                             1.0f);
-        }
         base[i] = o;
+        if constexpr (SURF) {
+            const SurfAcc u = surf[i];
+            float4 nn = make_float4(0.f, 0.f, 0.f, 0.f), cc = nn;
+            if (q.count) {
+                nn = make_float4((float)(long long)u.n[0] * inv, (float)(long long)u.n[1] * inv,
+                                 (float)(long long)u.n[2] * inv, 1.0f);
+                cc = make_float4((float)(long long)u.c[0] * inv, (float)(long long)u.c[1] * inv,
+                                 (float)(long long)u.c[2] * inv, 1.0f);
+            }
+            normal[i] = nn;
+            albedo[i] = cc;
+        }
     }
 }
 
 }  // namespace
 
-// Workspace: the per-voxel accumulators, then per-triangle setup records, the
-// chunk offsets and the chunk total.
-size_t vct_voxelize_acc_bytes(int n) { return (size_t)n * n * n * sizeof(VoxAcc); }
+// Workspace: the per-voxel accumulators (with surface attributes, their sums
+// follow), then per-triangle setup records, the chunk offsets and the chunk
+// total.
+size_t vct_voxelize_acc_bytes(int n, bool surface) {
+    return (size_t)n * n * n * (sizeof(VoxAcc) + (surface ? sizeof(SurfAcc) : 0));
+}
 
-size_t vct_voxelize_workspace_size(int n, long long n_tris) {
-    return vct_voxelize_acc_bytes(n) + (size_t)n_tris * (sizeof(TriSetup) + 8) + 256;
+size_t vct_voxelize_workspace_size(int n, long long n_tris, bool surface) {
+    return vct_voxelize_acc_bytes(n, surface) + (size_t)n_tris * (sizeof(TriSetup) + 8) + 256;
 }
 
 hipError_t vct_launch_voxelize(const vct_grid* g, const float* tris, const float* colors, long long n_tris,
-                               const vct_voxelize_params* p, float* base, void* ws, hipStream_t st, EventSink& es) {
+                               const vct_voxelize_params* p, float* base, float* normal, float* albedo, void* ws,
+                               hipStream_t st, EventSink& es) {
+    const bool surface = normal != nullptr;
     VoxArgs a{};
     a.n = g->n;
     for (int i = 0; i < 3; ++i) a.origin[i] = g->origin[i];
@@ -310,23 +348,34 @@ hipError_t vct_launch_voxelize(const vct_grid* g, const float* tris, const float
     const size_t nvox = (size_t)g->n * g->n * g->n;
     char* w = static_cast<char*>(ws);
     VoxAcc* acc = reinterpret_cast<VoxAcc*>(w);
-    TriSetup* setup = reinterpret_cast<TriSetup*>(w + vct_voxelize_acc_bytes(g->n));
+    SurfAcc* surf = surface ? reinterpret_cast<SurfAcc*>(acc + nvox) : nullptr;
+    const size_t acc_bytes = vct_voxelize_acc_bytes(g->n, surface);
+    TriSetup* setup = reinterpret_cast<TriSetup*>(w + acc_bytes);
     unsigned long long* offs = reinterpret_cast<unsigned long long*>(setup + n_tris);
     unsigned long long* total = offs + n_tris;
-    const int fill_blocks = (int)min((nvox * sizeof(VoxAcc) / 16 + 255) / 256, (size_t)65536);
+    const int fill_blocks = (int)min((acc_bytes / 16 + 255) / 256, (size_t)65536);
     es.mark(st);
-    hipLaunchKernelGGL(k_clear, dim3(fill_blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(ws),
-                       nvox * sizeof(VoxAcc) / 16);
+    hipLaunchKernelGGL(k_clear, dim3(fill_blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(ws), acc_bytes / 16);
     es.mark(st);
     if (n_tris > 0) {
         hipLaunchKernelGGL(k_tri_setup, dim3((unsigned)((n_tris + 255) / 256)), dim3(256), 0, st, a, tris, colors,
                            n_tris, setup, offs);
         hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(256), 0, st, offs, n_tris, total);
-        hipLaunchKernelGGL(k_raster, dim3(2048), dim3(256), 0, st, a, setup, offs, n_tris, total, acc);
+        if (surface)
+            hipLaunchKernelGGL(k_raster<true>, dim3(2048), dim3(256), 0, st, a, setup, offs, n_tris, total, acc, surf);
+        else
+            hipLaunchKernelGGL(k_raster<false>, dim3(2048), dim3(256), 0, st, a, setup, offs, n_tris, total, acc,
+                               surf);
     }
     es.mark(st);
     const int res_blocks = (int)min((nvox + 255) / 256, (size_t)65536);
-    hipLaunchKernelGGL(k_resolve, dim3(res_blocks), dim3(256), 0, st, acc, reinterpret_cast<float4*>(base), nvox);
+    if (surface)
+        hipLaunchKernelGGL(k_resolve<true>, dim3(res_blocks), dim3(256), 0, st, acc, surf,
+                           reinterpret_cast<float4*>(base), reinterpret_cast<float4*>(normal),
+                           reinterpret_cast<float4*>(albedo), nvox);
+    else
+        hipLaunchKernelGGL(k_resolve<false>, dim3(res_blocks), dim3(256), 0, st, acc, surf,
+                           reinterpret_cast<float4*>(base), nullptr, nullptr, nvox);
     es.mark(st);
     return hipGetLastError();
 }

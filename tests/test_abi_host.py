@@ -358,24 +358,58 @@ def test_voxelize_validation_and_workspace_size():
     lib = vct.lib()
     g = vct.Grid(32).c()
     n = ctypes.c_size_t()
-    assert lib.vct_voxelize_workspace_bytes(ctypes.byref(g), 0, ctypes.byref(n)) == 0 and n.value >= 32 ** 3 * 32
+    assert lib.vct_voxelize_workspace_bytes(ctypes.byref(g), 0, 0, ctypes.byref(n)) == 0 and n.value >= 32 ** 3 * 32
     n0 = n.value
-    assert lib.vct_voxelize_workspace_bytes(ctypes.byref(g), 10, ctypes.byref(n)) == 0 and n.value > n0
+    assert lib.vct_voxelize_workspace_bytes(ctypes.byref(g), 10, 0, ctypes.byref(n)) == 0 and n.value > n0
+    assert lib.vct_voxelize_workspace_bytes(ctypes.byref(g), 0, 1, ctypes.byref(n)) == 0
+    assert n.value == n0 + 32 ** 3 * 48                     # surface sums: 48 more bytes per voxel
     good = B.voxelize_params([((0.5, 0.9, 0.5), (1, 1, 1), (1, 0, 0))])
     fake = ctypes.c_void_p(0x1000)
     cases = [(dict(n_tris=-1), "n_tris"), (dict(n_tris=1 << 31), "n_tris"), (dict(base=None), "non-null"),
-             (dict(tris=None), "non-null")]
+             (dict(tris=None), "non-null"), (dict(normal=fake), "both"), (dict(albedo=fake), "both")]
     for kw, msg in cases:
-        args = dict(tris=fake, colors=fake, n_tris=3, base=fake, ws=fake, ws_bytes=1 << 30)
+        args = dict(tris=fake, colors=fake, n_tris=3, base=fake, normal=None, albedo=None, ws=fake, ws_bytes=1 << 30)
         args.update(kw)
         rc = lib.vct_voxelize(ctypes.byref(g), args["tris"], args["colors"], args["n_tris"], ctypes.byref(good),
-                              args["base"], args["ws"], args["ws_bytes"], None)
+                              args["base"], args["normal"], args["albedo"], args["ws"], args["ws_bytes"], None)
         assert rc == EINVAL and msg in lib.vct_last_error().decode(), (kw, lib.vct_last_error())
     bad = B.voxelize_params([((0.5, 0.9, 0.5), (1, 1, 1), (0, 0, 0))])
-    rc = lib.vct_voxelize(ctypes.byref(g), fake, fake, 3, ctypes.byref(bad), fake, fake, 1 << 30, None)
+    rc = lib.vct_voxelize(ctypes.byref(g), fake, fake, 3, ctypes.byref(bad), fake, None, None, fake, 1 << 30, None)
     assert rc == EINVAL and "attenuation" in lib.vct_last_error().decode()
     bad = B.voxelize_params([((0.5, 0.9, 0.5), (1, 1, 1), (1, 0, 0))], ambient=-1.0)
-    rc = lib.vct_voxelize(ctypes.byref(g), fake, fake, 3, ctypes.byref(bad), fake, fake, 1 << 30, None)
+    rc = lib.vct_voxelize(ctypes.byref(g), fake, fake, 3, ctypes.byref(bad), fake, None, None, fake, 1 << 30, None)
     assert rc == EINVAL and "ambient" in lib.vct_last_error().decode()
-    rc = lib.vct_voxelize(ctypes.byref(g), fake, fake, 3, ctypes.byref(good), fake, fake, 1000, None)
+    rc = lib.vct_voxelize(ctypes.byref(g), fake, fake, 3, ctypes.byref(good), fake, None, None, fake, 1000, None)
     assert rc == EWORKSPACE and "workspace" in lib.vct_last_error().decode()
+    # the surface outputs need the larger workspace
+    lib.vct_voxelize_workspace_bytes(ctypes.byref(g), 3, 0, ctypes.byref(n))
+    rc = lib.vct_voxelize(ctypes.byref(g), fake, fake, 3, ctypes.byref(good), fake, fake, fake, fake, n.value, None)
+    assert rc == EWORKSPACE and "workspace" in lib.vct_last_error().decode()
+
+
+def test_bounce_validation_and_workspace_size():
+    lib = vct.lib()
+    g = vct.Grid(64).c()
+    n = ctypes.c_size_t()
+    assert lib.vct_bounce_workspace_bytes(ctypes.byref(g), ctypes.byref(n)) == 0
+    nvox = 64 ** 3
+    # list (4 B per voxel) + one mask bit per voxel + a count per 4096 voxels, 256-byte aligned pieces
+    assert nvox * 4 + nvox // 8 <= n.value <= nvox * 4 + nvox // 8 + 4 * 256 + 4 * (nvox // 4096)
+    need = n.value
+    p = B.cone_params(_params())
+    fake = ctypes.c_void_p(0x1000)
+    names = ["pyramid", "base", "normal", "albedo", "out", "ws"]
+    for k in names:
+        args = {nm: fake for nm in names}
+        args[k] = None
+        rc = lib.vct_bounce(ctypes.byref(g), args["pyramid"], args["base"], args["normal"], args["albedo"],
+                            ctypes.byref(p), args["out"], args["ws"], need, None)
+        assert rc == EINVAL and "non-null" in lib.vct_last_error().decode(), k
+    rc = lib.vct_bounce(ctypes.byref(g), fake, fake, fake, fake, ctypes.byref(p), fake, fake, need - 1, None)
+    assert rc == EWORKSPACE and "workspace" in lib.vct_last_error().decode()
+    bad = B.cone_params(_params().replace(step_factor=0.0))
+    rc = lib.vct_bounce(ctypes.byref(g), fake, fake, fake, fake, ctypes.byref(bad), fake, fake, need, None)
+    assert rc == EINVAL and "step_factor" in lib.vct_last_error().decode()
+    g.n = 48
+    rc = lib.vct_bounce(ctypes.byref(g), fake, fake, fake, fake, ctypes.byref(p), fake, fake, need, None)
+    assert rc == EINVAL and "power of two" in lib.vct_last_error().decode()

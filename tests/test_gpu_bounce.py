@@ -1,0 +1,218 @@
+"""GPU further bounce (vct_bounce) and the voxelizer's surface attributes
+against the FP64 oracles: surface normal and albedo grids, the bounced grid
+(untouched voxels bit-exact, the added light within 1e-5 of its range for
+float32 pyramids), in place, repeated bounces, tiny and degenerate grids, and
+sampled voxels of the 256^3 launch."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import vct_bounce as vb
+from oracle import vct_voxelize as vx
+import paper_2104_00618_amd as vct
+from scenes import ConeParams, cone_set
+from scenes.mesh import cornell_mesh
+from tests.parity import fmt, range_errors, worst
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+LIGHTS = [((0.5, 0.95, 0.5), (1.0, 1.0, 1.0), (1.0, 0.5, 0.25)), ((0.2, 0.6, 0.8), (0.4, 0.3, 0.2), (1.0, 0.0, 0.0))]
+TOL = {"f32": 1e-5, "f16": 2e-3}
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def params(kind="five", **kw):
+    d, w = cone_set(kind)
+    return ConeParams(d, w, alpha_thresh=0.99, **kw)
+
+
+def scene(n, seed):
+    """Oracle-voxelized Cornell mesh: float32 base, normal and albedo grids."""
+    tris, cols = cornell_mesh(seed)
+    base, nrm, alb = vx.voxelize(tris, cols, n, LIGHTS, return_surface=True)
+    return base.astype(np.float32), nrm.astype(np.float32), alb.astype(np.float32)
+
+
+def near_threshold(nrm):
+    """Voxels whose normal length is within float rounding of the cut (B1)."""
+    ln = np.linalg.norm(nrm[..., 0:3].astype(np.float64), axis=-1)
+    return np.abs(ln - vb.MIN_NORMAL) < 1e-6
+
+
+def gpu_bounce(base, nrm, alb, p, n, dtype="f32", levels=None, gather=None):
+    g = vct.Grid(n, levels=levels, dtype=dtype)
+    pyr = vct.build_mips(dev(base if gather is None else gather), g)
+    out = vct.bounce(pyr, g, dev(base), dev(nrm), dev(alb), p)
+    return host(out), pyr, g
+
+
+def check_bounce(got, ref, base, amb, tol, label, require_light=True):
+    changed = ref[..., 0:3] != base[..., 0:3]
+    keep = ~amb
+    # voxels that the oracle leaves alone are copied bit for bit
+    same = ~changed.any(-1) & keep
+    assert np.array_equal(got[same].view(np.uint32), base[same].view(np.uint32)), label
+    np.testing.assert_array_equal(got[..., 3], base[..., 3])
+    inc_g = (got[..., 0:3] - base[..., 0:3]).reshape(-1, 3)
+    inc_r = (ref[..., 0:3] - base[..., 0:3].astype(np.float64)).reshape(-1, 3)
+    e = range_errors(inc_g, inc_r, keep.reshape(-1))
+    print(f"{label}: {int(changed.any(-1).sum())} lit voxels, {int(amb.sum())} ambiguous; added light {fmt(e)}",
+          flush=True)
+    assert worst(e)[0] <= tol, label
+    assert changed.any() or not require_light, label
+
+
+# ----------------------------------------------------------- surface grids
+@pytest.mark.parametrize("n,seed", [(64, 1), (256, 2)])
+def test_voxelize_surface_attributes_match_oracle(n, seed):
+    tris, cols = cornell_mesh(seed)
+    rng = np.random.default_rng(seed)
+    extra = rng.uniform(-0.2, 1.2, size=(40, 3, 3)).astype(np.float32)
+    tris = np.concatenate([tris, extra])
+    cols = np.concatenate([cols, rng.uniform(0, 1, size=(40, 3)).astype(np.float32)])
+    base, nrm, alb = vct.voxelize(dev(tris), dev(cols), vct.Grid(n), LIGHTS, surface=True)
+    base, nrm, alb = host(base), host(nrm), host(alb)
+    rb, cnt, rn, ra = vx.voxelize(tris, cols, n, LIGHTS, return_counts=True, return_surface=True)
+    hit = cnt > 0
+    np.testing.assert_array_equal(base[..., 3], hit.astype(np.float32))
+    np.testing.assert_array_equal(nrm[..., 3], hit.astype(np.float32))
+    np.testing.assert_array_equal(alb[..., 3], hit.astype(np.float32))
+    en = np.abs(nrm[..., 0:3] - rn[..., 0:3]).max()          # unit-vector averages: absolute error
+    ea = np.abs(alb[..., 0:3] - ra[..., 0:3]).max() / np.abs(ra[..., 0:3]).max()
+    eb = np.abs(base[..., 0:3] - rb[..., 0:3]).max() / np.abs(rb[..., 0:3]).max()
+    print(f"voxelize surface {n}^3: normal max abs {en:.2e}, albedo max rel {ea:.2e}, light max rel {eb:.2e}",
+          flush=True)
+    assert en <= 1e-6 and ea <= 1e-6 and eb <= 1e-5
+    # the plain call gives the same light grid bit for bit
+    plain = host(vct.voxelize(dev(tris), dev(cols), vct.Grid(n), LIGHTS))
+    assert np.array_equal(plain.view(np.uint32), base.view(np.uint32))
+
+
+# ------------------------------------------------------------------ bounce
+@pytest.mark.parametrize("n,seed,kind", [(32, 3, "six"), (64, 4, "five")])
+def test_bounce_matches_oracle(n, seed, kind):
+    base, nrm, alb = scene(n, seed)
+    p = params(kind)
+    got, _, _ = gpu_bounce(base, nrm, alb, p, n)
+    ref, info = vb.bounce(base, nrm, alb, p, return_info=True)
+    check_bounce(got, ref, base, info["ambiguous"] | near_threshold(nrm), TOL["f32"], f"bounce {n}^3 {kind}")
+
+
+def test_bounce_reduced_precision_pyramid():
+    n = 64
+    base, nrm, alb = scene(n, 5)
+    p = params()
+    got, pyr, g = gpu_bounce(base, nrm, alb, p, n, dtype="f16")
+    decoded = [vct.unpack_level(pyr, g, lv).cpu().numpy().astype(np.float64) for lv in range(g.levels)]
+    ref, info = vb.bounce(base, nrm, alb, p, mips=decoded, return_info=True)
+    check_bounce(got, ref, base, info["ambiguous"] | near_threshold(nrm), TOL["f32"], "bounce f16 path parity")
+    ref64, info64 = vb.bounce(base, nrm, alb, p, return_info=True)
+    check_bounce(got, ref64, base, info["ambiguous"] | info64["ambiguous"] | near_threshold(nrm), TOL["f16"],
+                 "bounce f16 storage")
+
+
+def test_bounce_in_place_and_partial_pyramid():
+    n = 32
+    base, nrm, alb = scene(n, 6)
+    p = params("six", max_dist=0.6, normal_offset=1.5)
+    g = vct.Grid(n, levels=3)
+    pyr = vct.build_mips(dev(base), g)
+    out = vct.bounce(pyr, g, dev(base), dev(nrm), dev(alb), p)
+    inplace = dev(base)
+    vct.bounce(pyr, g, inplace, dev(nrm), dev(alb), p, out=inplace)
+    a, b = host(out), host(inplace)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    ref, info = vb.bounce(base, nrm, alb, p, levels=3, return_info=True)
+    check_bounce(a, ref, base, info["ambiguous"] | near_threshold(nrm), TOL["f32"], "bounce 32^3 3 levels")
+
+
+def test_two_bounces_match_oracle():
+    n = 32
+    base, nrm, alb = scene(n, 7)
+    alb = np.clip(alb * 1.5, 0, 1).astype(np.float32)
+    p = params("six")
+    g = vct.Grid(n)
+    cur = dev(base)
+    for _ in range(2):
+        pyr = vct.build_mips(cur, g)
+        cur = vct.bounce(pyr, g, dev(base), dev(nrm), dev(alb), p)
+    got = host(cur)
+    ref1, i1 = vb.bounce(base, nrm, alb, p, return_info=True)
+    ref2, i2 = vb.bounce(base, nrm, alb, p, gather_from=ref1, return_info=True)
+    np.testing.assert_allclose(ref2, vb.bounces(base, nrm, alb, p, 2), rtol=0, atol=0)
+    # the second gather sees the first bounce's float32 rounding: same tolerance on the added light
+    check_bounce(got, ref2, base, i1["ambiguous"] | i2["ambiguous"] | near_threshold(nrm), 2 * TOL["f32"],
+                 "two bounces 32^3")
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16])
+def test_bounce_tiny_grids(n):
+    """Grids below one 64-voxel mask word and one 4096-voxel compaction block."""
+    rng = np.random.default_rng(n)
+    base = np.zeros((n, n, n, 4), np.float32)
+    solid = rng.uniform(size=(n, n, n)) < 0.4
+    base[solid, 3] = rng.choice([0.5, 1.0], size=solid.sum())
+    base[solid, 0:3] = rng.uniform(0, 1, size=(solid.sum(), 3)) * base[solid, 3:4]
+    nrm = np.zeros_like(base)
+    nrm[..., 0:3] = rng.normal(size=(n, n, n, 3))
+    alb = np.zeros_like(base)
+    alb[..., 0:3] = rng.uniform(0.2, 0.9, size=(n, n, n, 3))
+    p = params("six", max_dist=2.0, normal_offset=0.5)
+    got, _, _ = gpu_bounce(base, nrm, alb, p, n)
+    ref, info = vb.bounce(base, nrm, alb, p, return_info=True)
+    check_bounce(got, ref, base, info["ambiguous"] | near_threshold(nrm), TOL["f32"], f"bounce {n}^3",
+                 require_light=n >= 4)
+
+
+def test_bounce_empty_full_and_coneless_grids():
+    n = 16
+    p = params("six")
+    empty = np.zeros((n, n, n, 4), np.float32)
+    nrm = np.zeros_like(empty)
+    nrm[..., 1] = 1.0
+    alb = np.full_like(empty, 0.5)
+    got, _, _ = gpu_bounce(empty, nrm, alb, p, n)
+    assert not got.any()
+    # every voxel a surface voxel: the list is the whole grid
+    full = np.zeros_like(empty)
+    full[...] = (0.1, 0.2, 0.3, 0.25)
+    got, _, _ = gpu_bounce(full, nrm, alb, p, n)
+    ref, info = vb.bounce(full, nrm, alb, p, return_info=True)
+    check_bounce(got, ref, full, info["ambiguous"], TOL["f32"], "bounce full 16^3")
+    # no diffuse cones: a copy
+    base, nrm2, alb2 = scene(32, 8)
+    p0 = ConeParams(np.zeros((0, 3), np.float32), np.zeros(0, np.float32))
+    got, _, _ = gpu_bounce(base, nrm2, alb2, p0, 32)
+    assert np.array_equal(got.view(np.uint32), base.view(np.uint32))
+
+
+def test_bounce_full_launch_sampled_voxels():
+    """256^3 (the bench launch): GPU voxelize with surface attributes, bounce,
+    and the oracle on a seeded sample of surface voxels of its own grids."""
+    n = 256
+    tris, cols = cornell_mesh(1)
+    rb, rn, ra = (a.astype(np.float32) for a in vx.voxelize(tris, cols, n, LIGHTS, return_surface=True))
+    p = params()
+    got, _, _ = gpu_bounce(rb, rn, ra, p, n)
+    surf = np.argwhere(vb.surface_mask(rb, rn))
+    rng = np.random.default_rng(11)
+    pick = surf[rng.choice(len(surf), size=600, replace=False)]
+    ref, amb = vb.bounce(rb, rn, ra, p, voxels=pick, return_info=True)
+    z, y, x = pick[:, 0], pick[:, 1], pick[:, 2]
+    amb |= near_threshold(rn)[z, y, x]
+    inc_g = got[z, y, x, 0:3] - rb[z, y, x, 0:3]
+    inc_r = ref[:, 0:3] - rb[z, y, x, 0:3].astype(np.float64)
+    e = range_errors(inc_g, inc_r, ~amb)
+    print(f"bounce 256^3: {len(surf)} surface voxels, 600 sampled ({int(amb.sum())} ambiguous): {fmt(e)}", flush=True)
+    assert worst(e)[0] <= TOL["f32"]
+    untouched = ~vb.surface_mask(rb, rn)
+    assert np.array_equal(got[untouched].view(np.uint32), rb[untouched].view(np.uint32))
