@@ -107,6 +107,63 @@ def cpu_baseline(w, n_pix=24576, seed=0):
                       f"({info['samples']} samples, {dt:.1f} s, NumPy FP64, single thread)"}
 
 
+BOUNCE_KERNELS = ["flag + copy", "scan", "list", "gather"]
+
+
+def bench_bounce(vct, torch, grid, vt, vc, vlights, params, timed, steps):
+    """One further bounce at the grid of the step: voxelize the Cornell mesh
+    with surface normal and albedo grids, build the direct-light pyramid,
+    bounce (surface voxels re-gather through it), and build the pyramid of the
+    bounced grid for the final gather."""
+    dev = vt.device
+    n = grid.n
+    shape = (n, n, n, 4)
+    vbase, vnrm, valb, bout = (torch.empty(shape, dtype=torch.float32, device=dev) for _ in range(4))
+    vws = torch.empty(vct.voxelize_workspace_bytes(grid, vt.shape[0], surface=True), dtype=torch.uint8, device=dev)
+    vox_ms = timed(lambda: vct.voxelize(vt, vc, grid, vlights, base=vbase, workspace=vws, surface=True,
+                                        normal=vnrm, albedo=valb), steps)
+    del vws
+    vpyr = vct.build_mips(vbase, grid)
+    bws = torch.empty(vct.bounce_workspace_bytes(grid), dtype=torch.uint8, device=dev)
+    bounce_ms = timed(lambda: vct.bounce(vpyr, grid, vbase, vnrm, valb, params, out=bout, workspace=bws), steps)
+    kev = [vct.KernelEvents(len(BOUNCE_KERNELS) + 1) for _ in range(steps)]
+    for k in kev:
+        k.arm()
+        vct.bounce(vpyr, grid, vbase, vnrm, valb, params, out=bout, workspace=bws)
+    torch.cuda.synchronize()
+    kms = np.mean([k.times() for k in kev], axis=0)
+    remip_ms = timed(lambda: vct.build_mips(bout, grid, vpyr), steps)
+    # cone samples of the bounce: the surface voxels as a one-row G-buffer (centres (i + 1/2) / N are exact
+    # in float32 for this power-of-two grid over the unit cube, so the march and its count are the bounce's)
+    a = vbase[..., 3] > 0
+    nn = vnrm[..., 0:3]
+    live = a & ((nn * nn).sum(-1) >= 1e-4)
+    idx = torch.nonzero(live)                      # (z, y, x)
+    m = int(idx.shape[0])
+    rows = (m + 1023) // 1024                      # 1024-wide rows, the tail padded with background pixels
+    pr = torch.zeros((rows * 1024, 4), device=dev)
+    nr = torch.zeros((rows * 1024, 4), device=dev)
+    pr[:m, 0:3] = (idx.flip(1).to(torch.float32) + 0.5) / n
+    nr[:m, 0:3] = vnrm[live][:, 0:3]
+    nr[:m, 3] = 1.0
+    pr, nr = pr.reshape(1, rows, 1024, 4), nr.reshape(1, rows, 1024, 4)
+    cam = torch.zeros((1, 3), device=dev)
+    vct.build_mips(vbase, grid, vpyr)              # the direct-light pyramid the bounce marched through
+    samples = vct.count_samples(vpyr, grid, pr, nr, cam, params.replace(enable_spec=False, enable_occ=False))
+    flag_bytes = n ** 3 * 16 * 2                   # base read + copy written (out is not base here)
+    res = {"surface_voxels": m, "cones_per_voxel": params.n_diffuse, "samples": samples,
+           "voxelize_with_surface_ms": vox_ms, "bounce_ms": bounce_ms,
+           "bounce_kernels_ms": {k: float(t) for k, t in zip(BOUNCE_KERNELS, kms)},
+           "remip_ms": remip_ms, "voxelize_mips_bounce_mips_ms": vox_ms + 2 * remip_ms + bounce_ms,
+           "gather_samples_per_s": samples / (kms[3] * 1e-3),
+           "gather_frac_of_alu_peak": FLOPS_FWD_SAMPLE * samples / (kms[3] * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+           "flag_GBps": flag_bytes / (kms[0] * 1e-3) / 1e9,
+           "flag_frac_of_hbm_peak": flag_bytes / (kms[0] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    log(f"bounce: {m} surface voxels, {samples} samples; voxelize+surface {vox_ms:.3f} ms, bounce {bounce_ms:.3f} ms "
+        f"({', '.join(f'{k} {t:.3f}' for k, t in zip(BOUNCE_KERNELS, kms))}), re-mip {remip_ms:.3f} ms")
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -219,6 +276,7 @@ def main():
     del vws
     log(f"trace alone {fwd_ms:.3f} ms; recompute path step {mips_ms + fwd_ms + recompute_bwd_ms:.3f} ms; "
         f"shade {', '.join(f'{k} {v:.3f} ms' for k, v in shade_ms.items())}; voxelize {vox_ms:.3f} ms")
+    bounce = bench_bounce(vct, torch, grid, vt, vc, vlights, w.params, timed, args.steps)
 
     texel_bytes = 16 if args.dtype == "f32" else 8
     trace_bytes = samples * 16 * texel_bytes + npix * 64
@@ -228,7 +286,9 @@ def main():
         "trace_backward_saved_kernels_ms": {n: float(t) for n, t in zip(BWD_KERNELS, bwd_k)},
         "trace_ms": fwd_ms, "fwd_ms_per_frame": mips_ms + fwd_ms,
         "shade_ms": shade_ms,
-        "revoxelize": {"triangles": vox_tris, "voxelize_ms": vox_ms, "voxelize_plus_mips_ms": vox_ms + mips_ms}, "fwd_bwd_ms_per_frame": mips_ms + save_ms + bwd_ms,
+        "revoxelize": {"triangles": vox_tris, "voxelize_ms": vox_ms, "voxelize_plus_mips_ms": vox_ms + mips_ms},
+        "bounce": bounce,
+        "fwd_bwd_ms_per_frame": mips_ms + save_ms + bwd_ms,
         "recompute_path": {"trace_backward_ms": recompute_bwd_ms,
                            "fwd_bwd_ms_per_frame": mips_ms + fwd_ms + recompute_bwd_ms},
         "samples_per_frame": samples, "samples_per_pixel": samples / npix,

@@ -305,7 +305,10 @@ int vct_voxelize(const vct_grid* grid, const float* tris, const float* colors, i
  *   albedo     device float32 [N][N][N][4] surface colour (rgb; w unused), read only
  *   out        device float32 [N][N][N][4], overwritten; may be base itself (in place), must not
  *              overlap normal, albedo, pyramid or workspace otherwise
- *   workspace  device, vct_bounce_workspace_bytes(grid) bytes (about 4.2 per voxel)
+ *   workspace  device, vct_bounce_workspace_bytes(grid) bytes (about 4.1 per voxel: a list entry for
+ *              every voxel that could be a surface voxel, and a flag bit)
+ * The cones' terms are summed in cone order, as in vct_trace's D, so the result
+ * is the same on every run.
  * Errors: VCT_EINVAL for a bad grid or cone parameters or a null pointer;
  * VCT_EWORKSPACE if the workspace is too small. */
 int vct_bounce_workspace_bytes(const vct_grid* grid, size_t* bytes);

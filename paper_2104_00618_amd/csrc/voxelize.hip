@@ -300,9 +300,9 @@ __global__ __launch_bounds__(256) void k_resolve(const VoxAcc* __restrict__ acc,
                             1.0f);
         base[i] = o;
         if constexpr (SURF) {
-            const SurfAcc u = surf[i];
             float4 nn = make_float4(0.f, 0.f, 0.f, 0.f), cc = nn;
-            if (q.count) {
+            if (q.count) {                               // empty voxels (most of them) never read their sums
+                const SurfAcc u = surf[i];
                 nn = make_float4((float)(long long)u.n[0] * inv, (float)(long long)u.n[1] * inv,
                                  (float)(long long)u.n[2] * inv, 1.0f);
                 cc = make_float4((float)(long long)u.c[0] * inv, (float)(long long)u.c[1] * inv,

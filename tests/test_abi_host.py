@@ -393,8 +393,10 @@ def test_bounce_validation_and_workspace_size():
     n = ctypes.c_size_t()
     assert lib.vct_bounce_workspace_bytes(ctypes.byref(g), ctypes.byref(n)) == 0
     nvox = 64 ** 3
-    # list (4 B per voxel) + one mask bit per voxel + a count per 4096 voxels, 256-byte aligned pieces
-    assert nvox * 4 + nvox // 8 <= n.value <= nvox * 4 + nvox // 8 + 4 * 256 + 4 * (nvox // 4096)
+    # list (4 B per voxel) + one mask bit per voxel + a count per 4096 voxels + 8 counters on lines of
+    # their own, 256-byte aligned pieces
+    lo = nvox * 4 + nvox // 8
+    assert lo <= n.value <= lo + 4 * 256 + 2048 + 4 * (nvox // 4096)
     need = n.value
     p = B.cone_params(_params())
     fake = ctypes.c_void_p(0x1000)
