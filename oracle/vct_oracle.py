@@ -226,11 +226,12 @@ def cone_lanes(pos_rough, normal, cam_pos, params, n, origin=(0.0, 0.0, 0.0), ex
 # cone march (Section 4.3.2, cone-trace function)
 # ---------------------------------------------------------------------------
 
-def march(mips, lanes, params, origin=(0.0, 0.0, 0.0), extent=1.0, record=False):
+def march(mips, lanes, params, origin=(0.0, 0.0, 0.0), extent=1.0, record=False, sampler=None):
     """Volume ray march of every lane.  Returns dict with c [m,3], alpha [m],
     K [m] (samples taken), ambiguous [m] (a termination decision within the
     tie band), and, if record, the per-step list of (lane idx, t, d, lam,
-    alpha before, sample)."""
+    alpha before, sample).  sampler(p, lam, w) replaces the isotropic
+    quadrilinear sample when given (w: the lanes' unit axes)."""
     n0 = mips[0].shape[0]
     nlev = len(mips)
     v0 = extent / n0
@@ -258,7 +259,7 @@ def march(mips, lanes, params, origin=(0.0, 0.0, 0.0), extent=1.0, record=False)
         d = np.maximum(2.0 * ti * np.tan(gamma[idx] / 2.0), v0)       # sampling diameter
         lam = np.clip(np.log2(d / v0), 0.0, nlev - 1)                  # LOD (R2)
         p = x[idx] + ti[:, None] * w[idx]                               # sampling position
-        s = sample(mips, p, lam, origin, extent)
+        s = sample(mips, p, lam, origin, extent) if sampler is None else sampler(p, lam, w[idx])
         a_prev = alpha[idx]
         if record:
             steps.append((idx, ti, d, lam, a_prev.copy(), s))
