@@ -277,6 +277,19 @@ def main():
     log(f"trace alone {fwd_ms:.3f} ms; recompute path step {mips_ms + fwd_ms + recompute_bwd_ms:.3f} ms; "
         f"shade {', '.join(f'{k} {v:.3f} ms' for k, v in shade_ms.items())}; voxelize {vox_ms:.3f} ms")
     bounce = bench_bounce(vct, torch, grid, vt, vc, vlights, w.params, timed, args.steps)
+    # the same frame through an anisotropic (six-direction) pyramid
+    ga = vct.Grid(w.n, dtype=args.dtype, anisotropic=True)
+    pa = torch.empty(vct.pyramid_bytes(ga), dtype=torch.uint8, device=dev)
+    amips_ms = timed(lambda: vct.build_mips(base, ga, pa), args.steps)
+    atrace_ms = timed(lambda: vct.trace(pa, ga, pr, nr, cam, w.params, out), args.steps)
+    asamples = vct.count_samples(pa, ga, pr, nr, cam, w.params)
+    aniso = {"pyramid_bytes": int(pa.numel()), "isotropic_pyramid_bytes": int(pyr.numel()),
+             "build_mips_ms": amips_ms, "trace_ms": atrace_ms, "samples_per_frame": asamples,
+             "trace_samples_per_s": asamples / (atrace_ms * 1e-3), "fwd_ms_per_frame": amips_ms + atrace_ms,
+             "trace_slowdown_vs_isotropic": atrace_ms / fwd_ms}
+    del pa
+    log(f"anisotropic: mips {amips_ms:.3f} ms, trace {atrace_ms:.3f} ms ({asamples} samples, "
+        f"{atrace_ms / fwd_ms:.2f}x the isotropic trace)")
 
     texel_bytes = 16 if args.dtype == "f32" else 8
     trace_bytes = samples * 16 * texel_bytes + npix * 64
@@ -288,6 +301,7 @@ def main():
         "shade_ms": shade_ms,
         "revoxelize": {"triangles": vox_tris, "voxelize_ms": vox_ms, "voxelize_plus_mips_ms": vox_ms + mips_ms},
         "bounce": bounce,
+        "anisotropic": aniso,
         "fwd_bwd_ms_per_frame": mips_ms + save_ms + bwd_ms,
         "recompute_path": {"trace_backward_ms": recompute_bwd_ms,
                            "fwd_bwd_ms_per_frame": mips_ms + fwd_ms + recompute_bwd_ms},

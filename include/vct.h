@@ -66,6 +66,9 @@ typedef struct {
     int32_t dtype;     /* vct_dtype of the pyramid storage */
     float origin[3];   /* world position of the grid's minimum corner */
     float extent;      /* side length of the grid cube, world units, finite and > 0 */
+    int32_t anisotropic; /* 0: one pyramid of 2x2x2 means; 1: six directional pyramids sharing level 0
+                            (see vct_build_mips); only vct_build_mips, vct_unpack_level(_dir), vct_trace
+                            and vct_count_samples accept 1, the others return VCT_EUNSUPPORTED */
 } vct_grid;
 
 /* Deferred-shading G-buffer: one cone origin per pixel (Section 5.1.3 adopts
@@ -151,12 +154,30 @@ int vct_pyramid_bytes(const vct_grid* grid, size_t* bytes);
  *   pyramid_bytes its size (VCT_EWORKSPACE if too small) */
 int vct_build_mips(const vct_grid* grid, const float* base, void* pyramid, size_t pyramid_bytes,
                    hipStream_t stream);
+/* Anisotropic pyramids (grid->anisotropic = 1; the mipmaps built with
+ * anisotropic filtering of Section 5.1.3, "Villegas"): six pyramids, one per
+ * direction +x, -x, +y, -y, +z, -z, sharing level 0 = base.  A texel of level
+ * l + 1 in direction d composites its two children along the axis of d front
+ * to back as seen by a ray travelling along d (c = c_f + (1 - a_f) c_b on all
+ * four premultiplied channels; "+x" puts the smaller-x child in front) and
+ * averages the four pairs ((p0 + p1) + (p2 + p3)) / 4 in float32.  Level 1 is
+ * computed from the float32 base; level l + 1 >= 2 from the stored level l (so
+ * for float16 / bfloat16 storage it is rounded once per level).  A cone with
+ * unit axis w samples sum_a w_a^2 * (quadrilinear sample of the pyramid of
+ * direction sign(w_a) along axis a); at level 0 all six coincide.  Storage:
+ * level 0 plus six copies of levels 1..L-1 (about 1.86x the base for full
+ * pyramids, vct_pyramid_bytes). */
 
 /* Copy level `level` of a built pyramid out as logical float32
  * [N_l][N_l][N_l][4] (test and inspection hook; the thesis's
  * VoxelMap::retrieveData, Section 5.4.4). */
 int vct_unpack_level(const vct_grid* grid, const void* pyramid, int32_t level, float* out,
                      hipStream_t stream);
+/* Same for one direction of an anisotropic pyramid: direction 0..5 = +x, -x,
+ * +y, -y, +z, -z (level 0 is the same for all six).  For an isotropic grid
+ * direction must be 0 and this equals vct_unpack_level. */
+int vct_unpack_level_dir(const vct_grid* grid, const void* pyramid, int32_t level, int32_t direction,
+                         float* out, hipStream_t stream);
 
 /* Forward cone trace (Section 4.3.2 cone-trace function; sampler of Section
  * 4.5; cone set of Sections 4.2 and 5.4.4).  For every pixel with valid != 0:

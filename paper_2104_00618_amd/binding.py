@@ -28,7 +28,7 @@ class VctError(RuntimeError):
 
 class CGrid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("levels", ctypes.c_int32), ("dtype", ctypes.c_int32),
-                ("origin", ctypes.c_float * 3), ("extent", ctypes.c_float)]
+                ("origin", ctypes.c_float * 3), ("extent", ctypes.c_float), ("anisotropic", ctypes.c_int32)]
 
 
 class CGBuffer(ctypes.Structure):
@@ -65,6 +65,7 @@ def lib():
         "vct_pyramid_bytes": [P(CGrid), P(sz)],
         "vct_build_mips": [P(CGrid), vp, vp, sz, vp],
         "vct_unpack_level": [P(CGrid), vp, ctypes.c_int32, vp, vp],
+        "vct_unpack_level_dir": [P(CGrid), vp, ctypes.c_int32, ctypes.c_int32, vp, vp],
         "vct_trace": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
         "vct_count_samples": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
         "vct_shade": [P(CGrid), vp, P(CGBuffer), vp, P(CConeParams), P(CShadeParams), vp, vp],
@@ -154,12 +155,13 @@ def _check(rc):
 class Grid:
     """Grid descriptor: N^3 base texels over [origin, origin + extent]^3."""
 
-    def __init__(self, n, levels=None, dtype="f32", origin=(0.0, 0.0, 0.0), extent=1.0):
+    def __init__(self, n, levels=None, dtype="f32", origin=(0.0, 0.0, 0.0), extent=1.0, anisotropic=False):
         self.n = int(n)
         self.levels = int(levels) if levels is not None else int(round(math.log2(max(self.n, 1)))) + 1
         self.dtype = dtype
         self.origin = tuple(float(v) for v in origin)
         self.extent = float(extent)
+        self.anisotropic = bool(anisotropic)
 
     def c(self):
         g = CGrid()
@@ -169,6 +171,7 @@ class Grid:
         for i in range(3):
             g.origin[i] = self.origin[i]
         g.extent = self.extent
+        g.anisotropic = 1 if self.anisotropic else 0
         return g
 
 
@@ -330,6 +333,17 @@ def unpack_level(pyramid, grid, level):
     with torch.cuda.device(pyramid.device):
         _check(lib().vct_unpack_level(ctypes.byref(grid.c()), _ptr(pyramid), int(level), _ptr(out),
                                       _stream(pyramid.device)))
+    return out
+
+
+def unpack_level_dir(pyramid, grid, level, direction):
+    """Level `level` of direction `direction` (0..5 = +x, -x, +y, -y, +z, -z)
+    of an anisotropic pyramid as float32 [N_l, N_l, N_l, 4]."""
+    nl = grid.n >> level
+    out = torch.empty((nl, nl, nl, 4), dtype=torch.float32, device=pyramid.device)
+    with torch.cuda.device(pyramid.device):
+        _check(lib().vct_unpack_level_dir(ctypes.byref(grid.c()), _ptr(pyramid), int(level), int(direction),
+                                          _ptr(out), _stream(pyramid.device)))
     return out
 
 

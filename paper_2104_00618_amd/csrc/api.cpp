@@ -55,6 +55,16 @@ int check_grid(const char* fn, const vct_grid* g) {
         if (!finite(g->origin[i])) return fail(VCT_EINVAL, fn, "grid origin[%d] is not finite", i);
     if (!finite(g->extent) || !(g->extent > 0.f))
         return fail(VCT_EINVAL, fn, "grid extent must be finite and > 0");
+    if (g->anisotropic != 0 && g->anisotropic != 1)
+        return fail(VCT_EINVAL, fn, "grid anisotropic = %d must be 0 or 1", g->anisotropic);
+    return VCT_OK;
+}
+
+// Entry points whose kernels sample isotropic pyramids only.
+int check_isotropic(const char* fn, const vct_grid* g) {
+    if (g->anisotropic)
+        return fail(VCT_EUNSUPPORTED, fn, "anisotropic pyramids are supported by vct_build_mips, vct_unpack_level(_dir), "
+                    "vct_trace and vct_count_samples only");
     return VCT_OK;
 }
 
@@ -135,6 +145,11 @@ TraceArgs make_args(const vct_grid* g, const PyrLayout& L, const void* pyr, cons
     }
     a.pyr = pyr;
     a.rsrc = vct_pyr_rsrc(pyr, g->dtype == VCT_F32 ? 16 : 8, (uint32_t)L.total_texels);
+    for (int d = 0; d < 6; ++d)
+        for (int l = 0; l < VCT_MAX_LEVELS; ++l)
+            a.ddelta[d][l] = l < g->levels ? (uint32_t)(L.doff[d][l] - L.off[l]) : 0u;
+    a.inv_scale2 = (float)(((double)g->extent / g->n) * ((double)g->extent / g->n));
+    a.aniso = g->anisotropic ? 1 : 0;
     a.b = gb->b;
     a.h = gb->h;
     a.w = gb->w;
@@ -180,7 +195,7 @@ int vct_pyramid_bytes(const vct_grid* grid, size_t* bytes) {
     const char* fn = "vct_pyramid_bytes";
     if (int r = check_grid(fn, grid)) return r;
     if (!bytes) return fail(VCT_EINVAL, fn, "bytes is null");
-    *bytes = (size_t)vct_make_layout(grid->n, grid->levels, grid->dtype).bytes;
+    *bytes = (size_t)vct_make_layout(grid->n, grid->levels, grid->dtype, grid->anisotropic).bytes;
     ok();
     return VCT_OK;
 }
@@ -191,7 +206,7 @@ int vct_build_mips(const vct_grid* grid, const float* base, void* pyramid, size_
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
     if (!base || !pyramid) return fail(VCT_EINVAL, fn, "base and pyramid must be non-null");
-    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype, grid->anisotropic);
     if (pyramid_bytes < (size_t)L.bytes)
         return fail(VCT_EWORKSPACE, fn, "pyramid buffer has %zu bytes, needs %lld", pyramid_bytes,
                     (long long)L.bytes);
@@ -201,17 +216,28 @@ int vct_build_mips(const vct_grid* grid, const float* base, void* pyramid, size_
     return VCT_OK;
 }
 
-int vct_unpack_level(const vct_grid* grid, const void* pyramid, int32_t level, float* out, hipStream_t stream) {
-    const char* fn = "vct_unpack_level";
+static int unpack_common(const char* fn, const vct_grid* grid, const void* pyramid, int32_t level, int32_t direction,
+                         float* out, hipStream_t stream) {
     if (int r = check_grid(fn, grid)) return r;
     if (!pyramid || !out) return fail(VCT_EINVAL, fn, "pyramid and out must be non-null");
     if (level < 0 || level >= grid->levels)
         return fail(VCT_EINVAL, fn, "level = %d must be in [0, %d]", level, grid->levels - 1);
-    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
-    hipError_t e = vct_launch_unpack(L, pyramid, level, out, stream);
+    if (direction < 0 || direction >= (grid->anisotropic ? 6 : 1))
+        return fail(VCT_EINVAL, fn, "direction = %d must be in [0, %d]", direction, grid->anisotropic ? 5 : 0);
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype, grid->anisotropic);
+    hipError_t e = vct_launch_unpack(L, pyramid, level, direction, out, stream);
     if (e != hipSuccess) return device_error(fn, e);
     ok();
     return VCT_OK;
+}
+
+int vct_unpack_level(const vct_grid* grid, const void* pyramid, int32_t level, float* out, hipStream_t stream) {
+    return unpack_common("vct_unpack_level", grid, pyramid, level, 0, out, stream);
+}
+
+int vct_unpack_level_dir(const vct_grid* grid, const void* pyramid, int32_t level, int32_t direction, float* out,
+                         hipStream_t stream) {
+    return unpack_common("vct_unpack_level_dir", grid, pyramid, level, direction, out, stream);
 }
 
 static int trace_common(const char* fn, const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
@@ -225,7 +251,7 @@ static int trace_common(const char* fn, const vct_grid* grid, const void* pyrami
     if (counting && !count) return fail(VCT_EINVAL, fn, "count is null");
     if (!counting && !out && np > 0) return fail(VCT_EINVAL, fn, "out is null");
     if (!pyramid) return fail(VCT_EINVAL, fn, "pyramid is null");
-    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype, grid->anisotropic);
     TraceArgs a = make_args(grid, L, pyramid, gbuf, params);
     if (a.n_tiles == 0 && !count) {
         ok();
@@ -252,6 +278,7 @@ int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf
     const char* fn = "vct_shade";
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
+    if (int r = check_isotropic(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
     if (int r = check_params(fn, grid, params)) return r;
     if (!shade) return fail(VCT_EINVAL, fn, "shade is null");
@@ -277,7 +304,7 @@ int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf
     long long np = (long long)gbuf->b * gbuf->h * gbuf->w;
     if (np > 0 && (!pyramid || !material || !out))
         return fail(VCT_EINVAL, fn, "pyramid, material and out must be non-null");
-    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype, grid->anisotropic);
     TraceArgs a = make_args(grid, L, pyramid, gbuf, params);
     if (a.n_tiles == 0) {
         ok();
@@ -341,10 +368,11 @@ int vct_backward_workspace_bytes(const vct_grid* grid, const vct_gbuffer* gbuf, 
                                  size_t* bytes) {
     const char* fn = "vct_backward_workspace_bytes";
     if (int r = check_grid(fn, grid)) return r;
+    if (int r = check_isotropic(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
     if (int r = check_params(fn, grid, params)) return r;
     if (!bytes) return fail(VCT_EINVAL, fn, "bytes is null");
-    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype, grid->anisotropic);
     TraceArgs a = make_args(grid, L, nullptr, gbuf, params);
     *bytes = (size_t)vct_plan_backward(L, a).bytes;
     ok();
@@ -369,6 +397,7 @@ int vct_trace_save(const vct_grid* grid, const void* pyramid, const vct_gbuffer*
     const char* fn = "vct_trace_save";
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
+    if (int r = check_isotropic(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
     if (int r = check_params(fn, grid, params)) return r;
     long long np = (long long)gbuf->b * gbuf->h * gbuf->w;
@@ -377,7 +406,7 @@ int vct_trace_save(const vct_grid* grid, const void* pyramid, const vct_gbuffer*
     int64_t need = vct_lane_state_bytes(np * (params->n_diffuse + 2));
     if (lane_state_bytes < (size_t)need)
         return fail(VCT_EWORKSPACE, fn, "lane_state has %zu bytes, needs %lld", lane_state_bytes, (long long)need);
-    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype, grid->anisotropic);
     TraceArgs a = make_args(grid, L, pyramid, gbuf, params);
     hipError_t e = vct_launch_trace_save(a, grid->dtype, out, lane_state, stream, es);
     if (e != hipSuccess) return device_error(fn, e);
@@ -391,6 +420,7 @@ static int backward_common(const char* fn, const vct_grid* grid, const void* pyr
                            size_t workspace_bytes, hipStream_t stream) {
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
+    if (int r = check_isotropic(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
     if (int r = check_params(fn, grid, params)) return r;
     if (!(params->alpha_thresh <= 1.0f))
@@ -400,7 +430,7 @@ static int backward_common(const char* fn, const vct_grid* grid, const void* pyr
         return fail(VCT_EINVAL, fn, "pyramid, grad_base and workspace must be non-null");
     long long np = (long long)gbuf->b * gbuf->h * gbuf->w;
     if (np > 0 && !grad_out) return fail(VCT_EINVAL, fn, "grad_out is null");
-    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype, grid->anisotropic);
     TraceArgs a = make_args(grid, L, pyramid, gbuf, params);
     BackwardPlan P = vct_plan_backward(L, a);
     const int64_t need = saved ? P.state_off : P.bytes;
@@ -449,13 +479,14 @@ int vct_bounce(const vct_grid* grid, const void* pyramid, const float* base, con
     const char* fn = "vct_bounce";
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
+    if (int r = check_isotropic(fn, grid)) return r;
     if (int r = check_params(fn, grid, params)) return r;
     if (!pyramid || !base || !normal || !albedo || !out || !workspace)
         return fail(VCT_EINVAL, fn, "pyramid, base, normal, albedo, out and workspace must be non-null");
     const size_t need = vct_bounce_workspace_size(grid->n);
     if (workspace_bytes < need)
         return fail(VCT_EWORKSPACE, fn, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype);
+    PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype, grid->anisotropic);
     const vct_gbuffer none{};
     TraceArgs a = make_args(grid, L, pyramid, &none, params);
     a.enable_spec = 0;

@@ -13,6 +13,8 @@
 // dw / (2 tan(aperture / 2)) texels of the sampled level.
 #pragma once
 
+#include <type_traits>
+
 #include "texel.h"
 #include "vct_internal.h"
 
@@ -147,6 +149,28 @@ __device__ __forceinline__ void level_taps(const LevelTable& T, int l, df Ux, df
     }
 }
 
+// Anisotropic pyramids: per direction and level, the texel offset relative to
+// the +x pyramid's level (which is what LevelTable::off holds); 0 at level 0.
+struct DirTable {
+    uint32_t delta[6][VCT_MAX_LEVELS];
+};
+
+// LDS slot of the table: a DirTable in anisotropic kernels, an empty struct otherwise.
+struct NoDirTable {};
+template <bool ANISO>
+using DirSlot = typename std::conditional<ANISO, DirTable, NoDirTable>::type;
+__device__ __forceinline__ const DirTable* dir_ptr(const DirTable& t) { return &t; }
+__device__ __forceinline__ const DirTable* dir_ptr(const NoDirTable&) { return nullptr; }
+__device__ __forceinline__ void load_dir_table(const TraceArgs&, NoDirTable*) {}
+
+__device__ __forceinline__ void load_dir_table(const TraceArgs& a, DirTable* t) {
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+#pragma unroll
+        for (int l = 0; l < VCT_MAX_LEVELS; ++l)
+            if ((int)threadIdx.x == d * VCT_MAX_LEVELS + l) t->delta[d][l] = a.ddelta[d][l];
+}
+
 template <int DT>
 __device__ __forceinline__ float4 gather(const vct_v4i& rsrc, const Taps& tp) {
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -276,22 +300,52 @@ __device__ __forceinline__ Cone cone_for_slot(const TraceArgs& a, const PixelSet
     return make_cone(a, P, w, a.occ_aperture, fminf(a.max_dist, dist));
 }
 
+// Trilinear sample of level l.  Anisotropic pyramids above level 0: the sum
+// over the three axes of w_a^2 times the sample of the direction sign(w_a)
+// (the taps are the same in every direction, only the level's offset moves);
+// axes with w_a = 0 are skipped.
+template <int DT, bool ANISO>
+__device__ __forceinline__ float4 level_sample(const TraceArgs& a, const LevelTable& T, const DirTable* D,
+                                               const Cone& c, int l, df Ux, df Uy, df Uz) {
+    Taps tp;
+    level_taps(T, l, Ux, Uy, Uz, tp);
+    if constexpr (ANISO) {
+        if (l > 0) {
+            const float W[3] = {c.Wx, c.Wy, c.Wz};
+            float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const float wt = W[ax] * W[ax] * a.inv_scale2;
+                if (wt == 0.0f) continue;
+                const uint32_t delta = D->delta[2 * ax + (W[ax] < 0.0f ? 1 : 0)][l];
+                Taps td = tp;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) td.idx[q] += delta;
+                const float4 g = gather<DT>(a.rsrc, td);
+                s.x = __builtin_fmaf(wt, g.x, s.x);
+                s.y = __builtin_fmaf(wt, g.y, s.y);
+                s.z = __builtin_fmaf(wt, g.z, s.z);
+                s.w = __builtin_fmaf(wt, g.w, s.w);
+            }
+            return s;
+        }
+    }
+    return gather<DT>(a.rsrc, tp);
+}
+
 // Quadrilinear sample at distance t along the cone.
-template <int DT>
+template <int DT, bool ANISO = false>
 __device__ __forceinline__ float4 sample_at(const TraceArgs& a, const LevelTable& T, const Cone& c, df t,
-                                            float lam) {
+                                            float lam, const DirTable* D = nullptr) {
     df Ux = df_axis(c.Ox, t, c.Wx);
     df Uy = df_axis(c.Oy, t, c.Wy);
     df Uz = df_axis(c.Oz, t, c.Wz);
     int l0 = (int)lam;
     float f = lam - (float)l0;
-    Taps tp;
-    level_taps(T, l0, Ux, Uy, Uz, tp);
-    float4 s0 = gather<DT>(a.rsrc, tp);
+    float4 s0 = level_sample<DT, ANISO>(a, T, D, c, l0, Ux, Uy, Uz);
     if (f > 0.0f) {
         int l1 = min(l0 + 1, a.levels - 1);
-        level_taps(T, l1, Ux, Uy, Uz, tp);
-        float4 s1 = gather<DT>(a.rsrc, tp);
+        float4 s1 = level_sample<DT, ANISO>(a, T, D, c, l1, Ux, Uy, Uz);
         float g = 1.0f - f;
         s0.x = __builtin_fmaf(f, s1.x, g * s0.x);
         s0.y = __builtin_fmaf(f, s1.y, g * s0.y);
@@ -312,15 +366,16 @@ struct MarchResult {
 
 // Forward march of one cone (Section 4.3.2): sample while t <= t_max and
 // A < alpha_thresh; C += (1 - A) s.rgb, A += (1 - A) s.a, t += beta d.
-template <int DT>
-__device__ __forceinline__ MarchResult march(const TraceArgs& a, const LevelTable& T, const Cone& c) {
+template <int DT, bool ANISO = false>
+__device__ __forceinline__ MarchResult march(const TraceArgs& a, const LevelTable& T, const Cone& c,
+                                             const DirTable* D = nullptr) {
     MarchResult m = {0.f, 0.f, 0.f, 0.f, 0};
     df t = {a.t0, 0.0f};
     for (int k = 0; k < a.max_steps; ++k) {
         if (!t_within(t, c.tmax) || !(m.a < a.alpha_thresh)) break;
         float d = fmaxf(c.two_tan * t.hi, a.voxel);
         float lam = lod_of(a, d);
-        float4 s = sample_at<DT>(a, T, c, t, lam);
+        float4 s = sample_at<DT, ANISO>(a, T, c, t, lam, D);
         float tr = 1.0f - m.a;
         m.r = __builtin_fmaf(tr, s.x, m.r);
         m.g = __builtin_fmaf(tr, s.y, m.g);
@@ -334,9 +389,10 @@ __device__ __forceinline__ MarchResult march(const TraceArgs& a, const LevelTabl
 
 // All cones of one pixel (slots 0..u-1 diffuse, specular, occlusion); the
 // 8-float epilogue (D.rgb, D.a, S.rgb, O) goes to o0, o1, the sample count to k.
-template <int DT>
+template <int DT, bool ANISO = false>
 __device__ __forceinline__ void trace_pixel(const TraceArgs& a, const LevelTable& T, int view, size_t pix,
-                                            float4& o0, float4& o1, unsigned int& ksum) {
+                                            float4& o0, float4& o1, unsigned int& ksum,
+                                            const DirTable* D = nullptr) {
     o0 = make_float4(0.f, 0.f, 0.f, 0.f);
     o1 = o0;
     ksum = 0;
@@ -347,7 +403,7 @@ __device__ __forceinline__ void trace_pixel(const TraceArgs& a, const LevelTable
     float3 cam = make_float3(a.cam_pos[3 * view], a.cam_pos[3 * view + 1], a.cam_pos[3 * view + 2]);
     for (int q = 0; q < a.n_diffuse; ++q) {
         Cone c = cone_for_slot(a, P, q, cam);
-        MarchResult m = march<DT>(a, T, c);
+        MarchResult m = march<DT, ANISO>(a, T, c, D);
         float wq = a.weight[q];
         o0.x = __builtin_fmaf(wq, m.r, o0.x);
         o0.y = __builtin_fmaf(wq, m.g, o0.y);
@@ -357,7 +413,7 @@ __device__ __forceinline__ void trace_pixel(const TraceArgs& a, const LevelTable
     }
     if (a.enable_spec) {
         Cone c = cone_for_slot(a, P, a.n_diffuse, cam);
-        MarchResult m = march<DT>(a, T, c);
+        MarchResult m = march<DT, ANISO>(a, T, c, D);
         o1.x = m.r;
         o1.y = m.g;
         o1.z = m.b;
@@ -365,7 +421,7 @@ __device__ __forceinline__ void trace_pixel(const TraceArgs& a, const LevelTable
     }
     if (a.enable_occ) {
         Cone c = cone_for_slot(a, P, a.n_diffuse + 1, cam);
-        MarchResult m = march<DT>(a, T, c);
+        MarchResult m = march<DT, ANISO>(a, T, c, D);
         o1.w = m.a;
         ksum += m.k;
     }

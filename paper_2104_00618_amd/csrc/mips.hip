@@ -102,6 +102,103 @@ __global__ __launch_bounds__(kThreads) void k_mip_block(MipPass p) {
     }
 }
 
+// Anisotropic levels (Section 5.1.3: mipmaps built with anisotropic
+// filtering).  One thread per texel of level l >= 1, visited brick by brick,
+// computes the texel for all six directions: for direction d it composites the
+// two children along d's axis front to back as a ray travelling along d meets
+// them (v = f + (1 - f.a) b on the four premultiplied channels) and averages
+// the four pairs.  Level 1 reads the float32 base (and stores it as level 0);
+// higher levels read the stored level below of the same direction.
+struct AnisoPass {
+    const float4* base;      // float32 logical [N][N][N] (level 1 only)
+    void* pyr;
+    int32_t level, side, nb, nb_child, n_base;
+    uint32_t dst[6];         // texel offset of the produced level, per direction
+    uint32_t src[6];         // texel offset of the level below, per direction (level 0: all 0)
+};
+
+__device__ __forceinline__ float4 over(float4 f, float4 b) {
+    const float t = 1.0f - f.w;
+    return make_float4(__builtin_fmaf(t, b.x, f.x), __builtin_fmaf(t, b.y, f.y), __builtin_fmaf(t, b.z, f.z),
+                       __builtin_fmaf(t, b.w, f.w));
+}
+
+// Children indexed q = dz * 4 + dy * 2 + dx; axis 0 = x (bit 0), 1 = y (bit 1), 2 = z (bit 2).
+__device__ __forceinline__ float4 reduce_dir(const float4 (&ch)[8], int axis, bool front_low) {
+    const int bit = 1 << axis;
+    float4 p[4];
+    int k = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (!(q & bit)) {
+            const float4 lo = ch[q], hi = ch[q | bit];
+            p[k++] = front_low ? over(lo, hi) : over(hi, lo);
+        }
+    float4 s;
+    s.x = ((p[0].x + p[1].x) + (p[2].x + p[3].x)) * 0.25f;
+    s.y = ((p[0].y + p[1].y) + (p[2].y + p[3].y)) * 0.25f;
+    s.z = ((p[0].z + p[1].z) + (p[2].z + p[3].z)) * 0.25f;
+    s.w = ((p[0].w + p[1].w) + (p[2].w + p[3].w)) * 0.25f;
+    return s;
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_mip_aniso(AnisoPass p) {
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t brick = t >> 6, w = t & 63u;
+    const uint32_t nb = (uint32_t)p.nb;
+    if (brick >= nb * nb * nb) return;
+    const int x = (int)(brick % nb) * 4 + (int)(w & 3u), y = (int)((brick / nb) % nb) * 4 + (int)((w >> 2) & 3u),
+              z = (int)(brick / (nb * nb)) * 4 + (int)(w >> 4);
+    if (x >= p.side || y >= p.side || z >= p.side) return;
+    const uint32_t at = vct_brick_index(x, y, z, p.nb);
+    float4 ch[8];
+    if (p.level == 1) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int cx = 2 * x + (q & 1), cy = 2 * y + ((q >> 1) & 1), cz = 2 * z + (q >> 2);
+            ch[q] = p.base[((size_t)cz * p.n_base + cy) * p.n_base + cx];
+            vct_store_texel<DT>(p.pyr, vct_brick_index(cx, cy, cz, p.nb_child), ch[q]);
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        if (p.level > 1) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                ch[q] = vct_load_texel<DT>(
+                    p.pyr, p.src[d] + vct_brick_index(2 * x + (q & 1), 2 * y + ((q >> 1) & 1), 2 * z + (q >> 2),
+                                                      p.nb_child));
+        }
+        vct_store_texel<DT>(p.pyr, p.dst[d] + at, reduce_dir(ch, d >> 1, (d & 1) == 0));
+    }
+}
+
+template <int DT>
+hipError_t run_build_aniso(const PyrLayout& L, const float* base, void* pyr, hipStream_t s, EventSink& es) {
+    AnisoPass p{};
+    p.base = reinterpret_cast<const float4*>(base);
+    p.pyr = pyr;
+    p.n_base = L.n;
+    for (int l = 1; l < L.levels; ++l) {
+        p.level = l;
+        p.side = L.n >> l;
+        p.nb = L.nb[l];
+        p.nb_child = L.nb[l - 1];
+        for (int d = 0; d < 6; ++d) {
+            p.dst[d] = (uint32_t)L.doff[d][l];
+            p.src[d] = (uint32_t)L.doff[d][l - 1];
+        }
+        const uint32_t threads = (uint32_t)p.nb * p.nb * p.nb * 64u;
+        es.mark(s);
+        hipLaunchKernelGGL(k_mip_aniso<DT>, dim3((threads + 255u) / 256u), dim3(256), 0, s, p);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    es.mark(s);
+    return hipSuccess;
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_unpack(const void* __restrict__ pyr, int nl, int nb, uint32_t off,
                                                 float4* __restrict__ out) {
@@ -159,6 +256,13 @@ hipError_t run_build(const PyrLayout& L, const float* base, void* pyr, hipStream
 }  // namespace
 
 hipError_t vct_launch_build_mips(const PyrLayout& L, const float* base, void* pyr, hipStream_t s, EventSink& es) {
+    if (L.aniso && L.levels > 1) {   // (a single level is level 0 alone: the isotropic pack below)
+        switch (L.dtype) {
+            case VCT_F32: return run_build_aniso<VCT_F32>(L, base, pyr, s, es);
+            case VCT_F16: return run_build_aniso<VCT_F16>(L, base, pyr, s, es);
+            default: return run_build_aniso<VCT_BF16>(L, base, pyr, s, es);
+        }
+    }
     switch (L.dtype) {
         case VCT_F32: return run_build<VCT_F32>(L, base, pyr, s, es);
         case VCT_F16: return run_build<VCT_F16>(L, base, pyr, s, es);
@@ -166,13 +270,14 @@ hipError_t vct_launch_build_mips(const PyrLayout& L, const float* base, void* py
     }
 }
 
-hipError_t vct_launch_unpack(const PyrLayout& L, const void* pyr, int level, float* out, hipStream_t s) {
+hipError_t vct_launch_unpack(const PyrLayout& L, const void* pyr, int level, int direction, float* out,
+                             hipStream_t s) {
     int nl = L.n >> level;
     uint32_t total = (uint32_t)nl * nl * nl;
     int blocks = (int)((total + 255) / 256);
     if (blocks > 65536) blocks = 65536;
     float4* o = reinterpret_cast<float4*>(out);
-    uint32_t off = (uint32_t)L.off[level];
+    uint32_t off = (uint32_t)L.doff[direction][level];
     switch (L.dtype) {
         case VCT_F32: hipLaunchKernelGGL(k_unpack<VCT_F32>, dim3(blocks), dim3(256), 0, s, pyr, nl, L.nb[level], off, o); break;
         case VCT_F16: hipLaunchKernelGGL(k_unpack<VCT_F16>, dim3(blocks), dim3(256), 0, s, pyr, nl, L.nb[level], off, o); break;

@@ -1,6 +1,8 @@
 // Forward cone trace: one lane per pixel, each lane marches all cones of its
 // pixel (u diffuse, specular, occlusion) and writes the 8-float epilogue
-// (D.rgb, D.a, S.rgb, O).  Sections 4.2, 4.3.2, 4.5 and 5.4.4.
+// (D.rgb, D.a, S.rgb, O).  Sections 4.2, 4.3.2, 4.5 and 5.4.4; with an
+// anisotropic pyramid the samples weight its directional levels by the cone
+// axis (Section 5.1.3).
 //
 // Launch: 256-thread workgroups over 16x16-pixel tiles (a wave is an 8x8
 // quadrant, so the 64 lanes of a wave start from neighbouring surface points
@@ -12,12 +14,14 @@ namespace {
 
 using namespace vct;
 
-template <int DT, bool COUNT>
+template <int DT, bool COUNT, bool ANISO>
 __global__ __launch_bounds__(256) void k_trace(TraceArgs a, float4* __restrict__ out,
                                                unsigned long long* __restrict__ count) {
     __shared__ LevelTable T;
+    __shared__ DirSlot<ANISO> D;
     __shared__ unsigned long long s_cnt;
     load_level_table(a, &T);
+    load_dir_table(a, &D);
     if (COUNT && threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
 
@@ -28,7 +32,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a, float4* __restrict__
     unsigned int ksum = 0;
     float4 o0, o1;
     const size_t pix = ((size_t)view * a.h + y) * a.w + x;
-    if (inb) trace_pixel<DT>(a, T, view, pix, o0, o1, ksum);
+    if (inb) trace_pixel<DT, ANISO>(a, T, view, pix, o0, o1, ksum, dir_ptr(D));
     if constexpr (COUNT) {
         if (ksum) atomicAdd(&s_cnt, (unsigned long long)ksum);
         __syncthreads();
@@ -43,7 +47,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a, float4* __restrict__
 
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 
-template <int DT>
+template <int DT, bool ANISO>
 hipError_t run_trace(const TraceArgs& a, float* out, unsigned long long* count, hipStream_t s, EventSink& es) {
     dim3 grid(a.n_tiles), block(256);
     if (count) {
@@ -51,14 +55,20 @@ hipError_t run_trace(const TraceArgs& a, float* out, unsigned long long* count, 
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, count);
         if (a.n_tiles > 0) {
             es.mark(s);
-            hipLaunchKernelGGL((k_trace<DT, true>), grid, block, 0, s, a, nullptr, count);
+            hipLaunchKernelGGL((k_trace<DT, true, ANISO>), grid, block, 0, s, a, nullptr, count);
         }
     } else if (a.n_tiles > 0) {
         es.mark(s);
-        hipLaunchKernelGGL((k_trace<DT, false>), grid, block, 0, s, a, reinterpret_cast<float4*>(out), nullptr);
+        hipLaunchKernelGGL((k_trace<DT, false, ANISO>), grid, block, 0, s, a, reinterpret_cast<float4*>(out),
+                           nullptr);
     }
     es.mark(s);
     return hipGetLastError();
+}
+
+template <int DT>
+hipError_t run_trace_any(const TraceArgs& a, float* out, unsigned long long* count, hipStream_t s, EventSink& es) {
+    return a.aniso ? run_trace<DT, true>(a, out, count, s, es) : run_trace<DT, false>(a, out, count, s, es);
 }
 
 }  // namespace
@@ -66,8 +76,8 @@ hipError_t run_trace(const TraceArgs& a, float* out, unsigned long long* count, 
 hipError_t vct_launch_trace(const TraceArgs& a, int dtype, float* out, unsigned long long* count, hipStream_t s,
                             EventSink& es) {
     switch (dtype) {
-        case VCT_F32: return run_trace<VCT_F32>(a, out, count, s, es);
-        case VCT_F16: return run_trace<VCT_F16>(a, out, count, s, es);
-        default: return run_trace<VCT_BF16>(a, out, count, s, es);
+        case VCT_F32: return run_trace_any<VCT_F32>(a, out, count, s, es);
+        case VCT_F16: return run_trace_any<VCT_F16>(a, out, count, s, es);
+        default: return run_trace_any<VCT_BF16>(a, out, count, s, es);
     }
 }

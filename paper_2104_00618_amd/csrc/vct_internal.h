@@ -20,11 +20,15 @@
 // one, and a brick of float16 texels is 512 contiguous bytes.
 // After the last level comes a float32 staging area of two buffers of
 // (N/16)^3 texels used by the multi-pass mip build.
+// An anisotropic pyramid stores level 0 once, then levels 1..L-1 of each of
+// the six directions (+x, -x, +y, -y, +z, -z) in turn; off[] then describes
+// the +x pyramid and doff[d][] every direction (doff[d][0] = 0).
 // ---------------------------------------------------------------------------
 struct PyrLayout {
-    int32_t n, levels, dtype, texel_bytes;
+    int32_t n, levels, dtype, texel_bytes, aniso;
     int32_t nb[VCT_MAX_LEVELS];        // bricks per axis of each level
     int64_t off[VCT_MAX_LEVELS];       // texel offset of each level
+    int64_t doff[6][VCT_MAX_LEVELS];   // texel offset of each level of each direction
     int64_t total_texels;              // all levels
     int64_t stage_off_bytes[2];        // byte offsets of the two staging buffers
     int64_t stage_texels;              // capacity of each staging buffer (float4 texels)
@@ -37,22 +41,31 @@ static inline int vct_log2i(int v) {
     return l;
 }
 
-static inline PyrLayout vct_make_layout(int n, int levels, int dtype) {
+static inline PyrLayout vct_make_layout(int n, int levels, int dtype, int aniso = 0) {
     PyrLayout p{};
     p.n = n;
     p.levels = levels;
     p.dtype = dtype;
+    p.aniso = aniso ? 1 : 0;
     p.texel_bytes = dtype == VCT_F32 ? 16 : 8;
     int64_t off = 0;
+    // (every level stays 256-byte aligned: a brick is >= 512 bytes)
     for (int l = 0; l < levels; ++l) {
         int nl = n >> l;
         int nb = (nl + VCT_BRICK - 1) / VCT_BRICK;
         p.nb[l] = nb;
-        p.off[l] = off;
-        int64_t tex = (int64_t)nb * nb * nb * VCT_BRICK_TEXELS;
-        off += tex;
-        // keep every level 256-byte aligned (a brick is >= 512 bytes, so this holds already)
     }
+    for (int d = 0; d < (p.aniso ? 6 : 1); ++d)
+        for (int l = (d == 0 ? 0 : 1); l < levels; ++l) {
+            p.doff[d][l] = off;
+            off += (int64_t)p.nb[l] * p.nb[l] * p.nb[l] * VCT_BRICK_TEXELS;
+        }
+    for (int d = 0; d < 6; ++d)
+        for (int l = 0; l < levels; ++l) {
+            if (!p.aniso) p.doff[d][l] = p.doff[0][l];
+            if (l == 0) p.doff[d][0] = 0;
+        }
+    for (int l = 0; l < levels; ++l) p.off[l] = p.doff[0][l];
     p.total_texels = off;
     int64_t bytes = off * p.texel_bytes;
     bytes = (bytes + 255) & ~int64_t(255);
@@ -91,6 +104,9 @@ struct TraceArgs {
     LevelInfo lv[VCT_MAX_LEVELS];
     const void* pyr;
     vct_v4i rsrc;                  // structured buffer resource over pyr (one record per texel)
+    uint32_t ddelta[6][VCT_MAX_LEVELS];   // anisotropic: texel offset of direction d's level l minus lv[l].off
+    float inv_scale2;              // (extent / N)^2: unit-axis weights w_a^2 = W_a^2 * inv_scale2
+    int32_t aniso;                 // six directional pyramids (levels >= 1)
     // G-buffer
     int32_t b, h, w;
     int32_t tiles_x, tiles_y, n_tiles;   // 16x16-pixel tiles
@@ -119,7 +135,8 @@ struct EventSink {
 
 // Launch helpers implemented in the .hip files.
 hipError_t vct_launch_build_mips(const PyrLayout& L, const float* base, void* pyr, hipStream_t s, EventSink& es);
-hipError_t vct_launch_unpack(const PyrLayout& L, const void* pyr, int level, float* out, hipStream_t s);
+hipError_t vct_launch_unpack(const PyrLayout& L, const void* pyr, int level, int direction, float* out,
+                             hipStream_t s);
 hipError_t vct_launch_trace(const TraceArgs& a, int dtype, float* out, unsigned long long* count,
                             hipStream_t s, EventSink& es);
 size_t vct_voxelize_acc_bytes(int n, bool surface);

@@ -415,3 +415,40 @@ def test_bounce_validation_and_workspace_size():
     g.n = 48
     rc = lib.vct_bounce(ctypes.byref(g), fake, fake, fake, fake, ctypes.byref(p), fake, fake, need, None)
     assert rc == EINVAL and "power of two" in lib.vct_last_error().decode()
+
+
+def test_anisotropic_grid_size_validation_and_unsupported_paths():
+    lib = vct.lib()
+    EUNSUPPORTED = -4
+    iso, ani = vct.Grid(64).c(), vct.Grid(64, anisotropic=True).c()
+    bi, ba = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.vct_pyramid_bytes(ctypes.byref(iso), ctypes.byref(bi)) == 0
+    assert lib.vct_pyramid_bytes(ctypes.byref(ani), ctypes.byref(ba)) == 0
+    above0 = sum(max(64 >> l, 4) ** 3 for l in range(1, 7)) * 16      # bricks round small levels up to 4^3
+    assert ba.value - bi.value == 5 * above0                              # five more copies of levels 1..L-1
+    bad = vct.Grid(16).c()
+    bad.anisotropic = 2
+    assert lib.vct_pyramid_bytes(ctypes.byref(bad), ctypes.byref(bi)) == EINVAL
+    assert "anisotropic" in lib.vct_last_error().decode()
+    fake = ctypes.c_void_p(0x1000)
+    p = B.cone_params(_params(alpha_thresh=0.99))
+    gb = _empty_gbuf()
+    n = ctypes.c_size_t()
+    assert lib.vct_backward_workspace_bytes(ctypes.byref(ani), ctypes.byref(gb), ctypes.byref(p),
+                                            ctypes.byref(n)) == EUNSUPPORTED
+    assert lib.vct_trace_save(ctypes.byref(ani), fake, ctypes.byref(gb), ctypes.byref(p), fake, fake, 1 << 20,
+                              None) == EUNSUPPORTED
+    assert lib.vct_trace_backward(ctypes.byref(ani), fake, ctypes.byref(gb), ctypes.byref(p), fake, fake, fake,
+                                  1 << 30, None) == EUNSUPPORTED
+    assert lib.vct_bounce(ctypes.byref(ani), fake, fake, fake, fake, ctypes.byref(p), fake, fake, 1 << 30,
+                          None) == EUNSUPPORTED
+    s = _shade_params()
+    assert lib.vct_shade(ctypes.byref(ani), fake, ctypes.byref(gb), fake, ctypes.byref(p), ctypes.byref(s), fake,
+                         None) == EUNSUPPORTED
+    assert "anisotropic" in lib.vct_last_error().decode()
+    # the forward accepts it (nothing to do for an empty G-buffer)
+    assert lib.vct_trace(ctypes.byref(ani), fake, ctypes.byref(gb), ctypes.byref(p), None, None) == 0
+    # directions: 0..5 for anisotropic grids, 0 only for isotropic ones
+    assert lib.vct_unpack_level_dir(ctypes.byref(ani), fake, 1, 6, fake, None) == EINVAL
+    assert lib.vct_unpack_level_dir(ctypes.byref(iso), fake, 1, 1, fake, None) == EINVAL
+    assert "direction" in lib.vct_last_error().decode()

@@ -1,0 +1,125 @@
+"""GPU anisotropic (six-direction) mips and the forward trace that samples
+them, against the FP64 oracle: every directional level, the trace on random
+and Cornell scenes with ragged tiles, float16 storage (path parity on the
+decoded pyramid and storage error), sample counts, and sampled pixels of the
+256^3 / 1080p launch."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import vct_aniso as va
+import paper_2104_00618_amd as vct
+from scenes import ConeParams, cone_set, random_gbuffer, random_grid
+from tests.parity import fmt, range_errors, worst
+from tests.workloads import sample_pixels, sub_gbuffer, workload
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = 1e-5
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def gpu_aniso(base, n, levels=None, dtype="f32"):
+    g = vct.Grid(n, levels=levels, dtype=dtype, anisotropic=True)
+    return vct.build_mips(dev(base), g), g
+
+
+def decoded(pyr, g):
+    """The GPU pyramid read back: [direction][level] float64."""
+    return [[vct.unpack_level_dir(pyr, g, lv, d).cpu().numpy().astype(np.float64) for lv in range(g.levels)]
+            for d in range(6)]
+
+
+def check(gpu, ref, keep, tol, label):
+    e = range_errors(gpu, ref, keep)
+    print(f"{label}: {fmt(e)}; ambiguous excluded {int((~keep).sum())}", flush=True)
+    assert worst(e)[0] <= tol, label
+
+
+@pytest.mark.parametrize("n,levels", [(2, None), (4, None), (16, None), (64, None), (64, 3)])
+def test_aniso_mips_f32_match_oracle(n, levels):
+    base = random_grid(n, seed=200 + n, alpha_max=0.8)
+    pyr, g = gpu_aniso(base, n, levels)
+    ref = va.build_aniso_mips(base, g.levels)
+    got = decoded(pyr, g)
+    for d in range(6):
+        np.testing.assert_array_equal(got[d][0], base)                   # level 0: the input, in every direction
+        for lv in range(1, g.levels):
+            err = np.abs(got[d][lv] - ref[d][lv]).max() / np.abs(ref[d][lv]).max()
+            assert err <= 1e-6, (d, lv, err)
+    # the directions differ (an isotropic build would make them equal)
+    assert np.abs(got[0][1] - got[1][1]).max() > 1e-3
+
+
+def test_aniso_mips_f16_within_storage_rounding():
+    n = 32
+    base = random_grid(n, seed=7, alpha_max=0.8)
+    pyr, g = gpu_aniso(base, n, dtype="f16")
+    ref = va.build_aniso_mips(base)
+    got = decoded(pyr, g)
+    for d in range(6):
+        for lv in range(g.levels):
+            # level l is rounded once per level on its way up: at most l + 1 half-ulps of float16, relative
+            err = (np.abs(got[d][lv] - ref[d][lv]) / np.maximum(np.abs(ref[d][lv]), 2.0 ** -14)).max()
+            assert err <= (lv + 1) * 2.0 ** -11 + 1e-7, (d, lv, err)
+
+
+def test_aniso_trace_random_ragged():
+    n = 32
+    base = random_grid(n, seed=31, alpha_max=0.3)
+    pr, nr, cam = random_gbuffer(2, 37, 53, seed=32, n=n)
+    d, w = cone_set("six")
+    p = ConeParams(d, w, alpha_thresh=0.99, light_pos=(0.3, 0.8, 0.6))
+    pyr, g = gpu_aniso(base, n)
+    out = vct.trace(pyr, g, dev(pr), dev(nr), dev(cam), p).cpu().numpy()
+    ref, info = va.trace_aniso(va.build_aniso_mips(base), pr, nr, cam, p, return_info=True)
+    check(out, ref, ~info["ambiguous"].reshape(-1), TOL, "aniso random 32^3 2x37x53")
+    # sample counts are those of the oracle's march
+    cnt = vct.count_samples(pyr, g, dev(pr), dev(nr), dev(cam), p)
+    assert abs(cnt - info["samples"]) <= int(info["ambiguous"].sum()) * 64, (cnt, info["samples"])
+
+
+def test_aniso_trace_cornell_and_partial_pyramid():
+    w = workload("c0")
+    n = w.n
+    pr, nr, cam = w.pos_rough[:, ::3, ::3].copy(), w.normal[:, ::3, ::3].copy(), w.cam_pos
+    for levels in (None, 4):
+        pyr, g = gpu_aniso(w.base, n, levels)
+        out = vct.trace(pyr, g, dev(pr), dev(nr), dev(cam), w.params).cpu().numpy()
+        ref, info = va.trace_aniso(va.build_aniso_mips(w.base, g.levels), pr, nr, cam, w.params, return_info=True)
+        check(out, ref, ~info["ambiguous"].reshape(-1), TOL, f"aniso c0 64^3 {pr.shape[1]}x{pr.shape[2]} levels {g.levels}")
+
+
+def test_aniso_trace_f16_two_tiers():
+    n = 32
+    base = random_grid(n, seed=41, alpha_max=0.3)
+    pr, nr, cam = random_gbuffer(1, 29, 31, seed=42, n=n)
+    d, w = cone_set("five")
+    p = ConeParams(d, w, alpha_thresh=0.99)
+    pyr, g = gpu_aniso(base, n, dtype="f16")
+    out = vct.trace(pyr, g, dev(pr), dev(nr), dev(cam), p).cpu().numpy()
+    ref_dec, i_dec = va.trace_aniso(decoded(pyr, g), pr, nr, cam, p, return_info=True)
+    check(out, ref_dec, ~i_dec["ambiguous"].reshape(-1), TOL, "aniso f16 path parity")
+    ref, info = va.trace_aniso(va.build_aniso_mips(base), pr, nr, cam, p, return_info=True)
+    check(out, ref, ~(info["ambiguous"] | i_dec["ambiguous"]).reshape(-1), 2e-3, "aniso f16 storage")
+
+
+def test_aniso_trace_full_launch_sampled_pixels():
+    """256^3 / 1920x1080 (the benchmark frame) with an anisotropic pyramid;
+    512 seeded pixels recomputed by the oracle."""
+    w = workload("c1")
+    pyr, g = gpu_aniso(w.base, w.n)
+    out = vct.trace(pyr, g, dev(w.pos_rough), dev(w.normal), dev(w.cam_pos), w.params).cpu().numpy()
+    am = va.build_aniso_mips(w.base)
+    v, y, x = sample_pixels(w.shape, 512, seed=5)
+    ref = np.zeros((len(v), 8))
+    amb = np.zeros(len(v), dtype=bool)
+    for sel, pr, nr, cam in sub_gbuffer(w.pos_rough, w.normal, w.cam_pos, v, y, x):
+        o, info = va.trace_aniso(am, pr, nr, cam, w.params, return_info=True)
+        ref[sel] = o.reshape(-1, 8)
+        amb[sel] = info["ambiguous"].reshape(-1)
+    check(out[v, y, x], ref, ~amb, TOL, "aniso c1 256^3 1080p sampled")
