@@ -96,6 +96,13 @@ def sample_aniso(amips, p, lam, w, origin=(0.0, 0.0, 0.0), extent=1.0):
     return s
 
 
+def aniso_sampler(amips, origin=(0.0, 0.0, 0.0), extent=1.0):
+    """The sampler hook of the march, shading and bounce oracles for an
+    anisotropic pyramid (pass amips[0] as their isotropic ``mips``: it gives
+    the level count and N)."""
+    return lambda p, lam, w: sample_aniso(amips, p, lam, w, origin, extent)
+
+
 def trace_aniso(amips, pos_rough, normal, cam_pos, params, origin=(0.0, 0.0, 0.0), extent=1.0,
                 return_info=False):
     """Forward trace [b, h, w, 8] float64 with anisotropic sampling (A3)."""

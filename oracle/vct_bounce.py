@@ -75,12 +75,13 @@ def voxel_gbuffer(mask, normal_grid, origin=(0.0, 0.0, 0.0), extent=1.0, voxels=
 
 
 def bounce(base, normal_grid, albedo_grid, params, levels=None, origin=(0.0, 0.0, 0.0), extent=1.0,
-           gather_from=None, mips=None, voxels=None, return_info=False):
+           gather_from=None, mips=None, voxels=None, return_info=False, sampler=None):
     """One bounce (B1-B3): [N, N, N, 4] float64.
 
     gather_from: the grid whose pyramid the cones march through (default
     base; B4 passes the previous bounce); mips: that pyramid given directly
-    (e.g. a decoded reduced-precision one).  voxels: optional [M, 3] (z, y, x)
+    (e.g. a decoded reduced-precision one); sampler: replaces the isotropic
+    sample (an anisotropic pyramid's).  voxels: optional [M, 3] (z, y, x)
     list; then only those voxels are computed and the result is their [M, 4]
     values (for sampled checks of large grids)."""
     base = np.asarray(base, dtype=np.float64)
@@ -94,7 +95,7 @@ def bounce(base, normal_grid, albedo_grid, params, levels=None, origin=(0.0, 0.0
     nr[0, 0, ~live, 3] = 0.0
     cone = params.replace(enable_spec=False, enable_occ=False)
     cam = np.zeros((1, 3))
-    out, info = trace(mips, pr, nr, cam, cone, origin, extent, return_info=True)
+    out, info = trace(mips, pr, nr, cam, cone, origin, extent, return_info=True, sampler=sampler)
     gathered = out[0, 0, :, 0:3]
     alb = np.asarray(albedo_grid, dtype=np.float64)[z, y, x, 0:3]
     vals = base[z, y, x].copy()

@@ -300,13 +300,14 @@ def assemble(lanes, res, params, shape):
 
 
 def trace(mips, pos_rough, normal, cam_pos, params, origin=(0.0, 0.0, 0.0), extent=1.0,
-          return_info=False):
+          return_info=False, sampler=None):
     """Forward: out [b,h,w,8] float64.  ``mips`` is the pyramid as returned by
-    build_mips (or a decoded reduced-precision pyramid)."""
+    build_mips (or a decoded reduced-precision pyramid); ``sampler`` replaces
+    the isotropic sample (see march)."""
     n = mips[0].shape[0]
     shape = np.asarray(pos_rough).shape[:3]
     lanes = cone_lanes(pos_rough, normal, cam_pos, params, n, origin, extent)
-    res = march(mips, lanes, params, origin, extent)
+    res = march(mips, lanes, params, origin, extent, sampler=sampler)
     out = assemble(lanes, res, params, shape)
     if not return_info:
         return out

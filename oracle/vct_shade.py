@@ -77,7 +77,7 @@ def f_spec(axis, ldir, shininess, params):
     return (1.0 - np.maximum(0.0, gamma - p) / math.pi) ** params.shininess_falloff
 
 
-def _march_variant(mips, lanes, cone_params, mode, shade, origin=(0.0, 0.0, 0.0), extent=1.0):
+def _march_variant(mips, lanes, cone_params, mode, shade, origin=(0.0, 0.0, 0.0), extent=1.0, sampler=None):
     """The two modified marches: mode "first_hit" (S2) returns rgb [m,3];
     mode "falloff" returns accumulated alpha [m] with every sample's alpha
     scaled by smoothstep(0, max_dist, sqrt(t) * shadow_strength).  Also
@@ -105,7 +105,8 @@ def _march_variant(mips, lanes, cone_params, mode, shade, origin=(0.0, 0.0, 0.0)
         ti = t[idx]
         d = np.maximum(2.0 * ti * np.tan(gamma[idx] / 2.0), v0)
         lam = np.clip(np.log2(d / v0), 0.0, nlev - 1)
-        s = sample(mips, x[idx] + ti[:, None] * w[idx], lam, origin, extent)
+        p = x[idx] + ti[:, None] * w[idx]
+        s = sample(mips, p, lam, origin, extent) if sampler is None else sampler(p, lam, w[idx])
         if mode == "first_hit":
             hit = s[:, 3] > shade.first_hit_alpha
             amb[idx] |= np.abs(s[:, 3] - shade.first_hit_alpha) < AMBIG_HIT
@@ -137,7 +138,7 @@ def _occlusion_lanes(pos_rough, normal, cone_params, light, n, origin, extent):
 
 
 def shade(mips, pos_rough, normal, material, cam_pos, cone_params, shade, origin=(0.0, 0.0, 0.0), extent=1.0,
-          return_info=False):
+          return_info=False, sampler=None):
     """Shaded radiance and o_min per pixel: [b,h,w,4] float64 = (L.rgb, o_min).
 
     material [b,h,w,4] = (c_d.rgb, shininess); cone_params supplies the diffuse
@@ -171,14 +172,14 @@ def shade(mips, pos_rough, normal, material, cam_pos, cone_params, shade, origin
     if dsel.any():
         dl = {k: v[dsel] for k, v in lanes.items()}
         if shade.diffuse_first_hit:
-            c, a = _march_variant(mips, dl, cone_params, "first_hit", shade, origin, extent)
+            c, a = _march_variant(mips, dl, cone_params, "first_hit", shade, origin, extent, sampler)
         else:
-            r = march(mips, dl, cone_params, origin, extent)
+            r = march(mips, dl, cone_params, origin, extent, sampler=sampler)
             c, a = r["c"], r["ambiguous"]
         np.add.at(diffuse, dl["pix"], wq[dl["slot"]][:, None] * c)
         np.logical_or.at(amb, dl["pix"], a)
     sl = {k: v[ssel] for k, v in lanes.items()}
-    rs = march(mips, sl, cone_params, origin, extent)
+    rs = march(mips, sl, cone_params, origin, extent, sampler=sampler)
     c_spec = np.zeros((npix, 3))
     c_spec[sl["pix"]] = rs["c"]
     np.logical_or.at(amb, sl["pix"], rs["ambiguous"])
@@ -202,9 +203,9 @@ def shade(mips, pos_rough, normal, material, cam_pos, cone_params, shade, origin
         light = np.asarray(shade.light_pos[s], dtype=np.float64)
         ol = _occlusion_lanes(pos_rough, normal, cone_params, light, n0, origin, extent)
         if shade.occlusion_falloff:
-            occ, a = _march_variant(mips, ol, cone_params, "falloff", shade, origin, extent)
+            occ, a = _march_variant(mips, ol, cone_params, "falloff", shade, origin, extent, sampler)
         else:
-            r = march(mips, ol, cone_params, origin, extent)
+            r = march(mips, ol, cone_params, origin, extent, sampler=sampler)
             occ, a = r["alpha"], r["ambiguous"]
         np.logical_or.at(amb, ol["pix"], a)
         vis = np.ones(npix)

@@ -95,3 +95,107 @@ def test_below_lod_one_the_trace_is_the_isotropic_trace():
     wide = p.replace(diffuse_aperture=math.pi / 3, spec_aperture_scale=math.pi / 3, occ_aperture=math.pi / 3)
     assert np.abs(va.trace_aniso(va.build_aniso_mips(base), pr, nr, cam, wide)
                   - oracle.trace(oracle.build_mips(base), pr, nr, cam, wide)).max() > 1e-3
+
+
+def _uniform_cone(c, a, gamma, p, n, levels, mode="plain", strength=1.0):
+    """(C, A) of one cone in a uniform medium through an anisotropic pyramid,
+    by a scalar loop: the level-l texel holds the light and opacity of 2^l
+    voxels, (c (1 - (1-a)^(2^l)) / a, 1 - (1-a)^(2^l)), in every direction.
+    mode "first" returns the first sample's colour (every sample's alpha
+    exceeds 1/100 here); "falloff" scales each alpha by the Hermite step of
+    sqrt(t) * strength over [0, max_dist]."""
+    v0 = 1.0 / n
+
+    def level(lv):
+        t = (1.0 - a) ** (2 ** lv)
+        return np.append(c * (1.0 - t) / a, 1.0 - t)
+
+    t, C, A = p.t0, np.zeros(3), 0.0
+    while t <= p.max_dist and A < p.alpha_thresh:
+        d = max(2.0 * t * math.tan(gamma / 2.0), v0)
+        lam = min(max(math.log2(d / v0), 0.0), levels - 1)
+        l0 = int(math.floor(lam))
+        f = lam - l0
+        s = (1.0 - f) * level(l0) + (f * level(min(l0 + 1, levels - 1)) if f > 0 else 0.0)
+        if mode == "first":
+            return s[0:3], s[3]
+        if mode == "falloff":
+            h = min(max(math.sqrt(t) * strength / p.max_dist, 0.0), 1.0)
+            s = s.copy()
+            s[3] *= h * h * (3.0 - 2.0 * h)
+        C += (1.0 - A) * s[0:3]
+        A += (1.0 - A) * s[3]
+        t += p.step_factor * d
+    return C, A
+
+
+def _uniform_setup(n=16):
+    c, a = np.array([0.12, 0.06, 0.03]), 0.15
+    base = np.zeros((n, n, n, 4))
+    base[..., 0:3] = c
+    base[..., 3] = a
+    rng = np.random.default_rng(4)
+    pr = np.concatenate([rng.uniform(0.3, 0.7, size=(1, 3, 4, 3)), np.full((1, 3, 4, 1), 0.5)], -1)
+    nr = np.concatenate([rng.normal(size=(1, 3, 4, 3)), np.ones((1, 3, 4, 1))], -1)
+    dirs = np.array([[0, 0, 1], [0.6, 0, 0.8], [0, -0.6, 0.8]], np.float32)
+    p = ConeParams(dirs, np.array([0.5, 0.3, 0.2], np.float32), diffuse_aperture=0.9, spec_aperture_scale=0.5,
+                   occ_aperture=0.7, light_pos=(9.0, 9.0, 9.0), step_factor=0.6, t0=0.01, max_dist=0.6,
+                   alpha_thresh=0.97)
+    return n, c, a, base, pr, nr, p
+
+
+def test_uniform_medium_trace_through_anisotropic_pyramids():
+    n, c, a, base, pr, nr, p = _uniform_setup()
+    am = va.build_aniso_mips(base)
+    out = va.trace_aniso(am, pr, nr, np.array([[0.5, 0.5, 3.0]]), p)
+    Cd, Ad = _uniform_cone(c, a, p.diffuse_aperture, p, n, 5)
+    Cs, _ = _uniform_cone(c, a, 0.5 * p.spec_aperture_scale, p, n, 5)
+    _, Ao = _uniform_cone(c, a, p.occ_aperture, p, n, 5)
+    W = float(np.sum(p.diffuse_weights.astype(np.float64)))
+    expect = np.concatenate([W * Cd, [W * Ad], Cs, [Ao]])
+    np.testing.assert_allclose(out.reshape(-1, 8), np.broadcast_to(expect, (12, 8)), rtol=1e-12)
+    # the isotropic pyramid of the same medium holds the 2x2x2 means (c, a) at every level: a different result
+    assert np.abs(oracle.trace(oracle.build_mips(base), pr, nr, np.array([[0.5, 0.5, 3.0]]), p)
+                  - out).max() > 1e-2
+
+
+def test_uniform_medium_shading_and_bounce_through_the_sampler_hook():
+    from oracle import vct_bounce as vb
+    from oracle import vct_shade as vs
+    from scenes.configs import ShadeParams
+    n, c, a, base, pr, nr, p = _uniform_setup()
+    am = va.build_aniso_mips(base)
+    smp = va.aniso_sampler(am)
+    # the oracles' own pyramid argument gets the isotropic pyramid, whose levels hold (c, a) unintegrated: a
+    # march that bypassed the sampler hook would read it and miss the closed forms below
+    iso = oracle.build_mips(base)
+    Cd, _ = _uniform_cone(c, a, p.diffuse_aperture, p, n, 5)
+    Cs, _ = _uniform_cone(c, a, 0.5 * p.spec_aperture_scale, p, n, 5)
+    W = float(np.sum(p.diffuse_weights.astype(np.float64)))
+    # no lights, unmodified cones: L = sum_q w_q C_q + C_spec
+    sp = ShadeParams(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32),
+                     diffuse_first_hit=False, occlusion_falloff=False, specular_brdf=False)
+    mat = np.concatenate([np.full((1, 3, 4, 3), 0.5), np.full((1, 3, 4, 1), 8.0)], -1)
+    out = vs.shade(iso, pr, nr, mat, np.array([[0.5, 0.5, 3.0]]), p, sp, sampler=smp)
+    np.testing.assert_allclose(out[..., 0:3].reshape(-1, 3), np.broadcast_to(W * Cd + Cs, (12, 3)), rtol=1e-12)
+    # first-hit diffuse cones and one far, dark light with falloff occlusion: L = o_min (sum_q w_q s_0) + C_spec
+    sp2 = ShadeParams(np.array([[9.0, 9.0, 9.0]], np.float32), np.zeros((1, 3), np.float32),
+                      np.zeros((1, 3), np.float32), diffuse_first_hit=True, occlusion_falloff=True,
+                      shadow_strength=2.0, specular_brdf=False)
+    # (t0 = 0.2: the first sample lies between levels 1 and 2, where the directions are pre-integrated)
+    p2 = p.replace(t0=0.2)
+    out = vs.shade(iso, pr, nr, mat, np.array([[0.5, 0.5, 3.0]]), p2, sp2, sampler=smp)
+    s0, _ = _uniform_cone(c, a, p2.diffuse_aperture, p2, n, 5, mode="first")
+    _, Af = _uniform_cone(c, a, p2.occ_aperture, p2, n, 5, mode="falloff", strength=2.0)
+    Cs2, _ = _uniform_cone(c, a, 0.5 * p2.spec_aperture_scale, p2, n, 5)
+    np.testing.assert_allclose(out[..., 3].ravel(), 1.0 - Af, rtol=1e-12)
+    np.testing.assert_allclose(out[..., 0:3].reshape(-1, 3), np.broadcast_to((1.0 - Af) * W * s0 + Cs2, (12, 3)),
+                               rtol=1e-12)
+    # one bounce in the same medium: c + a * rho * W * C_diffuse
+    rho = np.array([0.9, 0.5, 0.2])
+    nrm = np.zeros((n, n, n, 4))
+    nrm[..., 0:3] = (0.3, 0.0, -0.4)
+    alb = np.zeros((n, n, n, 4))
+    alb[..., 0:3] = rho
+    got = vb.bounce(base, nrm, alb, p, mips=iso, sampler=smp)
+    np.testing.assert_allclose(got[..., 0:3], np.broadcast_to(c + a * rho * W * Cd, (n, n, n, 3)), rtol=1e-12)
