@@ -67,8 +67,8 @@ typedef struct {
     float origin[3];   /* world position of the grid's minimum corner */
     float extent;      /* side length of the grid cube, world units, finite and > 0 */
     int32_t anisotropic; /* 0: one pyramid of 2x2x2 means; 1: six directional pyramids sharing level 0
-                            (see vct_build_mips); only vct_build_mips, vct_unpack_level(_dir), vct_trace
-                            and vct_count_samples accept 1, the others return VCT_EUNSUPPORTED */
+                            (see vct_build_mips); the training entry points (vct_trace_save and the
+                            backward ones) return VCT_EUNSUPPORTED for 1, the others accept it */
 } vct_grid;
 
 /* Deferred-shading G-buffer: one cone origin per pixel (Section 5.1.3 adopts

@@ -63,8 +63,8 @@ int check_grid(const char* fn, const vct_grid* g) {
 // Entry points whose kernels sample isotropic pyramids only.
 int check_isotropic(const char* fn, const vct_grid* g) {
     if (g->anisotropic)
-        return fail(VCT_EUNSUPPORTED, fn, "anisotropic pyramids are supported by vct_build_mips, vct_unpack_level(_dir), "
-                    "vct_trace and vct_count_samples only");
+        return fail(VCT_EUNSUPPORTED, fn, "anisotropic pyramids have no adjoint in this build (vct_build_mips, "
+                    "vct_unpack_level(_dir), vct_trace, vct_count_samples, vct_shade and vct_bounce accept them)");
     return VCT_OK;
 }
 
@@ -278,7 +278,6 @@ int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf
     const char* fn = "vct_shade";
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
-    if (int r = check_isotropic(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
     if (int r = check_params(fn, grid, params)) return r;
     if (!shade) return fail(VCT_EINVAL, fn, "shade is null");
@@ -479,7 +478,6 @@ int vct_bounce(const vct_grid* grid, const void* pyramid, const float* base, con
     const char* fn = "vct_bounce";
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
-    if (int r = check_isotropic(fn, grid)) return r;
     if (int r = check_params(fn, grid, params)) return r;
     if (!pyramid || !base || !normal || !albedo || !out || !workspace)
         return fail(VCT_EINVAL, fn, "pyramid, base, normal, albedo, out and workspace must be non-null");

@@ -153,12 +153,14 @@ struct BounceArgs {
 // sums them in cone order (the order of the forward trace's diffuse sum).
 // Tiles of 64 list entries are taken from the XCD's own contiguous run through
 // an atomic counter, so faster workgroups take more tiles.
-template <int DT>
+template <int DT, bool ANISO>
 __global__ __launch_bounds__(1024) void k_gather(TraceArgs a, BounceArgs b) {
     __shared__ LevelTable T;
+    __shared__ DirSlot<ANISO> D;
     __shared__ float s_c[VCT_MAX_DIFFUSE][3][64];
     __shared__ uint32_t s_tile;
     load_level_table(a, &T);
+    load_dir_table(a, &D);
     const uint32_t total = *b.total;
     const uint32_t nt = (total + 63u) / 64u;
     const uint32_t per_xcd = (nt + 7u) / 8u;
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(1024) void k_gather(TraceArgs a, BounceArgs b) {
                 const float x = (float)(v & mask), y = (float)((v >> b.lg) & mask), z = (float)(v >> (2 * b.lg));
                 set_origin(a, P, df{x + 0.5f, 0.0f}, df{y + 0.5f, 0.0f}, df{z + 0.5f, 0.0f});
                 const Cone c = cone_for_slot(a, P, q, make_float3(0.f, 0.f, 0.f));   // diffuse: no camera
-                const MarchResult m = march<DT>(a, T, c);
+                const MarchResult m = march<DT, ANISO>(a, T, c, dir_ptr(D));
                 r = m.r;
                 g = m.g;
                 bl = m.b;
@@ -215,7 +217,10 @@ __global__ __launch_bounds__(1024) void k_gather(TraceArgs a, BounceArgs b) {
 
 template <int DT>
 void launch_gather(const TraceArgs& a, const BounceArgs& b, hipStream_t st) {
-    hipLaunchKernelGGL(k_gather<DT>, dim3(kGatherBlocks), dim3(64 * a.n_diffuse), 0, st, a, b);
+    if (a.aniso)
+        hipLaunchKernelGGL((k_gather<DT, true>), dim3(kGatherBlocks), dim3(64 * a.n_diffuse), 0, st, a, b);
+    else
+        hipLaunchKernelGGL((k_gather<DT, false>), dim3(kGatherBlocks), dim3(64 * a.n_diffuse), 0, st, a, b);
 }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }

@@ -12,17 +12,20 @@
 // axis and aperture, so the per-light traces of the thesis are one trace
 // weighted by the sum of the per-light BRDF values.
 //
-// Launch: the tiles, waves and XCD order of the forward trace.
+// Launch: the tiles, waves and XCD order of the forward trace.  With an
+// anisotropic pyramid every cone samples its directional levels (Section 5.1.3).
 #include "shade_pixel.h"
 
 namespace {
 
 using namespace vct;
 
-template <int DT>
+template <int DT, bool ANISO>
 __global__ __launch_bounds__(256) void k_shade(TraceArgs a, ShadeArgs s, float4* __restrict__ out) {
     __shared__ LevelTable T;
+    __shared__ DirSlot<ANISO> D;
     load_level_table(a, &T);
+    load_dir_table(a, &D);
     __syncthreads();
     const int tile = xcd_tile(blockIdx.x, a.n_tiles);
     int view, y, x;
@@ -30,14 +33,19 @@ __global__ __launch_bounds__(256) void k_shade(TraceArgs a, ShadeArgs s, float4*
     if (!(x < a.w && y < a.h)) return;
     const size_t pix = ((size_t)view * a.h + y) * a.w + x;
     const float4 nr = a.normal[pix];
-    out[pix] = nr.w == 0.0f ? make_float4(0.f, 0.f, 0.f, 0.f) : shade_pixel<DT>(a, T, s, view, pix, nr);
+    out[pix] = nr.w == 0.0f ? make_float4(0.f, 0.f, 0.f, 0.f) : shade_pixel<DT, ANISO>(a, T, dir_ptr(D), s, view, pix, nr);
 }
 
 template <int DT>
 hipError_t run_shade(const TraceArgs& a, const ShadeArgs& s, float* out, hipStream_t st, EventSink& es) {
     if (a.n_tiles > 0) {
         es.mark(st);
-        hipLaunchKernelGGL(k_shade<DT>, dim3(a.n_tiles), dim3(256), 0, st, a, s, reinterpret_cast<float4*>(out));
+        if (a.aniso)
+            hipLaunchKernelGGL((k_shade<DT, true>), dim3(a.n_tiles), dim3(256), 0, st, a, s,
+                               reinterpret_cast<float4*>(out));
+        else
+            hipLaunchKernelGGL((k_shade<DT, false>), dim3(a.n_tiles), dim3(256), 0, st, a, s,
+                               reinterpret_cast<float4*>(out));
     }
     es.mark(st);
     return hipGetLastError();

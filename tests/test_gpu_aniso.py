@@ -123,3 +123,42 @@ def test_aniso_trace_full_launch_sampled_pixels():
         ref[sel] = o.reshape(-1, 8)
         amb[sel] = info["ambiguous"].reshape(-1)
     check(out[v, y, x], ref, ~amb, TOL, "aniso c1 256^3 1080p sampled")
+
+
+def test_aniso_shade_matches_oracle():
+    from oracle import vct_shade as vs
+    from scenes import random_material, scene_lights
+    w = workload("c0")
+    pr, nr, cam = w.pos_rough[:, ::4, ::4].copy(), w.normal[:, ::4, ::4].copy(), w.cam_pos
+    mat = random_material(pr.shape[:3], seed=9)
+    for sp in (scene_lights(2), scene_lights(1, diffuse_first_hit=False, occlusion_falloff=False,
+                                              specular_brdf=False)):
+        pyr, g = gpu_aniso(w.base, w.n)
+        out = vct.shade(pyr, g, dev(pr), dev(nr), dev(cam), dev(mat), w.params, sp).cpu().numpy()
+        am = va.build_aniso_mips(w.base)
+        ref, info = vs.shade(am[0], pr, nr, mat, cam, w.params, sp, return_info=True, sampler=va.aniso_sampler(am))
+        check(out, ref, ~info["ambiguous"].reshape(-1), 5e-5, f"aniso shade c0 {pr.shape[1]}x{pr.shape[2]} "
+              f"{sp.n_lights} lights first_hit={sp.diffuse_first_hit}")
+
+
+def test_aniso_bounce_matches_oracle():
+    from oracle import vct_bounce as vb
+    from oracle import vct_voxelize as vx
+    from scenes.mesh import cornell_mesh
+    n = 32
+    tris, cols = cornell_mesh(3)
+    lights = [((0.5, 0.95, 0.5), (1.0, 1.0, 1.0), (1.0, 0.5, 0.25))]
+    base, nrm, alb = (a.astype(np.float32) for a in vx.voxelize(tris, cols, n, lights, return_surface=True))
+    d, w = cone_set("six")
+    p = ConeParams(d, w, alpha_thresh=0.99)
+    pyr, g = gpu_aniso(base, n)
+    got = vct.bounce(pyr, g, dev(base), dev(nrm), dev(alb), p).cpu().numpy()
+    am = va.build_aniso_mips(base)
+    ref, info = vb.bounce(base, nrm, alb, p, mips=am[0], sampler=va.aniso_sampler(am), return_info=True)
+    near = np.abs(np.linalg.norm(nrm[..., 0:3].astype(np.float64), axis=-1) - vb.MIN_NORMAL) < 1e-6
+    keep = ~(info["ambiguous"] | near)
+    inc_g = (got[..., 0:3] - base[..., 0:3]).reshape(-1, 3)
+    inc_r = (ref[..., 0:3] - base[..., 0:3]).reshape(-1, 3)
+    check(inc_g, inc_r, keep.reshape(-1), TOL, "aniso bounce 32^3 (added light)")
+    same = (ref[..., 0:3] == base[..., 0:3]).all(-1) & keep
+    assert np.array_equal(got[same].view(np.uint32), base[same].view(np.uint32))
