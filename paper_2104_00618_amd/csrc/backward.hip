@@ -469,11 +469,9 @@ int64_t vct_lane_state_bytes(int64_t n_lanes) { return align256(n_lanes * (int64
 
 hipError_t vct_launch_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPlan& P, const float* grad_out,
                                float* grad_base, void* ws, const void* saved, hipStream_t s, EventSink& es) {
-    switch (L.dtype) {
-        case VCT_F32: return run_backward<VCT_F32>(L, a, P, grad_out, grad_base, ws, saved, s, es);
-        case VCT_F16: return run_backward<VCT_F16>(L, a, P, grad_out, grad_base, ws, saved, s, es);
-        default: return run_backward<VCT_BF16>(L, a, P, grad_out, grad_base, ws, saved, s, es);
-    }
+    return vct_dispatch_dt(L.dtype, a.wide != 0, [&](auto dt) {
+        return run_backward<decltype(dt)::value>(L, a, P, grad_out, grad_base, ws, saved, s, es);
+    });
 }
 
 hipError_t vct_launch_trace_save(const TraceArgs& a, int dtype, float* out, void* state, hipStream_t s,
@@ -482,11 +480,10 @@ hipError_t vct_launch_trace_save(const TraceArgs& a, int dtype, float* out, void
         es.mark(s);
         float4* o = reinterpret_cast<float4*>(out);
         LaneState* st = reinterpret_cast<LaneState*>(state);
-        switch (dtype) {
-            case VCT_F32: hipLaunchKernelGGL(k_trace_save<VCT_F32>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, o, st); break;
-            case VCT_F16: hipLaunchKernelGGL(k_trace_save<VCT_F16>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, o, st); break;
-            default: hipLaunchKernelGGL(k_trace_save<VCT_BF16>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, o, st); break;
-        }
+        vct_dispatch_dt(dtype, a.wide != 0, [&](auto dt) {
+            hipLaunchKernelGGL(k_trace_save<decltype(dt)::value>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, o, st);
+            return hipSuccess;
+        });
     }
     es.mark(s);
     return hipGetLastError();

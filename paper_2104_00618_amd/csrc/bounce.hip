@@ -272,11 +272,10 @@ hipError_t vct_launch_bounce(const TraceArgs& a, int dtype, const float* base, c
                  reinterpret_cast<const float4*>(albedo), reinterpret_cast<float4*>(out), list, total, queue, lg};
     es.mark(st);
     if (a.n_diffuse > 0) {
-        switch (dtype) {
-            case VCT_F32: launch_gather<VCT_F32>(a, b, st); break;
-            case VCT_F16: launch_gather<VCT_F16>(a, b, st); break;
-            default: launch_gather<VCT_BF16>(a, b, st); break;
-        }
+        vct_dispatch_dt(dtype, a.wide != 0, [&](auto dt) {
+            launch_gather<decltype(dt)::value>(a, b, st);
+            return hipSuccess;
+        });
     }
     es.mark(st);
     return hipGetLastError();

@@ -76,9 +76,6 @@ hipError_t vct_launch_shade(const TraceArgs& a, int dtype, const vct_shade_param
     s.grace = p->grace_per_shininess;
     s.q = p->shininess_falloff;
     s.material = reinterpret_cast<const float4*>(material);
-    switch (dtype) {
-        case VCT_F32: return run_shade<VCT_F32>(a, s, out, st, es);
-        case VCT_F16: return run_shade<VCT_F16>(a, s, out, st, es);
-        default: return run_shade<VCT_BF16>(a, s, out, st, es);
-    }
+    return vct_dispatch_dt(dtype, a.wide != 0,
+                           [&](auto dt) { return run_shade<decltype(dt)::value>(a, s, out, st, es); });
 }

@@ -66,11 +66,20 @@ __device__ __forceinline__ float4 vct_load_texel(const void* __restrict__ pyr, u
     }
 }
 
+// Fetch-path flag carried in the storage-type template argument: a structured
+// buffer load forms its byte offset (index * record size) in 32 bits, so a
+// pyramid of more than 4 GiB is read with 64-bit global addresses instead
+// (the base address is the one in the resource's first two words).
+constexpr int VCT_WIDE = 16;
+
 // Texel `idx` through the pyramid's buffer resource.
 template <int DT>
 __device__ __forceinline__ float4 vct_fetch_texel(const vct_v4i& rsrc, uint32_t idx) {
     VCT_CHECK_TEXEL(idx);
-    if constexpr (DT == VCT_F32) {
+    if constexpr ((DT & VCT_WIDE) != 0) {
+        const uint64_t base = (uint64_t)(uint32_t)rsrc.x | ((uint64_t)((uint32_t)rsrc.y & 0xffffu) << 32);
+        return vct_load_texel<DT & ~VCT_WIDE>(reinterpret_cast<const void*>(base), idx);
+    } else if constexpr (DT == VCT_F32) {
         const vct_v4f v = vct_struct_load_v4f32(rsrc, (int32_t)idx, 0, 0, 0);
         return make_float4(v.x, v.y, v.z, v.w);
     } else if constexpr (DT == VCT_F16) {

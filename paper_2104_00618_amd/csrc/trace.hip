@@ -75,9 +75,6 @@ hipError_t run_trace_any(const TraceArgs& a, float* out, unsigned long long* cou
 
 hipError_t vct_launch_trace(const TraceArgs& a, int dtype, float* out, unsigned long long* count, hipStream_t s,
                             EventSink& es) {
-    switch (dtype) {
-        case VCT_F32: return run_trace_any<VCT_F32>(a, out, count, s, es);
-        case VCT_F16: return run_trace_any<VCT_F16>(a, out, count, s, es);
-        default: return run_trace_any<VCT_BF16>(a, out, count, s, es);
-    }
+    return vct_dispatch_dt(dtype, a.wide != 0,
+                           [&](auto dt) { return run_trace_any<decltype(dt)::value>(a, out, count, s, es); });
 }

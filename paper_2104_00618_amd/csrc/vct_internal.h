@@ -3,6 +3,8 @@
 
 #include <stdint.h>
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include "texel.h"
@@ -107,6 +109,7 @@ struct TraceArgs {
     uint32_t ddelta[6][VCT_MAX_LEVELS];   // anisotropic: texel offset of direction d's level l minus lv[l].off
     float inv_scale2;              // (extent / N)^2: unit-axis weights w_a^2 = W_a^2 * inv_scale2
     int32_t aniso;                 // six directional pyramids (levels >= 1)
+    int32_t wide;                  // pyramid of more than 4 GiB: fetch through 64-bit addresses
     // G-buffer
     int32_t b, h, w;
     int32_t tiles_x, tiles_y, n_tiles;   // 16x16-pixel tiles
@@ -122,6 +125,21 @@ struct TraceArgs {
     float step_factor, t0, normal_offset, max_dist, alpha_thresh;
     int32_t max_steps;             // hard bound on samples per cone
 };
+
+// Calls f(std::integral_constant<int, DT>) with the kernel template argument
+// of a pyramid: its storage type, plus VCT_WIDE when it needs 64-bit fetches.
+template <typename F>
+static inline hipError_t vct_dispatch_dt(int dtype, bool wide, F&& f) {
+    using std::integral_constant;
+    switch (dtype) {
+        case VCT_F32:
+            return wide ? f(integral_constant<int, VCT_F32 | VCT_WIDE>{}) : f(integral_constant<int, VCT_F32>{});
+        case VCT_F16:
+            return wide ? f(integral_constant<int, VCT_F16 | VCT_WIDE>{}) : f(integral_constant<int, VCT_F16>{});
+        default:
+            return wide ? f(integral_constant<int, VCT_BF16 | VCT_WIDE>{}) : f(integral_constant<int, VCT_BF16>{});
+    }
+}
 
 // Optional per-kernel event recording (diagnostics): mark() records the next
 // registered event on the stream, before each kernel and after the last.

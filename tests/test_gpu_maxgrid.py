@@ -1,0 +1,102 @@
+"""The largest grid, 1024^3 in float32 (pyramid 19.6 GB isotropic, 31 GB
+anisotropic): texels far past 4 GiB into the pyramid are read correctly by the
+structured buffer loads.  The grid is zero except the corner block
+[768, 1024)^3; G-buffer points inside the block march short, narrow cones
+that stay inside it, so for every level they reach (LOD <= 4) the pyramid of
+the whole grid restricted to the block is the pyramid of the block alone, and
+the FP64 oracle runs on that 256^3 window (origin 0.75, extent 0.25, the same
+voxel size) instead of on the whole grid."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import vct_aniso as va
+import paper_2104_00618_amd as vct
+from scenes import ConeParams, cone_set, random_grid
+from tests.parity import fmt, range_errors, worst
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+N, W0 = 1024, 768
+
+
+def _inputs():
+    rng = np.random.default_rng(78)
+    h, w = 16, 16
+    pos = rng.uniform(0.83, 0.92, size=(1, h, w, 3))
+    rough = rng.uniform(0.05, 0.3, size=(1, h, w, 1))
+    nrm = rng.normal(size=(1, h, w, 3))
+    nrm /= np.linalg.norm(nrm, axis=-1, keepdims=True)
+    pr = np.concatenate([pos, rough], -1).astype(np.float32)
+    nr = np.concatenate([nrm, np.ones((1, h, w, 1))], -1).astype(np.float32)
+    cam = np.array([[0.875, 0.875, 0.5]], np.float32)
+    d, wt = cone_set("six")
+    ap = np.float32(0.349)      # 20 degrees: LOD <= 3.9 within max_dist
+    p = ConeParams(d, wt, diffuse_aperture=float(ap), spec_aperture_scale=float(ap), occ_aperture=float(ap),
+                   light_pos=(0.9, 0.95, 0.88), max_dist=0.04, alpha_thresh=0.99)
+    return pr, nr, cam, p
+
+
+@pytest.mark.parametrize("aniso", [False, True])
+def test_1024_cubed_f32_far_texels(aniso):
+    block = random_grid(N - W0, seed=77, alpha_max=0.25)
+    base = torch.zeros((N, N, N, 4), dtype=torch.float32, device=DEV)
+    base[W0:, W0:, W0:] = torch.from_numpy(block).to(DEV)
+    g = vct.Grid(N, anisotropic=aniso)
+    pyr = vct.build_mips(base, g)
+    del base
+    pr, nr, cam, p = _inputs()
+    out = vct.trace(pyr, g, torch.from_numpy(pr).to(DEV), torch.from_numpy(nr).to(DEV),
+                    torch.from_numpy(cam).to(DEV), p).cpu().numpy()
+    nbytes = pyr.numel()
+    del pyr
+    torch.cuda.empty_cache()
+    origin, extent = (W0 / N,) * 3, (N - W0) / N
+    if aniso:
+        ref, info = va.trace_aniso(va.build_aniso_mips(block), pr, nr, cam, p, origin, extent, return_info=True)
+    else:
+        ref, info = oracle.trace(oracle.build_mips(block), pr, nr, cam, p, origin, extent, return_info=True)
+    keep = ~info["ambiguous"].reshape(-1)
+    e = range_errors(out, ref, keep)
+    print(f"1024^3 f32 {'anisotropic' if aniso else 'isotropic'} ({nbytes / 2**30:.1f} GiB pyramid): {fmt(e)}; "
+          f"ambiguous {int((~keep).sum())}", flush=True)
+    assert worst(e)[0] <= 1e-5
+    assert np.abs(ref).max() > 0.05          # the cones do see the block
+
+
+def test_1024_cubed_f32_backward_saved():
+    """The training path at 1024^3 float32: trace_save + trace_backward_saved
+    against the oracle's adjoint on the window; every voxel outside it gets
+    exactly zero."""
+    block = random_grid(N - W0, seed=79, alpha_max=0.25)
+    base = torch.zeros((N, N, N, 4), dtype=torch.float32, device=DEV)
+    base[W0:, W0:, W0:] = torch.from_numpy(block).to(DEV)
+    g = vct.Grid(N)
+    pyr = vct.build_mips(base, g)
+    del base
+    pr, nr, cam, p = _inputs()
+    origin, extent = (W0 / N,) * 3, (N - W0) / N
+    mips = oracle.build_mips(block)
+    ref_out, info = oracle.trace(mips, pr, nr, cam, p, origin, extent, return_info=True)
+    # pixels with a termination tie may take another step count on either side: no gradient through them
+    gout = np.random.default_rng(80).normal(size=pr.shape[:3] + (8,)).astype(np.float32)
+    gout[info["ambiguous"]] = 0.0
+    t = [torch.from_numpy(a).to(DEV) for a in (pr, nr, cam)]
+    out, state = vct.trace_save(pyr, g, *t, p)
+    grad = vct.trace_backward_saved(pyr, g, *t, p, state, torch.from_numpy(gout).to(DEV))
+    del pyr, state
+    inside = grad[W0:, W0:, W0:].cpu().numpy()
+    grad[W0:, W0:, W0:] = 0
+    outside_nonzero = int(torch.count_nonzero(grad).item())
+    del grad
+    torch.cuda.empty_cache()
+    e = range_errors(out.cpu().numpy(), ref_out, ~info["ambiguous"].reshape(-1))
+    ref = oracle.trace_backward(mips, pr, nr, cam, p, gout, origin, extent)
+    scale = np.abs(ref).max()
+    err = np.abs(inside - ref).max() / scale
+    rms = np.sqrt(np.mean((inside - ref) ** 2)) / scale
+    print(f"1024^3 f32 training path: forward {fmt(e)}; gradient max {err:.2e} rms {rms:.2e}; "
+          f"{outside_nonzero} nonzero outside the block; {int(info['ambiguous'].sum())} tie pixels without "
+          f"gradient", flush=True)
+    assert worst(e)[0] <= 1e-5 and err <= 1e-4 and rms <= 1e-5 and outside_nonzero == 0
