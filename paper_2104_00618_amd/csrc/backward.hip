@@ -303,7 +303,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_bwd_pass2(TraceArgs a, const fl
             // pixel setup and dL/d(out) are reloaded per cone to keep registers free
             const PixelSetup P = pixel_setup(a, a.pos_rough[pix], a.normal[pix]);
             const float3 cam = make_float3(a.cam_pos[3 * view], a.cam_pos[3 * view + 1], a.cam_pos[3 * view + 2]);
-            pass2_init(a, P, cam, gout[2 * pix], gout[2 * pix + 1], state[pix * nslots + slot], slot, L);
+            pass2_init(a, P, cam, gout[2 * pix], gout[2 * pix + 1], lane_get(state, n_pixels(a), pix, slot), slot,
+                       L);
         }
         int Kw = L.K;
 #pragma unroll

@@ -17,6 +17,29 @@ struct LaneState {
     float4 st;   // sum_k |T_k|, sum_{k<K-1} |T_k / T_{k+1}|, max_k |C_k|, T_{K-1}
 };
 
+// Lane states are stored field-major: field f (hi, lo, st) of cone `slot` of
+// pixel `pix` is float4 number (slot * 3 + f) * n_pix + pix, so the 64 pixels
+// of a wave read and write contiguous 1 KiB runs.
+__device__ __forceinline__ LaneState lane_get(const LaneState* __restrict__ state, size_t n_pix, size_t pix,
+                                              int slot) {
+    const float4* f = reinterpret_cast<const float4*>(state) + (size_t)slot * 3 * n_pix + pix;
+    LaneState s;
+    s.hi = f[0];
+    s.lo = f[n_pix];
+    s.st = f[2 * n_pix];
+    return s;
+}
+
+__device__ __forceinline__ void lane_put(LaneState* __restrict__ state, size_t n_pix, size_t pix, int slot,
+                                         const LaneState& s) {
+    float4* f = reinterpret_cast<float4*>(state) + (size_t)slot * 3 * n_pix + pix;
+    f[0] = s.hi;
+    f[n_pix] = s.lo;
+    f[2 * n_pix] = s.st;
+}
+
+__device__ __forceinline__ size_t n_pixels(const TraceArgs& a) { return (size_t)a.b * a.h * a.w; }
+
 // dL/dC (3) and dL/dA of cone `slot` from the pixel's dL/d(out) = (g0, g1).
 __device__ __forceinline__ void slot_grads(const TraceArgs& a, int slot, float4 g0, float4 g1, float gc[3],
                                            float& ga) {
@@ -128,11 +151,11 @@ template <int DT>
 __device__ __forceinline__ float pass1_pixel(const TraceArgs& a, const LevelTable& T, const float4* __restrict__ gout,
                                              LaneState* __restrict__ state, int view, size_t pix) {
     const int nslots = a.n_diffuse + 2;
-    LaneState* st = state + pix * nslots;
+    const size_t np = n_pixels(a);
     float4 nr = a.normal[pix];
     float bound = 0.f;
     if (nr.w == 0.0f) {
-        for (int slot = 0; slot < nslots; ++slot) st[slot] = zero_lane_state();
+        for (int slot = 0; slot < nslots; ++slot) lane_put(state, np, pix, slot, zero_lane_state());
         return 0.f;
     }
     float4 pr = a.pos_rough[pix];
@@ -146,7 +169,7 @@ __device__ __forceinline__ float pass1_pixel(const TraceArgs& a, const LevelTabl
             out = lane_state(pass1_march<DT>(a, T, c));
             bound += lane_bound(a, slot, out, g0, g1);
         }
-        st[slot] = out;
+        lane_put(state, np, pix, slot, out);
     }
     return bound;
 }
@@ -159,7 +182,7 @@ __device__ __forceinline__ float saved_bound_pixel(const TraceArgs& a, const flo
     const float4 g0 = gout[2 * pix], g1 = gout[2 * pix + 1];
     float bound = 0.f;
     for (int slot = 0; slot < nslots; ++slot)
-        if (slot_enabled(a, slot)) bound += lane_bound(a, slot, state[pix * nslots + slot], g0, g1);
+        if (slot_enabled(a, slot)) bound += lane_bound(a, slot, lane_get(state, n_pixels(a), pix, slot), g0, g1);
     return bound;
 }
 
@@ -171,10 +194,10 @@ __device__ __forceinline__ void trace_save_pixel(const TraceArgs& a, const Level
     o0 = make_float4(0.f, 0.f, 0.f, 0.f);
     o1 = o0;
     const int nslots = a.n_diffuse + 2;
-    LaneState* st = state + pix * nslots;
+    const size_t np = n_pixels(a);
     float4 nr = a.normal[pix];
     if (nr.w == 0.0f) {
-        for (int slot = 0; slot < nslots; ++slot) st[slot] = zero_lane_state();
+        for (int slot = 0; slot < nslots; ++slot) lane_put(state, np, pix, slot, zero_lane_state());
         return;
     }
     PixelSetup P = pixel_setup(a, a.pos_rough[pix], nr);
@@ -200,7 +223,7 @@ __device__ __forceinline__ void trace_save_pixel(const TraceArgs& a, const Level
                 o1.w = r.A;
             }
         }
-        st[slot] = out;
+        lane_put(state, np, pix, slot, out);
     }
 }
 
