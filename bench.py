@@ -90,21 +90,73 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, n_pix=24576, seed=0):
-    """The FP64 oracle as it stands on a seeded pixel sample of the same frame
-    (build_mips of the full grid + all cones of n_pix pixels)."""
+def cpu_baseline(w, n_pix=12288, seed=0):
+    """The FP64 oracle as it stands doing the step on a seeded pixel sample of
+    the same frame: build_mips of the full grid, the forward of all cones of
+    n_pix pixels and its adjoint (seeded dL/d(out)).  Returns the baseline and
+    the timed parts (for the per-row table)."""
     import oracle
     from tests.workloads import sample_pixels
 
     v, y, x = sample_pixels(w.shape, n_pix, seed)
-    t = time.perf_counter()
+    pr, nr = w.pos_rough[v, y, x][None, None], w.normal[v, y, x][None, None]
+    gout = np.random.default_rng(seed).normal(size=(1, 1, n_pix, 8)) * 1e-3
+    t0 = time.perf_counter()
     mips = oracle.build_mips(w.base)
-    _, info = oracle.trace(mips, w.pos_rough[v, y, x][None, None], w.normal[v, y, x][None, None], w.cam_pos,
-                           w.params, return_info=True)
+    t1 = time.perf_counter()
+    _, info = oracle.trace(mips, pr, nr, w.cam_pos, w.params, return_info=True)
+    t2 = time.perf_counter()
+    oracle.trace_backward(mips, pr, nr, w.cam_pos, w.params, gout)
+    t3 = time.perf_counter()
+    n = info["samples"]
+    parts = {"mips_s": t1 - t0, "forward_s": t2 - t1, "backward_s": t3 - t2, "samples": n, "pixels": n_pix}
+    base = {"value": n / (t3 - t0), "unit": "cone samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"build_mips of the 256^3 grid + forward and adjoint of all 7 cones of {n_pix} seeded pixels "
+                      f"of the 1080p frame ({n} samples; {t1 - t0:.1f} + {t2 - t1:.1f} + {t3 - t2:.1f} s, NumPy "
+                      f"FP64, single thread)"}
+    return base, parts
+
+
+def cpu_rows(w, vox_mesh, vlights, seed=1):
+    """The oracle on bounded samples of the other rows' workloads (seconds each)."""
+    import oracle
+    from oracle import vct_aniso, vct_bounce, vct_shade, vct_voxelize
+    from scenes import random_material, scene_lights
+    from tests.workloads import sample_pixels
+
+    out = {}
+    mips = oracle.build_mips(w.base)
+    v, y, x = sample_pixels(w.shape, 2048, seed)
+    pr, nr = w.pos_rough[v, y, x][None, None], w.normal[v, y, x][None, None]
+    mat = random_material(pr.shape[:3], seed)
+    t = time.perf_counter()
+    vct_shade.shade(mips, pr, nr, mat, w.cam_pos, w.params, scene_lights(3))
     dt = time.perf_counter() - t
-    return {"value": info["samples"] / dt, "unit": "cone samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"build_mips of the 256^3 grid + all 7 cones of {n_pix} seeded pixels of the 1080p frame "
-                      f"({info['samples']} samples, {dt:.1f} s, NumPy FP64, single thread)"}
+    out["f1_shade"] = {"value": 2048 / dt, "unit": "pixels/s", "cores": 1, "kind": "oracle",
+                       "sample": f"2048 seeded pixels of the 1080p frame, 3 lights, pyramid given ({dt:.1f} s)"}
+    tris, cols = vox_mesh
+    t = time.perf_counter()
+    vb, vn, va_ = vct_voxelize.voxelize(tris, cols, w.n, vlights, return_surface=True)
+    dt = time.perf_counter() - t
+    out["f2_voxelize"] = {"value": len(tris) / dt, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+                          "sample": f"the whole {len(tris)}-triangle Cornell mesh at {w.n}^3 with surface grids "
+                                    f"({dt:.1f} s)"}
+    surf = np.argwhere(vct_bounce.surface_mask(vb, vn))
+    pick = surf[np.random.default_rng(seed).choice(len(surf), size=min(2000, len(surf)), replace=False)]
+    t = time.perf_counter()
+    vct_bounce.bounce(vb, vn, va_, w.params, voxels=pick)
+    dt = time.perf_counter() - t
+    out["f3_bounce"] = {"value": len(pick) / dt, "unit": "surface voxels/s", "cores": 1, "kind": "oracle",
+                        "sample": f"{len(pick)} seeded surface voxels of the {w.n}^3 mesh grid, pyramid built "
+                                  f"({dt:.1f} s)"}
+    t = time.perf_counter()
+    am = vct_aniso.build_aniso_mips(w.base)
+    _, info = vct_aniso.trace_aniso(am, pr[:, :, :1024], nr[:, :, :1024], w.cam_pos, w.params, return_info=True)
+    dt = time.perf_counter() - t
+    out["f4_anisotropic"] = {"value": info["samples"] / dt, "unit": "cone samples/s", "cores": 1, "kind": "oracle",
+                             "sample": f"anisotropic pyramids of the {w.n}^3 grid + all 7 cones of 1024 seeded "
+                                       f"pixels ({info['samples']} samples, {dt:.1f} s)"}
+    return out
 
 
 BOUNCE_KERNELS = ["flag + copy", "scan", "list", "gather"]
@@ -267,6 +319,7 @@ def main():
     # per-frame revoxelization: voxelize the Cornell mesh (direct-light injection) into the 256^3 base grid
     from scenes.mesh import cornell_mesh
     vt, vc = cornell_mesh(1)
+    vox_mesh = (vt, vc)
     vox_tris = int(vt.shape[0])
     vt, vc = T(vt), T(vc)
     vws = torch.empty(vct.voxelize_workspace_bytes(grid, vox_tris), dtype=torch.uint8, device=dev)
@@ -361,9 +414,54 @@ def main():
         "breakdown": breakdown,
         "roofline": roofline,
     }
+    mip_bytes = w.n ** 3 * 16 + int(pyr.numel()) - 2 * ((w.n // 16) ** 3) * 16   # base read + levels written
+    vox_bytes = w.n ** 3 * (32 + 32 + 16)        # accumulators cleared, read back, base written
+    rows = {
+        "a1_build_mips": {"kernel": "k_mip_block", "ms": mips_ms, "bound": "hbm",
+                          "achieved": mip_bytes / (mips_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": mip_bytes / (mips_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "model": f"float32 base read once + every level written ({mip_bytes} bytes)"},
+        "a2_a6_trace": {"kernel": "k_trace", "ms": fwd_ms, "bound": "alu",
+                        "achieved": FLOPS_FWD_SAMPLE * samples / (fwd_ms * 1e-3) / 1e12, "peak": ALU_PEAK_TFLOPS,
+                        "unit": "TFLOP/s",
+                        "frac": FLOPS_FWD_SAMPLE * samples / (fwd_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+                        "model": f"{FLOPS_FWD_SAMPLE} FP32 ops per cone sample x {samples} samples",
+                        "logical_tap_GBps": trace_gbs},
+        "a7_backward": dict(roofline, ms=bwd_ms),
+        "f1_shade": {"kernel": "k_shade", "ms": shade_ms["3_lights"], "pixels_per_s": npix / (shade_ms["3_lights"] * 1e-3),
+                     "bound": "alu", "achieved": None,
+                     "model": "the sampler and march of k_trace; its cone samples are not counted, so no rate"},
+        "f2_voxelize": {"kernel": "k_clear + k_tri_setup + k_chunk_scan + k_raster + k_resolve", "ms": vox_ms,
+                        "bound": "hbm", "achieved": vox_bytes / (vox_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": vox_bytes / (vox_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "model": f"80 B per voxel: 32 B accumulator cleared, read back, 16 B written ({vox_bytes} bytes)"},
+        "f3_bounce": {"kernel": "k_gather (k_flag: hbm)", "ms": bounce["bounce_ms"], "bound": "alu",
+                      "achieved": FLOPS_FWD_SAMPLE * bounce["samples"] / (bounce["bounce_kernels_ms"]["gather"] * 1e-3) / 1e12,
+                      "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": bounce["gather_frac_of_alu_peak"],
+                      "model": f"{FLOPS_FWD_SAMPLE} FP32 ops per cone sample x {bounce['samples']} samples",
+                      "flag_frac_of_hbm_peak": bounce["flag_frac_of_hbm_peak"]},
+        "f4_anisotropic": {"kernel": "k_trace<ANISO>", "ms": aniso["trace_ms"], "bound": "alu",
+                           "achieved": FLOPS_FWD_SAMPLE * aniso["samples_per_frame"] / (aniso["trace_ms"] * 1e-3) / 1e12,
+                           "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": FLOPS_FWD_SAMPLE * aniso["samples_per_frame"] / (aniso["trace_ms"] * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+                           "model": f"{FLOPS_FWD_SAMPLE} FP32 ops per cone sample (the isotropic count: a lower bound, "
+                                    f"samples above level 0 read up to three directions)"},
+    }
+    res["rows"] = rows
     if not args.no_cpu_baseline:
-        log("timing the oracle on a pixel sample")
-        res["cpu_baseline"] = cpu_baseline(w)
+        log("timing the oracle on bounded samples")
+        base_cpu, parts = cpu_baseline(w)
+        res["cpu_baseline"] = base_cpu
+        rows["a1_build_mips"]["cpu_baseline"] = {"value": w.n ** 3 / parts["mips_s"], "unit": "base texels/s",
+                                                 "cores": 1, "kind": "oracle", "sample": f"the whole {w.n}^3 grid"}
+        rows["a2_a6_trace"]["cpu_baseline"] = {"value": parts["samples"] / parts["forward_s"], "unit": "cone samples/s",
+                                               "cores": 1, "kind": "oracle",
+                                               "sample": f"all 7 cones of {parts['pixels']} seeded pixels"}
+        rows["a7_backward"]["cpu_baseline"] = {"value": parts["samples"] / parts["backward_s"],
+                                               "unit": "cone samples/s", "cores": 1, "kind": "oracle",
+                                               "sample": f"adjoint of all 7 cones of {parts['pixels']} seeded pixels"}
+        for k, v in cpu_rows(w, vox_mesh, vlights).items():
+            rows[k]["cpu_baseline"] = v
     print(json.dumps(res), flush=True)
 
 
