@@ -327,8 +327,16 @@ def main():
     vlights = [((0.5, 0.95, 0.5), (1.0, 1.0, 1.0), (1.0, 0.5, 0.25))]
     vox_ms = timed(lambda: vct.voxelize(vt, vc, grid, vlights, base=vbase, workspace=vws), args.steps)
     del vws
+    # the same room with 256 x 512 spheres: 522,286 triangles, most smaller than a voxel
+    bt, bc = cornell_mesh(1, rings=256, segments=512)
+    big_tris = int(bt.shape[0])
+    bt, bc = T(bt), T(bc)
+    vws = torch.empty(vct.voxelize_workspace_bytes(grid, big_tris), dtype=torch.uint8, device=dev)
+    vox_big_ms = timed(lambda: vct.voxelize(bt, bc, grid, vlights, base=vbase, workspace=vws), args.steps)
+    del vws, bt, bc
     log(f"trace alone {fwd_ms:.3f} ms; recompute path step {mips_ms + fwd_ms + recompute_bwd_ms:.3f} ms; "
-        f"shade {', '.join(f'{k} {v:.3f} ms' for k, v in shade_ms.items())}; voxelize {vox_ms:.3f} ms")
+        f"shade {', '.join(f'{k} {v:.3f} ms' for k, v in shade_ms.items())}; voxelize {vox_ms:.3f} ms "
+        f"({vox_tris} triangles), {vox_big_ms:.3f} ms ({big_tris} triangles)")
     bounce = bench_bounce(vct, torch, grid, vt, vc, vlights, w.params, timed, args.steps)
     # the same frame through an anisotropic (six-direction) pyramid
     ga = vct.Grid(w.n, dtype=args.dtype, anisotropic=True)
@@ -352,7 +360,9 @@ def main():
         "trace_backward_saved_kernels_ms": {n: float(t) for n, t in zip(BWD_KERNELS, bwd_k)},
         "trace_ms": fwd_ms, "fwd_ms_per_frame": mips_ms + fwd_ms,
         "shade_ms": shade_ms,
-        "revoxelize": {"triangles": vox_tris, "voxelize_ms": vox_ms, "voxelize_plus_mips_ms": vox_ms + mips_ms},
+        "revoxelize": {"triangles": vox_tris, "voxelize_ms": vox_ms, "voxelize_plus_mips_ms": vox_ms + mips_ms,
+                       "dense_mesh": {"triangles": big_tris, "voxelize_ms": vox_big_ms,
+                                      "triangles_per_s": big_tris / (vox_big_ms * 1e-3)}},
         "bounce": bounce,
         "anisotropic": aniso,
         "fwd_bwd_ms_per_frame": mips_ms + save_ms + bwd_ms,

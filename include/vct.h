@@ -298,7 +298,7 @@ int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf
  *   normal     device float32 [N][N][N][4] average normal, overwritten; or null (no surface attributes)
  *   albedo     device float32 [N][N][N][4] average colour, overwritten; null exactly when normal is
  *   workspace  device, vct_voxelize_workspace_bytes(grid, n_tris, surface) bytes (32 per voxel, 48 more
- *              with surface attributes, 160 per triangle); surface != 0 sizes it for normal/albedo output
+ *              with surface attributes, about 160 per triangle); surface != 0 sizes it for normal/albedo output
  * Errors: VCT_EINVAL for a bad grid, n_tris outside [0, 2^31), null buffers,
  * only one of normal / albedo given, n_lights outside 0..8, non-finite or
  * negative light parameters or attenuation all 0; VCT_EWORKSPACE if the

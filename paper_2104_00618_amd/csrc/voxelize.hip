@@ -20,10 +20,12 @@
 // normal textures from voxelization, Section 5.1.3).
 //
 // Launch: a setup pass (one thread per triangle) writes each triangle's
-// rasterization record and its number of 256-pixel chunks, one workgroup
-// scans the chunk counts, and the raster pass hands (triangle, chunk) items to
-// waves in a grid-stride loop, so a wall-sized triangle is spread over many
-// waves.  Per voxel the workspace holds {int64 r, g, b; uint32 count; pad}
+// rasterization record and the pixel count of its bounding box; a three-phase
+// scan (sums of 1024 counts, one workgroup over those sums, offsets inside
+// each 1024) turns the counts into offsets; the raster pass then walks the
+// flattened pixel space, one lane per bounding-box pixel, each lane finding its
+// triangle by a binary search of the offsets.  A wall-sized triangle spreads
+// over many waves and a thousand one-pixel triangles fill a wave.  Per voxel the workspace holds {int64 r, g, b; uint32 count; pad}
 // (32 bytes), and with surface attributes {int64 nx, ny, nz, r, g, b} (48 bytes)
 // more, cleared by a fill kernel (no memset, so the path can be captured in a
 // graph); a resolve pass writes the float32 grids.
@@ -85,15 +87,16 @@ struct TriSetup {
     float n[3], col[3];
 };
 
-constexpr int kChunk = 256;          // pixels per wave per work item
+constexpr int kScanBlock = 1024;     // counts per block of the offset scan (256 threads x 4)
+constexpr int kScanThreads = 1024;   // threads of the one-workgroup scan of block sums
 
 __global__ __launch_bounds__(256) void k_tri_setup(VoxArgs a, const float* __restrict__ tris,
                                                    const float* __restrict__ colors, long long n_tris,
-                                                   TriSetup* __restrict__ setup, unsigned long long* __restrict__ chunks) {
+                                                   TriSetup* __restrict__ setup, unsigned long long* __restrict__ counts) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tris) return;
     TriSetup r{};
-    chunks[t] = 0;
+    counts[t] = 0;
     // snapped vertices (float32 arithmetic, round half to even)
     float vf[3][3];
     long long s[3][3];
@@ -172,31 +175,74 @@ __global__ __launch_bounds__(256) void k_tri_setup(VoxArgs a, const float* __res
         r.col[i] = colors[t * 3 + i];
     }
     setup[t] = r;
-    chunks[t] = (unsigned long long)((r.npx + kChunk - 1) / kChunk);
+    counts[t] = (unsigned long long)r.npx;
 }
 
-// Exclusive prefix sum of the chunk counts, in place, one workgroup; the
-// total goes to *total.
-__global__ __launch_bounds__(256) void k_chunk_scan(unsigned long long* __restrict__ c, long long n,
-                                                    unsigned long long* __restrict__ total) {
-    __shared__ unsigned long long s[256];
-    unsigned long long carry = 0;
-    for (long long base = 0; base < n; base += 256) {
-        const long long i = base + threadIdx.x;
-        const unsigned long long v = i < n ? c[i] : 0ull;
-        s[threadIdx.x] = v;
+// Offset scan, phase 1: the sum of each block of kScanBlock counts.
+__global__ __launch_bounds__(256) void k_block_sums(const unsigned long long* __restrict__ c, long long n,
+                                                    unsigned long long* __restrict__ bsum) {
+    __shared__ unsigned long long s[4];
+    const long long i0 = (long long)blockIdx.x * kScanBlock + threadIdx.x * 4;
+    unsigned long long v = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v += i0 + k < n ? c[i0 + k] : 0ull;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+// Phase 2, one workgroup: bsum[b] becomes the sum of bsum[0..b); *total the sum of all.
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(unsigned long long* __restrict__ bsum, long long nb,
+                                                            unsigned long long* __restrict__ total) {
+    __shared__ unsigned long long s[kScanThreads];
+    const long long per = (nb + kScanThreads - 1) / kScanThreads;
+    const long long b = threadIdx.x * per, e = min(b + per, nb);
+    unsigned long long own = 0;
+    for (long long i = b; i < e; ++i) own += bsum[i];
+    s[threadIdx.x] = own;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {   // inclusive Hillis-Steele scan
+        const unsigned long long add = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0ull;
         __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {   // inclusive Hillis-Steele scan
-            const unsigned long long add = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0ull;
-            __syncthreads();
-            s[threadIdx.x] += add;
-            __syncthreads();
-        }
-        if (i < n) c[i] = carry + s[threadIdx.x] - v;
-        carry += s[255];
+        s[threadIdx.x] += add;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *total = carry;
+    unsigned long long run = s[threadIdx.x] - own;
+    for (long long i = b; i < e; ++i) {
+        const unsigned long long c = bsum[i];
+        bsum[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == kScanThreads - 1) *total = s[kScanThreads - 1];
+}
+
+// Phase 3: counts become exclusive offsets, in place (block base + prefix inside the block).
+__global__ __launch_bounds__(256) void k_block_offsets(unsigned long long* __restrict__ c, long long n,
+                                                       const unsigned long long* __restrict__ bsum) {
+    __shared__ unsigned long long s[256];
+    const long long i0 = (long long)blockIdx.x * kScanBlock + threadIdx.x * 4;
+    unsigned long long v[4], own = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = i0 + k < n ? c[i0 + k] : 0ull;
+        own += v[k];
+    }
+    s[threadIdx.x] = own;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {   // inclusive Hillis-Steele scan of the thread sums
+        const unsigned long long add = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0ull;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    unsigned long long run = bsum[blockIdx.x] + s[threadIdx.x] - own;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (i0 + k < n) {
+            c[i0 + k] = run;
+            run += v[k];
+        }
 }
 
 // floor(a / b) for b > 0 from a float estimate corrected in exact int64 arithmetic
@@ -208,32 +254,30 @@ __device__ __forceinline__ long long floor_div_est(long long a, long long b) {
     return q;
 }
 
-// Work items are (triangle, chunk of kChunk pixels); each wave takes items
-// k = wave, wave + n_waves, ... below the total and finds the triangle by a
-// binary search of the chunk offsets.
+// One lane per bounding-box pixel of the flattened pixel space (triangle t
+// owns [offs[t], offs[t] + npx)), in a grid-stride loop; a lane's triangle is
+// the last t with offs[t] <= g (a triangle without pixels has offs[t] =
+// offs[t + 1] and is passed over).
 template <bool SURF>
 __global__ __launch_bounds__(256) void k_raster(VoxArgs a, const TriSetup* __restrict__ setup,
                                                 const unsigned long long* __restrict__ offs, long long n_tris,
                                                 const unsigned long long* __restrict__ total_p,
                                                 VoxAcc* __restrict__ acc, SurfAcc* __restrict__ surf) {
-    const int lane = threadIdx.x & 63;
-    const unsigned long long n_waves = (unsigned long long)gridDim.x * (blockDim.x >> 6);
     const unsigned long long total = *total_p;
-    for (unsigned long long k = (unsigned long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < total;
-         k += n_waves) {
-        long long lo = 0, hi = n_tris - 1;            // last triangle with offs[t] <= k
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    const long long h = kSub / 2;
+    const float sub_to_world = a.voxel / (float)kSub;
+    for (unsigned long long g = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+        long long lo = 0, hi = n_tris - 1;
         while (lo < hi) {
             const long long mid = (lo + hi + 1) >> 1;
-            if (offs[mid] <= k) lo = mid;
+            if (offs[mid] <= g) lo = mid;
             else hi = mid - 1;
         }
         const TriSetup& r = setup[lo];
-        const int first = (int)(k - offs[lo]) * kChunk;
-        const int last = min(first + kChunk, r.npx);
-        const long long h = kSub / 2;
+        const int p = (int)(g - offs[lo]);
         const long long den = r.nw * kSub;
-        const float sub_to_world = a.voxel / (float)kSub;
-        for (int p = first + lane; p < last; p += 64) {
+        {
             const int pj_off = (int)((unsigned)p / (unsigned)r.w);
             const long long pi = r.i0 + (p - pj_off * r.w), pj = r.j0 + pj_off;
             const long long PX = pi * kSub + h, PY = pj * kSub + h;
@@ -317,14 +361,15 @@ __global__ __launch_bounds__(256) void k_resolve(const VoxAcc* __restrict__ acc,
 }  // namespace
 
 // Workspace: the per-voxel accumulators (with surface attributes, their sums
-// follow), then per-triangle setup records, the chunk offsets and the chunk
-// total.
+// follow), then per-triangle setup records, the pixel offsets, the pixel total
+// and the block sums of the offset scan.
 size_t vct_voxelize_acc_bytes(int n, bool surface) {
     return (size_t)n * n * n * (sizeof(VoxAcc) + (surface ? sizeof(SurfAcc) : 0));
 }
 
 size_t vct_voxelize_workspace_size(int n, long long n_tris, bool surface) {
-    return vct_voxelize_acc_bytes(n, surface) + (size_t)n_tris * (sizeof(TriSetup) + 8) + 256;
+    return vct_voxelize_acc_bytes(n, surface) + (size_t)n_tris * (sizeof(TriSetup) + 8) + 256 +
+           (size_t)((n_tris + kScanBlock - 1) / kScanBlock) * 8;
 }
 
 hipError_t vct_launch_voxelize(const vct_grid* g, const float* tris, const float* colors, long long n_tris,
@@ -353,6 +398,8 @@ hipError_t vct_launch_voxelize(const vct_grid* g, const float* tris, const float
     TriSetup* setup = reinterpret_cast<TriSetup*>(w + acc_bytes);
     unsigned long long* offs = reinterpret_cast<unsigned long long*>(setup + n_tris);
     unsigned long long* total = offs + n_tris;
+    unsigned long long* bsum = total + 32;      // (the 256 bytes after the offsets hold the total)
+    const long long nb = (n_tris + kScanBlock - 1) / kScanBlock;
     const int fill_blocks = (int)min((acc_bytes / 16 + 255) / 256, (size_t)65536);
     es.mark(st);
     hipLaunchKernelGGL(k_clear, dim3(fill_blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(ws), acc_bytes / 16);
@@ -360,7 +407,9 @@ hipError_t vct_launch_voxelize(const vct_grid* g, const float* tris, const float
     if (n_tris > 0) {
         hipLaunchKernelGGL(k_tri_setup, dim3((unsigned)((n_tris + 255) / 256)), dim3(256), 0, st, a, tris, colors,
                            n_tris, setup, offs);
-        hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(256), 0, st, offs, n_tris, total);
+        hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nb), dim3(256), 0, st, offs, n_tris, bsum);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, st, bsum, nb, total);
+        hipLaunchKernelGGL(k_block_offsets, dim3((unsigned)nb), dim3(256), 0, st, offs, n_tris, bsum);
         if (surface)
             hipLaunchKernelGGL(k_raster<true>, dim3(2048), dim3(256), 0, st, a, setup, offs, n_tris, total, acc, surf);
         else
