@@ -6,4 +6,5 @@ from .vct_oracle import (build_mips, mip_adjoint, taps, sample, cone_lanes, marc
                          assemble, trace, trace_backward, lane_grads, render)
 from .vct_shade import f_spec, shade, smoothstep  # noqa: F401
 from .vct_bounce import MIN_NORMAL, bounce, bounces, surface_mask  # noqa: F401
-from .vct_aniso import aniso_sampler, build_aniso_mips, sample_aniso, trace_aniso  # noqa: F401
+from .vct_aniso import (aniso_mip_adjoint, aniso_sampler, build_aniso_mips, sample_aniso, trace_aniso,  # noqa: F401
+                        trace_backward_aniso)

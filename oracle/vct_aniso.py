@@ -20,6 +20,14 @@ pre-integration of voxel cone tracing is taken):
                     w_a^2 times the quadrilinear sample of the pyramid whose
                     direction is sign(w_a) along axis a.
 * trace_aniso       the forward trace (readings R1-R12) with that sampler.
+* trace_backward_aniso
+                    its adjoint with respect to the base grid (step counts
+                    held fixed, R12): each sample's gradient goes to its taps
+                    in the three pyramids it read, weighted by w_a^2 (to the
+                    shared level 0 with the sum of the three), and each
+                    direction's level gradients flow down through the
+                    transpose of the linearised front-to-back composite into
+                    the level below, ending in the shared level 0.
 
 Readings (also listed in the repository's design notes):
 
@@ -38,7 +46,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .vct_oracle import assemble, cone_lanes, march, sample
+from .vct_oracle import assemble, cone_lanes, march, sample, taps, trace_backward
 
 DIRECTIONS = ("+x", "-x", "+y", "-y", "+z", "-z")
 
@@ -117,3 +125,71 @@ def trace_aniso(amips, pos_rough, normal, cam_pos, params, origin=(0.0, 0.0, 0.0
     amb_pix = np.zeros(int(np.prod(shape)), dtype=bool)
     np.logical_or.at(amb_pix, lanes["pix"], res["ambiguous"])
     return out, {"ambiguous": amb_pix.reshape(shape), "samples": int(res["K"].sum()), "K": res["K"]}
+
+
+def _reduce_adjoint(G, child, axis, front_even):
+    """Gradient of the level below from the gradient G [m, m, m, 4] of a
+    directional level: parent = (1/4) sum over the four pairs of
+    over(f, b) = f + (1 - f.a) b, so a front child receives
+    (1/4)(G - e_a (G . b)) and a back child (1/4)(1 - f.a) G."""
+    Gu = G
+    for ax in range(3):
+        if ax != axis:
+            Gu = np.repeat(Gu, 2, axis=ax)
+    ev = np.take(child, np.arange(0, child.shape[axis], 2), axis=axis)
+    od = np.take(child, np.arange(1, child.shape[axis], 2), axis=axis)
+    f, b = (ev, od) if front_even else (od, ev)
+    gf = 0.25 * Gu
+    gf[..., 3] -= 0.25 * np.sum(Gu * b, axis=-1)
+    gb = 0.25 * Gu * (1.0 - f[..., 3:4])
+    out = np.empty_like(child)
+    even = [slice(None)] * 3
+    odd = [slice(None)] * 3
+    even[axis] = slice(0, None, 2)
+    odd[axis] = slice(1, None, 2)
+    out[tuple(even)] = gf if front_even else gb
+    out[tuple(odd)] = gb if front_even else gf
+    return out
+
+
+def aniso_mip_adjoint(amips, level_grads):
+    """dL/d(base) from per-direction level gradients level_grads[d][l] (level 0
+    entries are the shared level's, summed over d), walking every direction
+    from its top level down."""
+    nlev = len(amips[0])
+    G0 = sum(level_grads[d][0] for d in range(6))
+    for d in range(6):
+        axis = 2 - d // 2
+        front_even = d % 2 == 0
+        g = level_grads[d][nlev - 1].copy() if nlev > 1 else None
+        for lv in range(nlev - 1, 0, -1):
+            below = _reduce_adjoint(g, amips[d][lv - 1], axis, front_even)
+            if lv - 1 == 0:
+                G0 = G0 + below
+            else:
+                g = level_grads[d][lv - 1] + below
+    return G0
+
+
+def trace_backward_aniso(amips, pos_rough, normal, cam_pos, params, grad_out, origin=(0.0, 0.0, 0.0), extent=1.0):
+    """Adjoint of trace_aniso with respect to the base grid: [N, N, N, 4] float64."""
+    grads = [[np.zeros_like(m) for m in pyr] for pyr in amips]
+
+    def scatter(p, lam, w, gs):
+        w2 = w ** 2
+        for lev, iz, iy, ix, wt in taps(amips[0], p, lam, origin, extent):
+            for lv in np.unique(lev):
+                sel = lev == lv
+                for a in range(3):
+                    if lv == 0:
+                        # the three directions read the same level-0 texel
+                        np.add.at(grads[0][0], (iz[sel], iy[sel], ix[sel]), (wt[sel] * w2[sel, a])[:, None] * gs[sel])
+                        continue
+                    for d, sd in ((2 * a, w[:, a] >= 0), (2 * a + 1, w[:, a] < 0)):
+                        s2 = sel & sd
+                        if s2.any():
+                            np.add.at(grads[d][lv], (iz[s2], iy[s2], ix[s2]), (wt[s2] * w2[s2, a])[:, None] * gs[s2])
+
+    return trace_backward(amips[0], pos_rough, normal, cam_pos, params, grad_out, origin, extent,
+                          sampler=aniso_sampler(amips, origin, extent), scatter=scatter,
+                          adjoint=lambda: aniso_mip_adjoint(amips, grads))

@@ -338,7 +338,8 @@ def lane_grads(lanes, params, grad_out):
 
 
 def trace_backward(mips, pos_rough, normal, cam_pos, params, grad_out,
-                   origin=(0.0, 0.0, 0.0), extent=1.0, return_levels=False):
+                   origin=(0.0, 0.0, 0.0), extent=1.0, return_levels=False, sampler=None, scatter=None,
+                   adjoint=None):
     """Adjoint of trace (R12): dL/d(base grid) [N,N,N,4] float64.
 
     Every step of every lane is recorded; a reverse sweep then carries the
@@ -346,10 +347,14 @@ def trace_backward(mips, pos_rough, normal, cam_pos, params, grad_out,
     (R_K = 0, U_K = 1), giving dL/dc_k = T_k dL/dC and
     dL/da_k = T_k (-dL/dC . R_{k+1} + dL/dA U_{k+1}), T_k = 1 - alpha_k.
     Each sample's gradient is scattered to its 16 taps with the tap weights,
-    then carried through the mip reduction by its transpose."""
+    then carried through the mip reduction by its transpose.
+
+    Hooks for other pyramids: sampler (see march); scatter(p, lam, w, gs)
+    replaces the scatter into the isotropic level gradients and adjoint()
+    the mip adjoint (then return_levels is not available)."""
     n = mips[0].shape[0]
     lanes = cone_lanes(pos_rough, normal, cam_pos, params, n, origin, extent)
-    res = march(mips, lanes, params, origin, extent, record=True)
+    res = march(mips, lanes, params, origin, extent, record=True, sampler=sampler)
     gc, ga = lane_grads(lanes, params, grad_out)
     m = len(lanes["gamma"])
     R = np.zeros((m, 3))
@@ -363,10 +368,15 @@ def trace_backward(mips, pos_rough, normal, cam_pos, params, grad_out,
         U[idx] = (1.0 - s[:, 3]) * U[idx]
         gs = np.concatenate([g_c, g_a[:, None]], axis=1)
         p = lanes["o"][idx] + ti[:, None] * lanes["w"][idx]
+        if scatter is not None:
+            scatter(p, lam, lanes["w"][idx], gs)
+            continue
         for lev, iz, iy, ix, wt in taps(mips, p, lam, origin, extent):
             for l in np.unique(lev):
                 sel = lev == l
                 np.add.at(level_grads[l], (iz[sel], iy[sel], ix[sel]), wt[sel, None] * gs[sel])
+    if adjoint is not None:
+        return adjoint()
     gb = mip_adjoint(level_grads)
     if return_levels:
         return gb, level_grads

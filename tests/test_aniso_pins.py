@@ -199,3 +199,59 @@ def test_uniform_medium_shading_and_bounce_through_the_sampler_hook():
     alb[..., 0:3] = rho
     got = vb.bounce(base, nrm, alb, p, mips=iso, sampler=smp)
     np.testing.assert_allclose(got[..., 0:3], np.broadcast_to(c + a * rho * W * Cd, (n, n, n, 3)), rtol=1e-12)
+
+
+def test_aniso_mip_adjoint_is_the_derivative_of_the_build():
+    """<adjoint(G), delta> = d/de <G, build(base + e delta)> at e = 0 (central
+    differences; the build is a polynomial in the base, so h = 1e-4 is exact to
+    rounding)."""
+    rng = np.random.default_rng(11)
+    n = 8
+    base = np.concatenate([rng.uniform(0, 0.6, size=(n, n, n, 3)), rng.uniform(0, 0.9, size=(n, n, n, 1))], -1)
+    delta = rng.normal(size=base.shape)
+    am = va.build_aniso_mips(base)
+    G = [[rng.normal(size=m.shape) for m in pyr] for pyr in am]
+    got = np.sum(va.aniso_mip_adjoint(am, G) * delta)
+
+    def pairing(b):
+        a = va.build_aniso_mips(b)
+        # level 0 is shared: pair it once with the sum of the six level-0 gradients, as the adjoint does
+        return (np.sum(sum(G[d][0] for d in range(6)) * a[0][0])
+                + sum(np.sum(G[d][lv] * a[d][lv]) for d in range(6) for lv in range(1, len(a[d]))))
+
+    h = 1e-4
+    fd = (pairing(base + h * delta) - pairing(base - h * delta)) / (2 * h)
+    np.testing.assert_allclose(got, fd, rtol=1e-9)
+
+
+def test_aniso_trace_adjoint_matches_finite_differences():
+    rng = np.random.default_rng(12)
+    n = 8
+    base = np.concatenate([rng.uniform(0, 0.5, size=(n, n, n, 3)), rng.uniform(0, 0.35, size=(n, n, n, 1))], -1)
+    base[..., 0:3] *= base[..., 3:4]
+    pr = np.concatenate([rng.uniform(0.3, 0.7, size=(1, 2, 3, 3)), np.full((1, 2, 3, 1), 0.6)], -1)
+    nr = np.concatenate([rng.normal(size=(1, 2, 3, 3)), np.ones((1, 2, 3, 1))], -1)
+    cam = np.array([[0.5, 0.5, 2.0]])
+    dirs = np.array([[0, 0, 1], [0.6, 0, 0.8], [0, -0.6, 0.8]], np.float32)
+    p = ConeParams(dirs, np.array([0.5, 0.3, 0.2], np.float32), diffuse_aperture=1.0, spec_aperture_scale=1.2,
+                   occ_aperture=0.9, light_pos=(0.5, 0.9, 0.5), step_factor=0.7, t0=0.02, max_dist=0.7,
+                   alpha_thresh=0.99)
+    out, info = va.trace_aniso(va.build_aniso_mips(base), pr, nr, cam, p, return_info=True)
+    gout = rng.normal(size=out.shape)
+    gout[info["ambiguous"]] = 0.0
+    grad = va.trace_backward_aniso(va.build_aniso_mips(base), pr, nr, cam, p, gout)
+
+    def loss(b):
+        return np.sum(gout * va.trace_aniso(va.build_aniso_mips(b), pr, nr, cam, p))
+
+    idx = [tuple(int(v) for v in rng.integers(0, n, size=3)) + (int(rng.integers(0, 4)),) for _ in range(10)]
+    big = np.unravel_index(np.argsort(-np.abs(grad).ravel())[:10], grad.shape)
+    idx += list(zip(*[a.tolist() for a in big]))
+    h = 1e-6
+    for i in idx:
+        bp, bm = base.copy(), base.copy()
+        bp[i] += h
+        bm[i] -= h
+        fd = (loss(bp) - loss(bm)) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, grad[i])
+    assert np.abs(grad).max() > 1e-2
