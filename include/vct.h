@@ -67,8 +67,7 @@ typedef struct {
     float origin[3];   /* world position of the grid's minimum corner */
     float extent;      /* side length of the grid cube, world units, finite and > 0 */
     int32_t anisotropic; /* 0: one pyramid of 2x2x2 means; 1: six directional pyramids sharing level 0
-                            (see vct_build_mips); the training entry points (vct_trace_save and the
-                            backward ones) return VCT_EUNSUPPORTED for 1, the others accept it */
+                            (see vct_build_mips); every entry point accepts both */
 } vct_grid;
 
 /* Deferred-shading G-buffer: one cone origin per pixel (Section 5.1.3 adopts
@@ -216,7 +215,13 @@ int vct_backward_workspace_bytes(const vct_grid* grid, const vct_gbuffer* gbuf,
  * sums: bitwise identical results on every run); then carried through the mip
  * reduction (each child receives 1/8 of its parent's gradient).  For float16 or
  * bfloat16 pyramids the sampled values are the stored ones and the rounding is
- * treated as the identity.
+ * treated as the identity.  Anisotropic pyramids: a sample above level 0 sends
+ * its gradient to the three directions it read, weighted by w_a^2, and each
+ * direction's level gradients reach the level below through the transpose of
+ * the linearised front-to-back composite of the two children (front child
+ * (G - e_alpha (G . b)) / 4, back child (1 - f.alpha) G / 4, with f, b the
+ * stored texels), computed in float32 from the top level down with one writer
+ * per texel, so the result is still the same on every run.
  *   grad_out   device float32 [b][h][w][8] = dL/d(out of vct_trace)
  *   grad_base  device float32 [N][N][N][4], overwritten (not accumulated)
  *   workspace  device buffer of at least vct_backward_workspace_bytes bytes */

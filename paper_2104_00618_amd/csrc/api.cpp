@@ -60,14 +60,6 @@ int check_grid(const char* fn, const vct_grid* g) {
     return VCT_OK;
 }
 
-// Entry points whose kernels sample isotropic pyramids only.
-int check_isotropic(const char* fn, const vct_grid* g) {
-    if (g->anisotropic)
-        return fail(VCT_EUNSUPPORTED, fn, "anisotropic pyramids have no adjoint in this build (vct_build_mips, "
-                    "vct_unpack_level(_dir), vct_trace, vct_count_samples, vct_shade and vct_bounce accept them)");
-    return VCT_OK;
-}
-
 int check_gbuffer(const char* fn, const vct_gbuffer* gb) {
     if (!gb) return fail(VCT_EINVAL, fn, "gbuffer is null");
     if (gb->b < 0 || gb->h < 0 || gb->w < 0)
@@ -368,7 +360,6 @@ int vct_backward_workspace_bytes(const vct_grid* grid, const vct_gbuffer* gbuf, 
                                  size_t* bytes) {
     const char* fn = "vct_backward_workspace_bytes";
     if (int r = check_grid(fn, grid)) return r;
-    if (int r = check_isotropic(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
     if (int r = check_params(fn, grid, params)) return r;
     if (!bytes) return fail(VCT_EINVAL, fn, "bytes is null");
@@ -397,7 +388,6 @@ int vct_trace_save(const vct_grid* grid, const void* pyramid, const vct_gbuffer*
     const char* fn = "vct_trace_save";
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
-    if (int r = check_isotropic(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
     if (int r = check_params(fn, grid, params)) return r;
     long long np = (long long)gbuf->b * gbuf->h * gbuf->w;
@@ -420,7 +410,6 @@ static int backward_common(const char* fn, const vct_grid* grid, const void* pyr
                            size_t workspace_bytes, hipStream_t stream) {
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
-    if (int r = check_isotropic(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
     if (int r = check_params(fn, grid, params)) return r;
     if (!(params->alpha_thresh <= 1.0f))

@@ -35,18 +35,21 @@ using namespace vct;
 
 constexpr int kThreads = 256;
 
-template <int DT>
+template <int DT, bool ANISO>
 __global__ __launch_bounds__(kThreads) void k_bwd_pass1(TraceArgs a, const float4* __restrict__ gout,
                                                         LaneState* __restrict__ state, float* __restrict__ part) {
     __shared__ LevelTable T;
+    __shared__ DirSlot<ANISO> D;
     __shared__ float s_part[kThreads / 64];
     load_level_table(a, &T);
+    load_dir_table(a, &D);
     __syncthreads();
     const int tile = xcd_tile(blockIdx.x, a.n_tiles);
     int view, y, x;
     tile_pixel(a, tile, threadIdx.x, view, y, x);
     float bound = 0.f;
-    if (x < a.w && y < a.h) bound = pass1_pixel<DT>(a, T, gout, state, view, ((size_t)view * a.h + y) * a.w + x);
+    if (x < a.w && y < a.h)
+        bound = pass1_pixel<DT, ANISO>(a, T, gout, state, view, ((size_t)view * a.h + y) * a.w + x, dir_ptr(D));
     // fixed-order workgroup sum
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int o = 32; o > 0; o >>= 1) bound += __shfl_xor(bound, o, 64);
@@ -57,11 +60,13 @@ __global__ __launch_bounds__(kThreads) void k_bwd_pass1(TraceArgs a, const float
 
 // Forward that also saves every cone's end state (training path: the
 // backward then skips pass 1).
-template <int DT>
+template <int DT, bool ANISO>
 __global__ __launch_bounds__(kThreads) void k_trace_save(TraceArgs a, float4* __restrict__ out,
                                                          LaneState* __restrict__ state) {
     __shared__ LevelTable T;
+    __shared__ DirSlot<ANISO> D;
     load_level_table(a, &T);
+    load_dir_table(a, &D);
     __syncthreads();
     const int tile = xcd_tile(blockIdx.x, a.n_tiles);
     int view, y, x;
@@ -69,7 +74,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_save(TraceArgs a, float4* __
     if (!(x < a.w && y < a.h)) return;
     const size_t pix = ((size_t)view * a.h + y) * a.w + x;
     float4 o0, o1;
-    trace_save_pixel<DT>(a, T, view, pix, state, o0, o1);
+    trace_save_pixel<DT, ANISO>(a, T, view, pix, state, o0, o1, dir_ptr(D));
     out[2 * pix] = o0;
     out[2 * pix + 1] = o1;
 }
@@ -232,7 +237,7 @@ __device__ __forceinline__ void emit_weights(const LevelGeom& g, float wl, const
 // table for the coarse levels (side <= 8), to the global accumulator otherwise.
 template <bool ALPHA_ONLY>
 __device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, float wl, const float gs[4],
-                                           const EmitLane& e, int E, unsigned long long* __restrict__ acc,
+                                           const EmitLane& e, int E, int lev_shift, unsigned long long* __restrict__ acc,
                                            unsigned long long* small, uint32_t small_off, int lane) {
     float wp[8];
     emit_weights(geo, wl, e, wp);
@@ -264,7 +269,7 @@ __device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, floa
         const uint32_t dy = (uint32_t)__builtin_amdgcn_readlane((int)geo.dy, leader);
         const uint32_t dz = (uint32_t)__builtin_amdgcn_readlane((int)geo.dz, leader);
         const uint32_t idx = k + (dx & e.xm) + (dy & e.ym) + (dz & e.zm);
-        const long long qv = emitter ? fixed_point(sum, E - 3 * lev) : 0;
+        const long long qv = emitter ? fixed_point(sum, E - lev_shift * lev) : 0;
         VCT_CHECK_ACC(idx);
         if (qv != 0 && idx >= small_off) atomicAdd(&small[(idx - small_off) * 4 + ch], (unsigned long long)qv);
         if (qv != 0 && idx < small_off) atomicAdd(&acc[(size_t)idx * 4 + ch], (unsigned long long)qv);
@@ -272,17 +277,52 @@ __device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, floa
     }
 }
 
-constexpr int kSmallMax = 704;   // texels of all levels with side <= 8 (8^3 + 3 bricks of 64)
+// One level's emission.  Isotropic pyramids: level l's integers carry the
+// scale 2^(E - 3l) (the 1/8 per level of the mip adjoint folded in).
+// Anisotropic pyramids: scale 2^E at every level (their mip adjoint is not a
+// fixed factor); above level 0 the sample read the three directions of its
+// axis signs with weights w_a^2, so each gets the gradient with that weight at
+// its direction's offset (a separate group key, since the base index moves).
+template <bool ALPHA_ONLY, bool ANISO>
+__device__ __forceinline__ void emit_dirs(const TraceArgs& a, const DirTable* D, const Cone& c, bool live,
+                                          const LevelGeom& geo, float wl, const float gs[4], const EmitLane& e, int E,
+                                          unsigned long long* __restrict__ acc, unsigned long long* small,
+                                          uint32_t small_off, int lane) {
+    if constexpr (!ANISO) {
+        emit_level<ALPHA_ONLY>(live, geo, wl, gs, e, E, 3, acc, small, small_off, lane);
+    } else {
+        const bool base_level = live && geo.level == 0;
+        emit_level<ALPHA_ONLY>(base_level, geo, wl, gs, e, E, 0, acc, small, small_off, lane);
+        const float W[3] = {c.Wx, c.Wy, c.Wz};
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const float wt = W[ax] * W[ax] * a.inv_scale2;
+            const bool on = live && !base_level && wt != 0.0f;
+            LevelGeom gd = geo;
+            gd.base += on ? D->delta[2 * ax + (W[ax] < 0.0f ? 1 : 0)][geo.level] : 0u;
+            // every lane's weights enter the butterfly (times a zero gradient
+            // outside the group), so they must be finite: a lane of a pixel
+            // with no surface has no cone, and its W is whatever the
+            // registers held
+            emit_level<ALPHA_ONLY>(on, gd, on ? wl * wt : 0.0f, gs, e, E, 0, acc, small, small_off, lane);
+        }
+    }
+}
 
-template <int DT>
+constexpr int kSmallMax = 704;        // texels of all levels with side <= 8 (8^3 + 3 bricks of 64)
+constexpr int kSmallMaxAniso = 1152;  // anisotropic: levels with side <= 4 of six directions (6 x 3 bricks)
+
+template <int DT, bool ANISO>
 __global__ __launch_bounds__(kThreads, 4) void k_bwd_pass2(TraceArgs a, const float4* __restrict__ gout,
                                                         const LaneState* __restrict__ state,
                                                         const int* __restrict__ ctl,
                                                         unsigned long long* __restrict__ acc, uint32_t small_off,
                                                         int small_n) {
     __shared__ LevelTable T;
-    __shared__ unsigned long long s_small[kSmallMax * 4];
+    __shared__ DirSlot<ANISO> D;
+    __shared__ unsigned long long s_small[(ANISO ? kSmallMaxAniso : kSmallMax) * 4];
     load_level_table(a, &T);
+    load_dir_table(a, &D);
     for (int i = threadIdx.x; i < small_n * 4; i += kThreads) s_small[i] = 0ull;
     __syncthreads();
     const int E = ctl[0];
@@ -317,17 +357,22 @@ __global__ __launch_bounds__(kThreads, 4) void k_bwd_pass2(TraceArgs a, const fl
             st.f = 0.f;
             st.g0.wx = st.g0.wy = st.g0.wz = 0.f;
             st.g1.wx = st.g1.wy = st.g1.wz = 0.f;
-            if (live) pass2_step<DT>(a, T, L, k, st);
+            if constexpr (ANISO) st.g0.level = st.g1.level = 0;   // (a dead lane's direction-table row)
+            if (live) pass2_step<DT, ANISO>(a, T, L, k, st, dir_ptr(D));
             if (occ) {
-                emit_level<true>(live, st.g0, 1.0f - st.f, st.g, e, E, acc, s_small, small_off, lane);
-                emit_level<true>(live && st.f > 0.0f, st.g1, st.f, st.g, e, E, acc, s_small, small_off, lane);
+                emit_dirs<true, ANISO>(a, dir_ptr(D), L.c, live, st.g0, 1.0f - st.f, st.g, e, E, acc, s_small,
+                                       small_off, lane);
+                emit_dirs<true, ANISO>(a, dir_ptr(D), L.c, live && st.f > 0.0f, st.g1, st.f, st.g, e, E, acc, s_small,
+                                       small_off, lane);
             } else {
                 // gradient in the lane's slot order (channel bit 1 flipped where cf);
                 // selects on values: an index select would move st to scratch memory
                 const float g0 = st.g[0], g1 = st.g[1], g2 = st.g[2], g3 = st.g[3];
                 const float gs[4] = {e.cf ? g2 : g0, e.cf ? g3 : g1, e.cf ? g0 : g2, e.cf ? g1 : g3};
-                emit_level<false>(live, st.g0, 1.0f - st.f, gs, e, E, acc, s_small, small_off, lane);
-                emit_level<false>(live && st.f > 0.0f, st.g1, st.f, gs, e, E, acc, s_small, small_off, lane);
+                emit_dirs<false, ANISO>(a, dir_ptr(D), L.c, live, st.g0, 1.0f - st.f, gs, e, E, acc, s_small,
+                                        small_off, lane);
+                emit_dirs<false, ANISO>(a, dir_ptr(D), L.c, live && st.f > 0.0f, st.g1, st.f, gs, e, E, acc,
+                                        s_small, small_off, lane);
             }
         }
     }
@@ -383,7 +428,92 @@ __global__ __launch_bounds__(256) void k_mip_adjoint(AdjArgs m, const long long*
     }
 }
 
+// Mip adjoint of anisotropic pyramids, one launch per level from the top
+// down.  The gradient of a directional texel is its own accumulated sum plus
+// what its parent (same direction, one level up) passes through the
+// linearised front-to-back composite: parent = (1/4) sum over the four child
+// pairs along the direction's axis of over(f, b) = f + (1 - f.a) b, so the
+// front child gets (G - e_a (G . b)) / 4 and the back child (1 - f.a) G / 4,
+// with f, b the stored texels of the pair.  Levels >= 1 keep their float32
+// gradient in the first 16 bytes of their own accumulator slot (one writer
+// per slot, parents final before their children run); level 0 sums the six
+// directions' contributions in order and writes the base gradient.
+struct AnisoAdj {
+    int32_t n, levels, level;          // level processed (its parents are level + 1)
+    int32_t nb[VCT_MAX_LEVELS];
+    uint32_t doff[6][VCT_MAX_LEVELS];
+};
+
+__device__ __forceinline__ float4 scaled(const long long* p, int E) {
+    const longlong2 u = reinterpret_cast<const longlong2*>(p)[0];
+    const longlong2 v = reinterpret_cast<const longlong2*>(p)[1];
+    return make_float4(ldexpf((float)u.x, -E), ldexpf((float)u.y, -E), ldexpf((float)v.x, -E),
+                       ldexpf((float)v.y, -E));
+}
+
 template <int DT>
+__device__ __forceinline__ float4 from_parent(const AnisoAdj& m, const void* pyr, const long long* acc, int d, int x,
+                                              int y, int z) {
+    const int c = m.level, nbp = m.nb[c + 1];
+    const float4 G = *reinterpret_cast<const float4*>(
+        acc + (size_t)(m.doff[d][c + 1] + vct_brick_index(x >> 1, y >> 1, z >> 1, nbp)) * 4);
+    const int axis = d >> 1;
+    const int coord = axis == 0 ? x : (axis == 1 ? y : z);
+    const bool front = ((coord & 1) == 0) == ((d & 1) == 0);
+    const int px = axis == 0 ? x ^ 1 : x, py = axis == 1 ? y ^ 1 : y, pz = axis == 2 ? z ^ 1 : z;
+    const float4 q = vct_load_texel<DT & ~VCT_WIDE>(pyr, m.doff[d][c] + vct_brick_index(px, py, pz, m.nb[c]));
+    if (front) {
+        const float gb = G.x * q.x + G.y * q.y + G.z * q.z + G.w * q.w;
+        return make_float4(0.25f * G.x, 0.25f * G.y, 0.25f * G.z, 0.25f * (G.w - gb));
+    }
+    const float t = 0.25f * (1.0f - q.w);
+    return make_float4(t * G.x, t * G.y, t * G.z, t * G.w);
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_aniso_adjoint(AnisoAdj m, long long* __restrict__ acc, const void* pyr,
+                                                       const int* __restrict__ ctl, float4* __restrict__ grad) {
+    const int E = ctl[0];
+    const bool bad = ctl[1] != 0;
+    const int c = m.level, side = m.n >> c, nb = m.nb[c];
+    const bool top = c == m.levels - 1;
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t brick = t >> 6, w = t & 63u;
+    if (brick >= (uint32_t)nb * nb * nb) return;
+    const int x = (int)(brick % nb) * 4 + (int)(w & 3u), y = (int)((brick / nb) % nb) * 4 + (int)((w >> 2) & 3u),
+              z = (int)(brick / ((uint32_t)nb * nb)) * 4 + (int)(w >> 4);
+    if (x >= side || y >= side || z >= side) return;
+    const uint32_t at = vct_brick_index(x, y, z, nb);
+    if (c == 0) {
+        float4 g = scaled(acc + (size_t)at * 4, E);
+        if (!top)
+            for (int d = 0; d < 6; ++d) {
+                const float4 p = from_parent<DT>(m, pyr, acc, d, x, y, z);
+                g.x += p.x;
+                g.y += p.y;
+                g.z += p.z;
+                g.w += p.w;
+            }
+        if (bad) g = make_float4(__int_as_float(0x7fc00000), __int_as_float(0x7fc00000), __int_as_float(0x7fc00000),
+                                 __int_as_float(0x7fc00000));
+        grad[((size_t)z * m.n + y) * m.n + x] = g;
+        return;
+    }
+    for (int d = 0; d < 6; ++d) {
+        long long* slot = acc + (size_t)(m.doff[d][c] + at) * 4;
+        float4 g = scaled(slot, E);
+        if (!top) {
+            const float4 p = from_parent<DT>(m, pyr, acc, d, x, y, z);
+            g.x += p.x;
+            g.y += p.y;
+            g.z += p.z;
+            g.w += p.w;
+        }
+        *reinterpret_cast<float4*>(slot) = g;
+    }
+}
+
+template <int DT, bool ANISO>
 hipError_t run_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPlan& P, const float* grad_out,
                         float* grad_base, void* ws, const void* saved, hipStream_t s, EventSink& es) {
     char* w = static_cast<char*>(ws);
@@ -403,24 +533,44 @@ hipError_t run_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPl
         if (saved)
             hipLaunchKernelGGL(k_bwd_bound, dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, part);
         else
-            hipLaunchKernelGGL(k_bwd_pass1<DT>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, part);
+            hipLaunchKernelGGL((k_bwd_pass1<DT, ANISO>), dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, part);
     }
     es.mark(s);
     hipLaunchKernelGGL(k_bwd_scale, dim3(1), dim3(kThreads), 0, s, part, (int)P.n_blocks, ctl);
-    // coarse levels (side <= 8) accumulate per workgroup in LDS first
+    // coarse levels accumulate per workgroup in LDS first: side <= 8, or for
+    // anisotropic pyramids the levels 1.. with side <= 4 of all six directions
+    // (stored together at the end of the pyramid)
     int ls = L.levels;
-    for (int l = 0; l < L.levels; ++l)
-        if ((L.n >> l) <= 8) {
+    for (int l = ANISO ? 1 : 0; l < L.levels; ++l)
+        if ((L.n >> l) <= (ANISO ? VCT_ANISO_SMALL_SIDE : 8)) {
             ls = l;
             break;
         }
-    const uint32_t small_off = (uint32_t)(ls < L.levels ? L.off[ls] : L.total_texels);
+    const uint32_t small_off = (uint32_t)(ls < L.levels ? L.doff[0][ls] : L.total_texels);
     const int small_n = (int)(L.total_texels - small_off);
-    if (small_n > kSmallMax) return hipErrorInvalidValue;
+    if (small_n > (ANISO ? kSmallMaxAniso : kSmallMax)) return hipErrorInvalidValue;
     es.mark(s);
     if (a.n_tiles > 0) {
-        hipLaunchKernelGGL(k_bwd_pass2<DT>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, ctl, acc, small_off,
-                           small_n);
+        hipLaunchKernelGGL((k_bwd_pass2<DT, ANISO>), dim3(a.n_tiles), dim3(kThreads), 0, s, a, g4, state, ctl, acc,
+                           small_off, small_n);
+    }
+    if constexpr (ANISO) {
+        AnisoAdj m{};
+        m.n = L.n;
+        m.levels = L.levels;
+        for (int l = 0; l < L.levels; ++l) {
+            m.nb[l] = L.nb[l];
+            for (int d = 0; d < 6; ++d) m.doff[d][l] = (uint32_t)L.doff[d][l];
+        }
+        es.mark(s);
+        for (int c = L.levels - 1; c >= 0; --c) {
+            m.level = c;
+            const uint32_t threads = (uint32_t)L.nb[c] * L.nb[c] * L.nb[c] * 64u;
+            hipLaunchKernelGGL(k_aniso_adjoint<DT>, dim3((threads + 255u) / 256u), dim3(256), 0, s, m,
+                               reinterpret_cast<long long*>(acc), a.pyr, ctl, reinterpret_cast<float4*>(grad_base));
+        }
+        es.mark(s);
+        return hipGetLastError();
     }
     AdjArgs m{};
     m.n = L.n;
@@ -471,7 +621,9 @@ int64_t vct_lane_state_bytes(int64_t n_lanes) { return align256(n_lanes * (int64
 hipError_t vct_launch_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPlan& P, const float* grad_out,
                                float* grad_base, void* ws, const void* saved, hipStream_t s, EventSink& es) {
     return vct_dispatch_dt(L.dtype, a.wide != 0, [&](auto dt) {
-        return run_backward<decltype(dt)::value>(L, a, P, grad_out, grad_base, ws, saved, s, es);
+        constexpr int DT = decltype(dt)::value;
+        return a.aniso ? run_backward<DT, true>(L, a, P, grad_out, grad_base, ws, saved, s, es)
+                       : run_backward<DT, false>(L, a, P, grad_out, grad_base, ws, saved, s, es);
     });
 }
 
@@ -482,7 +634,11 @@ hipError_t vct_launch_trace_save(const TraceArgs& a, int dtype, float* out, void
         float4* o = reinterpret_cast<float4*>(out);
         LaneState* st = reinterpret_cast<LaneState*>(state);
         vct_dispatch_dt(dtype, a.wide != 0, [&](auto dt) {
-            hipLaunchKernelGGL(k_trace_save<decltype(dt)::value>, dim3(a.n_tiles), dim3(kThreads), 0, s, a, o, st);
+            constexpr int DT = decltype(dt)::value;
+            if (a.aniso)
+                hipLaunchKernelGGL((k_trace_save<DT, true>), dim3(a.n_tiles), dim3(kThreads), 0, s, a, o, st);
+            else
+                hipLaunchKernelGGL((k_trace_save<DT, false>), dim3(a.n_tiles), dim3(kThreads), 0, s, a, o, st);
             return hipSuccess;
         });
     }

@@ -81,8 +81,9 @@ struct Pass1Out {
 
 // Recompute one cone (same A recurrence as the forward, so the same K),
 // with C as a double-float and the sums needed for the contribution bound.
-template <int DT>
-__device__ __forceinline__ Pass1Out pass1_march(const TraceArgs& a, const LevelTable& T, const Cone& c) {
+template <int DT, bool ANISO = false>
+__device__ __forceinline__ Pass1Out pass1_march(const TraceArgs& a, const LevelTable& T, const Cone& c,
+                                                const DirTable* D = nullptr) {
     Pass1Out r;
     for (int i = 0; i < 3; ++i) r.C[i] = {0.f, 0.f};
     r.A = 0.f;
@@ -96,7 +97,7 @@ __device__ __forceinline__ Pass1Out pass1_march(const TraceArgs& a, const LevelT
         if (!t_within(t, c.tmax) || !(r.A < a.alpha_thresh)) break;
         float d = fmaxf(c.two_tan * t.hi, a.voxel);
         float lam = lod_of(a, d);
-        float4 s = sample_at<DT>(a, T, c, t, lam);
+        float4 s = sample_at<DT, ANISO>(a, T, c, t, lam, D);
         float tr = 1.0f - r.A;
         // |T_{k-1}| / |T_k| for every sample k that follows another (T_k >= 2^-24 here)
         if (k > 0) r.SQ += fabsf(r.Tlast) / fabsf(tr);
@@ -147,9 +148,10 @@ __device__ __forceinline__ float lane_bound(const TraceArgs& a, int slot, const 
 
 // Pass 1 for one pixel: stores the lane states of its cones and returns the
 // bound on sum_k |dL/dc_k|_1 + |dL/da_k| over them.
-template <int DT>
+template <int DT, bool ANISO = false>
 __device__ __forceinline__ float pass1_pixel(const TraceArgs& a, const LevelTable& T, const float4* __restrict__ gout,
-                                             LaneState* __restrict__ state, int view, size_t pix) {
+                                             LaneState* __restrict__ state, int view, size_t pix,
+                                             const DirTable* D = nullptr) {
     const int nslots = a.n_diffuse + 2;
     const size_t np = n_pixels(a);
     float4 nr = a.normal[pix];
@@ -166,7 +168,7 @@ __device__ __forceinline__ float pass1_pixel(const TraceArgs& a, const LevelTabl
         LaneState out = zero_lane_state();
         if (slot_enabled(a, slot)) {
             Cone c = cone_for_slot(a, P, slot, cam);
-            out = lane_state(pass1_march<DT>(a, T, c));
+            out = lane_state(pass1_march<DT, ANISO>(a, T, c, D));
             bound += lane_bound(a, slot, out, g0, g1);
         }
         lane_put(state, np, pix, slot, out);
@@ -188,9 +190,10 @@ __device__ __forceinline__ float saved_bound_pixel(const TraceArgs& a, const flo
 
 // Forward for one pixel that also saves its cones' end states (for the
 // backward): the same march as pass 1, with the epilogue of trace_pixel.
-template <int DT>
+template <int DT, bool ANISO = false>
 __device__ __forceinline__ void trace_save_pixel(const TraceArgs& a, const LevelTable& T, int view, size_t pix,
-                                                 LaneState* __restrict__ state, float4& o0, float4& o1) {
+                                                 LaneState* __restrict__ state, float4& o0, float4& o1,
+                                                 const DirTable* D = nullptr) {
     o0 = make_float4(0.f, 0.f, 0.f, 0.f);
     o1 = o0;
     const int nslots = a.n_diffuse + 2;
@@ -206,7 +209,7 @@ __device__ __forceinline__ void trace_save_pixel(const TraceArgs& a, const Level
         LaneState out = zero_lane_state();
         if (slot_enabled(a, slot)) {
             Cone c = cone_for_slot(a, P, slot, cam);
-            Pass1Out r = pass1_march<DT>(a, T, c);
+            Pass1Out r = pass1_march<DT, ANISO>(a, T, c, D);
             out = lane_state(r);
             const float cr = r.C[0].hi + r.C[0].lo, cg = r.C[1].hi + r.C[1].lo, cb = r.C[2].hi + r.C[2].lo;
             if (slot < a.n_diffuse) {
@@ -308,6 +311,30 @@ __device__ __forceinline__ float4 gather_geom(const vct_v4i& rsrc, const LevelGe
     return s;
 }
 
+// Anisotropic pyramids: the level's sample as level_sample<.., true> forms it
+// (level 0 plain; above, the axes with w_a^2 > 0 in order, each gathered at
+// its direction's offset and added with an FMA), from the factored taps.
+template <int DT>
+__device__ __forceinline__ float4 gather_geom_aniso(const TraceArgs& a, const DirTable* D, const Cone& c,
+                                                    const LevelGeom& g) {
+    if (g.level == 0) return gather_geom<DT>(a.rsrc, g);
+    const float W[3] = {c.Wx, c.Wy, c.Wz};
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const float wt = W[ax] * W[ax] * a.inv_scale2;
+        if (wt == 0.0f) continue;
+        LevelGeom gd = g;
+        gd.base += D->delta[2 * ax + (W[ax] < 0.0f ? 1 : 0)][g.level];
+        const float4 v = gather_geom<DT>(a.rsrc, gd);
+        s.x = __builtin_fmaf(wt, v.x, s.x);
+        s.y = __builtin_fmaf(wt, v.y, s.y);
+        s.z = __builtin_fmaf(wt, v.z, s.z);
+        s.w = __builtin_fmaf(wt, v.w, s.w);
+    }
+    return s;
+}
+
 // Sample k of a pass-2 cone: its taps on one or two levels and the gradient
 // g = (dL/dc_k, dL/da_k) of the sample; advances the march.
 struct Pass2Step {
@@ -316,9 +343,9 @@ struct Pass2Step {
     float g[4];
 };
 
-template <int DT>
+template <int DT, bool ANISO = false>
 __device__ __forceinline__ void pass2_step(const TraceArgs& a, const LevelTable& T, Pass2Lane& L, int k,
-                                           Pass2Step& st) {
+                                           Pass2Step& st, const DirTable* D = nullptr) {
     const float d = fmaxf(L.c.two_tan * L.t.hi, a.voxel);
     const float lam = lod_of(a, d);
     const df Ux = df_axis(L.c.Ox, L.t, L.c.Wx);
@@ -327,10 +354,10 @@ __device__ __forceinline__ void pass2_step(const TraceArgs& a, const LevelTable&
     const int l0 = (int)lam;
     st.f = lam - (float)l0;
     st.g0 = level_geom(T, l0, Ux, Uy, Uz);
-    float4 s = gather_geom<DT>(a.rsrc, st.g0);
+    float4 s = ANISO ? gather_geom_aniso<DT>(a, D, L.c, st.g0) : gather_geom<DT>(a.rsrc, st.g0);
     if (st.f > 0.0f) {
         st.g1 = level_geom(T, min(l0 + 1, a.levels - 1), Ux, Uy, Uz);
-        float4 s1 = gather_geom<DT>(a.rsrc, st.g1);
+        float4 s1 = ANISO ? gather_geom_aniso<DT>(a, D, L.c, st.g1) : gather_geom<DT>(a.rsrc, st.g1);
         float gg = 1.0f - st.f;
         s.x = __builtin_fmaf(st.f, s1.x, gg * s.x);
         s.y = __builtin_fmaf(st.f, s1.y, gg * s.y);

@@ -22,9 +22,12 @@
 // one, and a brick of float16 texels is 512 contiguous bytes.
 // After the last level comes a float32 staging area of two buffers of
 // (N/16)^3 texels used by the multi-pass mip build.
-// An anisotropic pyramid stores level 0 once, then levels 1..L-1 of each of
-// the six directions (+x, -x, +y, -y, +z, -z) in turn; off[] then describes
+// An anisotropic pyramid stores level 0 once, then the levels 1.. with more
+// than 4 texels a side of each of the six directions (+x, -x, +y, -y, +z, -z)
+// in turn, then the levels with at most 4 of each direction in turn (so the
+// adjoint can keep all coarse levels in one LDS table); off[] then describes
 // the +x pyramid and doff[d][] every direction (doff[d][0] = 0).
+#define VCT_ANISO_SMALL_SIDE 4
 // ---------------------------------------------------------------------------
 struct PyrLayout {
     int32_t n, levels, dtype, texel_bytes, aniso;
@@ -57,11 +60,21 @@ static inline PyrLayout vct_make_layout(int n, int levels, int dtype, int aniso 
         int nb = (nl + VCT_BRICK - 1) / VCT_BRICK;
         p.nb[l] = nb;
     }
-    for (int d = 0; d < (p.aniso ? 6 : 1); ++d)
-        for (int l = (d == 0 ? 0 : 1); l < levels; ++l) {
-            p.doff[d][l] = off;
+    if (!p.aniso) {
+        for (int l = 0; l < levels; ++l) {
+            p.doff[0][l] = off;
             off += (int64_t)p.nb[l] * p.nb[l] * p.nb[l] * VCT_BRICK_TEXELS;
         }
+    } else {
+        off += (int64_t)p.nb[0] * p.nb[0] * p.nb[0] * VCT_BRICK_TEXELS;   // level 0, shared
+        for (int pass = 0; pass < 2; ++pass)                              // large levels, then small ones
+            for (int d = 0; d < 6; ++d)
+                for (int l = 1; l < levels; ++l)
+                    if (((n >> l) <= VCT_ANISO_SMALL_SIDE) == (pass == 1)) {
+                        p.doff[d][l] = off;
+                        off += (int64_t)p.nb[l] * p.nb[l] * p.nb[l] * VCT_BRICK_TEXELS;
+                    }
+    }
     for (int d = 0; d < 6; ++d)
         for (int l = 0; l < levels; ++l) {
             if (!p.aniso) p.doff[d][l] = p.doff[0][l];

@@ -417,15 +417,14 @@ def test_bounce_validation_and_workspace_size():
     assert rc == EINVAL and "power of two" in lib.vct_last_error().decode()
 
 
-def test_anisotropic_grid_size_validation_and_unsupported_paths():
+def test_anisotropic_grid_size_and_validation():
     lib = vct.lib()
-    EUNSUPPORTED = -4
     iso, ani = vct.Grid(64).c(), vct.Grid(64, anisotropic=True).c()
     bi, ba = ctypes.c_size_t(), ctypes.c_size_t()
     assert lib.vct_pyramid_bytes(ctypes.byref(iso), ctypes.byref(bi)) == 0
     assert lib.vct_pyramid_bytes(ctypes.byref(ani), ctypes.byref(ba)) == 0
-    above0 = sum(max(64 >> l, 4) ** 3 for l in range(1, 7)) * 16      # bricks round small levels up to 4^3
-    assert ba.value - bi.value == 5 * above0                              # five more copies of levels 1..L-1
+    above0 = sum(max(64 >> l, 4) ** 3 for l in range(1, 7))               # bricks round small levels up to 4^3
+    assert ba.value - bi.value == 5 * above0 * 16                          # five more copies of levels 1..L-1
     bad = vct.Grid(16).c()
     bad.anisotropic = 2
     assert lib.vct_pyramid_bytes(ctypes.byref(bad), ctypes.byref(bi)) == EINVAL
@@ -433,15 +432,12 @@ def test_anisotropic_grid_size_validation_and_unsupported_paths():
     fake = ctypes.c_void_p(0x1000)
     p = B.cone_params(_params(alpha_thresh=0.99))
     gb = _empty_gbuf()
-    n = ctypes.c_size_t()
-    assert lib.vct_backward_workspace_bytes(ctypes.byref(ani), ctypes.byref(gb), ctypes.byref(p),
-                                            ctypes.byref(n)) == EUNSUPPORTED
-    assert lib.vct_trace_save(ctypes.byref(ani), fake, ctypes.byref(gb), ctypes.byref(p), fake, fake, 1 << 20,
-                              None) == EUNSUPPORTED
-    assert lib.vct_trace_backward(ctypes.byref(ani), fake, ctypes.byref(gb), ctypes.byref(p), fake, fake, fake,
-                                  1 << 30, None) == EUNSUPPORTED
-    assert "anisotropic" in lib.vct_last_error().decode()
-    # the forward paths accept it (nothing to do for an empty G-buffer)
+    # every entry point takes it; the backward's accumulator covers the directional levels (32 B per texel)
+    n, ni = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.vct_backward_workspace_bytes(ctypes.byref(ani), ctypes.byref(gb), ctypes.byref(p), ctypes.byref(n)) == 0
+    assert lib.vct_backward_workspace_bytes(ctypes.byref(iso), ctypes.byref(gb), ctypes.byref(p),
+                                            ctypes.byref(ni)) == 0
+    assert n.value - ni.value == 5 * above0 * 32
     assert lib.vct_trace(ctypes.byref(ani), fake, ctypes.byref(gb), ctypes.byref(p), None, None) == 0
     s = _shade_params()
     assert lib.vct_shade(ctypes.byref(ani), fake, ctypes.byref(gb), fake, ctypes.byref(p), ctypes.byref(s), fake,

@@ -162,3 +162,67 @@ def test_aniso_bounce_matches_oracle():
     check(inc_g, inc_r, keep.reshape(-1), TOL, "aniso bounce 32^3 (added light)")
     same = (ref[..., 0:3] == base[..., 0:3]).all(-1) & keep
     assert np.array_equal(got[same].view(np.uint32), base[same].view(np.uint32))
+
+
+def _aniso_grads(base, n, pr, nr, cam, p, gout, dtype="f32", repeats=6):
+    pyr, g = gpu_aniso(base, n, dtype=dtype)
+    t = [dev(x) for x in (pr, nr, cam)]
+    go = dev(gout.astype(np.float32))
+    rec = vct.trace_backward(pyr, g, *t, p, go).cpu().numpy()
+    out, state = vct.trace_save(pyr, g, *t, p)
+    sav = vct.trace_backward_saved(pyr, g, *t, p, state, go).cpu().numpy()
+    # repeated calls: lanes of pixels with no surface hold no cone, and a
+    # non-finite weight of one of them once poisoned a group's sum now and then
+    again = [vct.trace_backward_saved(pyr, g, *t, p, state, go).cpu().numpy() for _ in range(repeats)]
+    return rec, sav, again, out.cpu().numpy(), pyr, g
+
+
+def _check_grad(got, ref, label, tmax=1e-4, trms=1e-5):
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max() / scale
+    rms = np.sqrt(np.mean((got - ref) ** 2)) / scale
+    print(f"{label}: gradient max {err:.2e} rms {rms:.2e}", flush=True)
+    assert err <= tmax and rms <= trms, label
+
+
+@pytest.mark.parametrize("case", ["random", "cornell"])
+def test_aniso_backward_matches_oracle(case):
+    if case == "random":
+        n = 16
+        base = random_grid(n, seed=61, alpha_max=0.35)
+        pr, nr, cam = random_gbuffer(2, 17, 19, seed=62, n=n)
+        d, w = cone_set("six")
+        p = ConeParams(d, w, alpha_thresh=0.99, light_pos=(0.4, 0.8, 0.6))
+    else:
+        wk = workload("c3fd")
+        n, base, pr, nr, cam, p = wk.n, wk.base, wk.pos_rough, wk.normal, wk.cam_pos, wk.params
+    am = va.build_aniso_mips(base)
+    fwd, info = va.trace_aniso(am, pr, nr, cam, p, return_info=True)
+    gout = np.random.default_rng(63).normal(size=fwd.shape)
+    gout[info["ambiguous"]] = 0.0
+    rec, sav, again, out, _, _ = _aniso_grads(base, n, pr, nr, cam, p, gout)
+    check(out, fwd, ~info["ambiguous"].reshape(-1), TOL, f"aniso trace_save {case}")
+    assert np.array_equal(rec.view(np.uint32), sav.view(np.uint32)), "saved path differs from the recompute path"
+    for r in again:
+        assert np.array_equal(sav.view(np.uint32), r.view(np.uint32)), "not reproducible"
+    ref = va.trace_backward_aniso(am, pr, nr, cam, p, gout)
+    _check_grad(sav, ref, f"aniso backward {case} {n}^3")
+
+
+def test_aniso_backward_f16_uses_stored_values():
+    n = 16
+    base = random_grid(n, seed=64, alpha_max=0.35)
+    pr, nr, cam = random_gbuffer(1, 19, 21, seed=65, n=n)
+    d, w = cone_set("five")
+    p = ConeParams(d, w, alpha_thresh=0.99)
+    gout = np.random.default_rng(66).normal(size=pr.shape[:3] + (8,))
+    rec, sav, again, out, pyr, g = _aniso_grads(base, n, pr, nr, cam, p, gout, dtype="f16")
+    dec = decoded(pyr, g)
+    _, info = va.trace_aniso(dec, pr, nr, cam, p, return_info=True)
+    gout[info["ambiguous"]] = 0.0
+    rec, sav, again, out, pyr, g = _aniso_grads(base, n, pr, nr, cam, p, gout, dtype="f16")
+    assert np.array_equal(rec.view(np.uint32), sav.view(np.uint32))
+    for r in again:
+        assert np.array_equal(sav.view(np.uint32), r.view(np.uint32)), "not reproducible"
+    ref = va.trace_backward_aniso(dec, pr, nr, cam, p, gout)
+    _check_grad(sav, ref, "aniso backward f16 (oracle on the stored values)")
