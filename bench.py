@@ -344,13 +344,24 @@ def main():
     amips_ms = timed(lambda: vct.build_mips(base, ga, pa), args.steps)
     atrace_ms = timed(lambda: vct.trace(pa, ga, pr, nr, cam, w.params, out), args.steps)
     asamples = vct.count_samples(pa, ga, pr, nr, cam, w.params)
+    # training through it: forward with saved states, then the adjoint (directional
+    # scatter + the per-level mip adjoint)
+    aws = torch.empty(vct.backward_workspace_bytes(ga, pr, nr, cam, w.params) - st_bytes, dtype=torch.uint8,
+                      device=dev)
+    asave_ms = timed(lambda: vct.trace_save(pa, ga, pr, nr, cam, w.params, out, state), args.steps)
+    abwd_ms = timed(lambda: vct.trace_backward_saved(pa, ga, pr, nr, cam, w.params, state, gout, aws, gbase),
+                    args.steps)
     aniso = {"pyramid_bytes": int(pa.numel()), "isotropic_pyramid_bytes": int(pyr.numel()),
              "build_mips_ms": amips_ms, "trace_ms": atrace_ms, "samples_per_frame": asamples,
              "trace_samples_per_s": asamples / (atrace_ms * 1e-3), "fwd_ms_per_frame": amips_ms + atrace_ms,
-             "trace_slowdown_vs_isotropic": atrace_ms / fwd_ms}
-    del pa
+             "trace_slowdown_vs_isotropic": atrace_ms / fwd_ms,
+             "trace_save_ms": asave_ms, "trace_backward_saved_ms": abwd_ms,
+             "fwd_bwd_ms_per_frame": amips_ms + asave_ms + abwd_ms,
+             "backward_slowdown_vs_isotropic": abwd_ms / bwd_ms}
+    del pa, aws
     log(f"anisotropic: mips {amips_ms:.3f} ms, trace {atrace_ms:.3f} ms ({asamples} samples, "
-        f"{atrace_ms / fwd_ms:.2f}x the isotropic trace)")
+        f"{atrace_ms / fwd_ms:.2f}x the isotropic trace); trace_save {asave_ms:.3f} ms, "
+        f"backward {abwd_ms:.3f} ms ({abwd_ms / bwd_ms:.2f}x the isotropic backward)")
 
     texel_bytes = 16 if args.dtype == "f32" else 8
     trace_bytes = samples * 16 * texel_bytes + npix * 64
@@ -455,7 +466,9 @@ def main():
                            "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": FLOPS_FWD_SAMPLE * aniso["samples_per_frame"] / (aniso["trace_ms"] * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
                            "model": f"{FLOPS_FWD_SAMPLE} FP32 ops per cone sample (the isotropic count: a lower bound, "
-                                    f"samples above level 0 read up to three directions)"},
+                                    f"samples above level 0 read up to three directions)",
+                           "backward_ms": aniso["trace_backward_saved_ms"],
+                           "fwd_bwd_ms_per_frame": aniso["fwd_bwd_ms_per_frame"]},
     }
     res["rows"] = rows
     if not args.no_cpu_baseline:
