@@ -233,13 +233,14 @@ int vct_trace_backward(const vct_grid* grid, const void* pyramid, const vct_gbuf
  * backward need not re-march once more to recover it.
  *
  * vct_lane_state_bytes: bytes of the lane-state buffer for these shapes (host
- * only); (b*h*w) * (n_diffuse + 2) states of 48 bytes, rounded up to 256.
+ * only); (b*h*w) * (n_diffuse + 2) states of 40 bytes, rounded up to 256.
  *
  * vct_trace_save: the forward of vct_trace (same cones, same sample counts),
  * with the colour accumulated as a double-float, so that `out` agrees with
  * vct_trace to float32 rounding rather than bit for bit; it also writes the
- * lane states (C_K, A_K, K and the sums the fixed-point scale of the adjoint
- * needs) to `lane_state` (device, opaque, overwritten).  Per-sample
+ * lane states (C_K, A_K, K and the two coefficients of the bound that sets
+ * the fixed-point scale of the adjoint) to `lane_state` (device, opaque,
+ * overwritten).  Per-sample
  * transmittance is not stored; the backward still recomputes it.
  *
  * vct_trace_backward_saved: vct_trace_backward given those lane states (same

@@ -343,7 +343,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_bwd_pass2(TraceArgs a, const fl
             // pixel setup and dL/d(out) are reloaded per cone to keep registers free
             const PixelSetup P = pixel_setup(a, a.pos_rough[pix], a.normal[pix]);
             const float3 cam = make_float3(a.cam_pos[3 * view], a.cam_pos[3 * view + 1], a.cam_pos[3 * view + 2]);
-            pass2_init(a, P, cam, gout[2 * pix], gout[2 * pix + 1], lane_get(state, n_pixels(a), pix, slot), slot,
+            pass2_init(a, P, cam, gout[2 * pix], gout[2 * pix + 1], lane_get(a, state, pix, slot), slot,
                        L);
         }
         int Kw = L.K;
@@ -616,7 +616,8 @@ BackwardPlan vct_plan_backward(const PyrLayout& L, const TraceArgs& a) {
     return P;
 }
 
-int64_t vct_lane_state_bytes(int64_t n_lanes) { return align256(n_lanes * (int64_t)sizeof(LaneState)); }
+// hi and lo (32 bytes) and the bound coefficients (8 bytes) of every lane
+int64_t vct_lane_state_bytes(int64_t n_lanes) { return align256(n_lanes * 40); }
 
 hipError_t vct_launch_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPlan& P, const float* grad_out,
                                float* grad_base, void* ws, const void* saved, hipStream_t s, EventSink& es) {

@@ -10,35 +10,49 @@
 
 namespace vct {
 
-// End state of one cone after its forward march (48 bytes).
+// End state of one cone after its forward march (40 bytes stored).
 struct LaneState {
     float4 hi;   // C_K.hi (rgb), A_K
     float4 lo;   // C_K.lo (rgb), K (as int bits)
-    float4 st;   // sum_k |T_k|, sum_{k<K-1} |T_k / T_{k+1}|, max_k |C_k|, T_{K-1}
+    float2 cf;   // (alpha, beta) of the contribution bound (lane_coefs)
 };
 
-// Lane states are stored field-major: field f (hi, lo, st) of cone `slot` of
-// pixel `pix` is float4 number (slot * 3 + f) * n_pix + pix, so the 64 pixels
-// of a wave read and write contiguous 1 KiB runs.
-__device__ __forceinline__ LaneState lane_get(const LaneState* __restrict__ state, size_t n_pix, size_t pix,
+__device__ __forceinline__ size_t n_pixels(const TraceArgs& a) { return (size_t)a.b * a.h * a.w; }
+
+// Lane states are stored field-major, so that the 64 pixels of a wave read and
+// write contiguous runs: float4 number (2 q + f) * n_pix + p holds field f
+// (hi, lo) of cone q of pixel p; after those 2 * nslots * n_pix float4s,
+// float2 number q * n_pix + p holds its bound coefficients.  The backward's
+// bound pass reads only the coefficients, the scatter pass only hi and lo.
+__device__ __forceinline__ const float2* lane_coefs_base(const TraceArgs& a, const LaneState* state) {
+    return reinterpret_cast<const float2*>(reinterpret_cast<const float4*>(state) +
+                                           (size_t)2 * (a.n_diffuse + 2) * n_pixels(a));
+}
+
+__device__ __forceinline__ LaneState lane_get(const TraceArgs& a, const LaneState* __restrict__ state, size_t pix,
                                               int slot) {
-    const float4* f = reinterpret_cast<const float4*>(state) + (size_t)slot * 3 * n_pix + pix;
+    const size_t np = n_pixels(a);
+    const float4* f = reinterpret_cast<const float4*>(state) + (size_t)slot * 2 * np + pix;
     LaneState s;
     s.hi = f[0];
-    s.lo = f[n_pix];
-    s.st = f[2 * n_pix];
+    s.lo = f[np];
+    s.cf = make_float2(0.f, 0.f);
     return s;
 }
 
-__device__ __forceinline__ void lane_put(LaneState* __restrict__ state, size_t n_pix, size_t pix, int slot,
-                                         const LaneState& s) {
-    float4* f = reinterpret_cast<float4*>(state) + (size_t)slot * 3 * n_pix + pix;
-    f[0] = s.hi;
-    f[n_pix] = s.lo;
-    f[2 * n_pix] = s.st;
+__device__ __forceinline__ float2 lane_get_coefs(const TraceArgs& a, const LaneState* __restrict__ state, size_t pix,
+                                                 int slot) {
+    return lane_coefs_base(a, state)[(size_t)slot * n_pixels(a) + pix];
 }
 
-__device__ __forceinline__ size_t n_pixels(const TraceArgs& a) { return (size_t)a.b * a.h * a.w; }
+__device__ __forceinline__ void lane_put(const TraceArgs& a, LaneState* __restrict__ state, size_t pix, int slot,
+                                         const LaneState& s) {
+    const size_t np = n_pixels(a);
+    float4* f = reinterpret_cast<float4*>(state) + (size_t)slot * 2 * np + pix;
+    f[0] = s.hi;
+    f[np] = s.lo;
+    const_cast<float2*>(lane_coefs_base(a, state))[(size_t)slot * np + pix] = s.cf;
+}
 
 // dL/dC (3) and dL/dA of cone `slot` from the pixel's dL/d(out) = (g0, g1).
 __device__ __forceinline__ void slot_grads(const TraceArgs& a, int slot, float4 g0, float4 g1, float gc[3],
@@ -114,11 +128,28 @@ __device__ __forceinline__ Pass1Out pass1_march(const TraceArgs& a, const LevelT
     return r;
 }
 
+// Bound on sum_k |dL/dc_k|_1 + |dL/da_k| of one cone, linear in its
+// gradient: |dL/dc_k| = |T_k| |dL/dC|, and for k < K-1
+// |dL/da_k| <= |T_k / T_{k+1}| (|dL/dC|_1 (|C_K| + max|C|) + |dL/dA| |T_K|);
+// the last sample gives |T_{K-1} dL/dA|.  So the sum is at most
+// alpha |dL/dC|_1 + beta |dL/dA| with
+//   alpha = sum_k |T_k| + sum_{k<K-1} |T_k / T_{k+1}| (|C_K| + max_k |C_k|),
+//   beta  = sum_{k<K-1} |T_k / T_{k+1}| |T_K| + |T_{K-1}|  (K > 0),
+// which the forward stores so that the backward's bound pass reads 8 bytes
+// per cone.
+__device__ __forceinline__ float2 lane_coefs(const Pass1Out& r) {
+    const float CK = fmaxf(fabsf(r.C[0].hi), fmaxf(fabsf(r.C[1].hi), fabsf(r.C[2].hi)));
+    const float TK = 1.0f - r.A;
+    const float alpha = r.ST + r.SQ * (CK + r.MC);
+    const float beta = r.SQ * fabsf(TK) + (r.K > 0 ? fabsf(r.Tlast) : 0.f);
+    return make_float2(alpha, beta);
+}
+
 __device__ __forceinline__ LaneState lane_state(const Pass1Out& r) {
     LaneState out;
     out.hi = make_float4(r.C[0].hi, r.C[1].hi, r.C[2].hi, r.A);
     out.lo = make_float4(r.C[0].lo, r.C[1].lo, r.C[2].lo, __int_as_float(r.K));
-    out.st = make_float4(r.ST, r.SQ, r.MC, r.Tlast);
+    out.cf = lane_coefs(r);
     return out;
 }
 
@@ -126,24 +157,17 @@ __device__ __forceinline__ LaneState zero_lane_state() {
     LaneState z;
     z.hi = make_float4(0.f, 0.f, 0.f, 0.f);
     z.lo = z.hi;
-    z.st = z.hi;
+    z.cf = make_float2(0.f, 0.f);
     return z;
 }
 
-// Bound on sum_k |dL/dc_k|_1 + |dL/da_k| of one cone from its end state:
-// |dL/dc_k| = |T_k| |dL/dC|, and for k < K-1
-// |dL/da_k| <= |T_k / T_{k+1}| (|dL/dC|_1 (|C_K| + max|C|) + |dL/dA| |T_K|);
-// the last sample gives |T_{K-1} dL/dA|.
-__device__ __forceinline__ float lane_bound(const TraceArgs& a, int slot, const LaneState& S, float4 g0, float4 g1) {
+// The bound of one cone for dL/d(out) = (g0, g1) of its pixel (1.001 covers
+// the float32 rounding of the sums).
+__device__ __forceinline__ float lane_bound(const TraceArgs& a, int slot, float2 cf, float4 g0, float4 g1) {
     float gc[3], ga;
     slot_grads(a, slot, g0, g1, gc, ga);
-    const int K = __float_as_int(S.lo.w);
     const float gc1 = fabsf(gc[0]) + fabsf(gc[1]) + fabsf(gc[2]);
-    const float TK = 1.0f - S.hi.w;
-    const float CK = fmaxf(fabsf(S.hi.x), fmaxf(fabsf(S.hi.y), fabsf(S.hi.z)));
-    const float b = S.st.x * gc1 + S.st.y * (gc1 * (CK + S.st.z) + fabsf(ga) * fabsf(TK)) +
-                    (K > 0 ? fabsf(ga) * fabsf(S.st.w) : 0.f);
-    return b * 1.001f;
+    return (cf.x * gc1 + cf.y * fabsf(ga)) * 1.001f;
 }
 
 // Pass 1 for one pixel: stores the lane states of its cones and returns the
@@ -153,11 +177,10 @@ __device__ __forceinline__ float pass1_pixel(const TraceArgs& a, const LevelTabl
                                              LaneState* __restrict__ state, int view, size_t pix,
                                              const DirTable* D = nullptr) {
     const int nslots = a.n_diffuse + 2;
-    const size_t np = n_pixels(a);
     float4 nr = a.normal[pix];
     float bound = 0.f;
     if (nr.w == 0.0f) {
-        for (int slot = 0; slot < nslots; ++slot) lane_put(state, np, pix, slot, zero_lane_state());
+        for (int slot = 0; slot < nslots; ++slot) lane_put(a, state, pix, slot, zero_lane_state());
         return 0.f;
     }
     float4 pr = a.pos_rough[pix];
@@ -169,9 +192,9 @@ __device__ __forceinline__ float pass1_pixel(const TraceArgs& a, const LevelTabl
         if (slot_enabled(a, slot)) {
             Cone c = cone_for_slot(a, P, slot, cam);
             out = lane_state(pass1_march<DT, ANISO>(a, T, c, D));
-            bound += lane_bound(a, slot, out, g0, g1);
+            bound += lane_bound(a, slot, out.cf, g0, g1);
         }
-        lane_put(state, np, pix, slot, out);
+        lane_put(a, state, pix, slot, out);
     }
     return bound;
 }
@@ -184,7 +207,7 @@ __device__ __forceinline__ float saved_bound_pixel(const TraceArgs& a, const flo
     const float4 g0 = gout[2 * pix], g1 = gout[2 * pix + 1];
     float bound = 0.f;
     for (int slot = 0; slot < nslots; ++slot)
-        if (slot_enabled(a, slot)) bound += lane_bound(a, slot, lane_get(state, n_pixels(a), pix, slot), g0, g1);
+        if (slot_enabled(a, slot)) bound += lane_bound(a, slot, lane_get_coefs(a, state, pix, slot), g0, g1);
     return bound;
 }
 
@@ -197,10 +220,9 @@ __device__ __forceinline__ void trace_save_pixel(const TraceArgs& a, const Level
     o0 = make_float4(0.f, 0.f, 0.f, 0.f);
     o1 = o0;
     const int nslots = a.n_diffuse + 2;
-    const size_t np = n_pixels(a);
     float4 nr = a.normal[pix];
     if (nr.w == 0.0f) {
-        for (int slot = 0; slot < nslots; ++slot) lane_put(state, np, pix, slot, zero_lane_state());
+        for (int slot = 0; slot < nslots; ++slot) lane_put(a, state, pix, slot, zero_lane_state());
         return;
     }
     PixelSetup P = pixel_setup(a, a.pos_rough[pix], nr);
@@ -226,7 +248,7 @@ __device__ __forceinline__ void trace_save_pixel(const TraceArgs& a, const Level
                 o1.w = r.A;
             }
         }
-        lane_put(state, np, pix, slot, out);
+        lane_put(a, state, pix, slot, out);
     }
 }
 

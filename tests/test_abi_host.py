@@ -236,7 +236,7 @@ def test_lane_state_size_query_follows_the_layout():
     gb.pos_rough = gb.normal = gb.cam_pos = 0x1000     # never dereferenced by a size query
     n = ctypes.c_size_t()
     assert vct.lib().vct_lane_state_bytes(ctypes.byref(gb), ctypes.byref(p), ctypes.byref(n)) == 0
-    assert n.value == (2 * 3 * 5 * (6 + 2) * 48 + 255) // 256 * 256
+    assert n.value == (2 * 3 * 5 * (6 + 2) * 40 + 255) // 256 * 256
     p.n_diffuse = 17
     assert vct.lib().vct_lane_state_bytes(ctypes.byref(gb), ctypes.byref(p), ctypes.byref(n)) == EINVAL
     assert "n_diffuse" in vct.lib().vct_last_error().decode()
