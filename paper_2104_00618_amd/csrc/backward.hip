@@ -26,7 +26,7 @@
 //                 workgroup's sum of per-cone contribution bounds
 //   k_bwd_scale   one workgroup: fixed-order sum of the bounds -> E
 //   k_bwd_pass2   per pixel: re-march, emit fixed-point tap gradients
-//   k_mip_adjoint per base texel: gather over levels, convert to float32
+//   k_mip_adjoint per 2x2x2 block of base texels: gather over levels, convert to float32
 #include "bwd_pixel.h"
 
 namespace {
@@ -394,37 +394,55 @@ struct AdjArgs {
     uint32_t off[VCT_MAX_LEVELS];
 };
 
+// One thread per 2x2x2 block of base texels (a level-1 texel): the sum of
+// the block's ancestors on levels >= 1 is shared by its eight children, so
+// the coarse levels are read once per block rather than once per texel.  A
+// wave takes one 4x4x4 brick of blocks, i.e. eight whole base-level bricks.
+// Integer sums, so the result does not depend on this grouping.
 __global__ __launch_bounds__(256) void k_mip_adjoint(AdjArgs m, const long long* __restrict__ acc,
                                                      const int* __restrict__ ctl, float4* __restrict__ grad) {
     const int E = ctl[0];
     const bool bad = ctl[1] != 0;
-    const uint32_t n = m.n;
-    const uint32_t total = n * n * n;
+    const int n = m.n;
+    const int nh = (n + 1) >> 1;             // blocks a side
+    const uint32_t nbh = (uint32_t)(nh + 3) >> 2;
+    const uint32_t total = nbh * nbh * nbh * 64u;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
-        int x = t % n, y = (t / n) % n, z = t / (n * n);
-        long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        const uint32_t brick = t >> 6, w = t & 63u;
+        const int bx = (int)(brick % nbh) * 4 + (int)(w & 3u);
+        const int by = (int)((brick / nbh) % nbh) * 4 + (int)((w >> 2) & 3u);
+        const int bz = (int)(brick / (nbh * nbh)) * 4 + (int)(w >> 4);
+        if (bx >= nh || by >= nh || bz >= nh) continue;
+        long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
-        for (int l = 0; l < VCT_MAX_LEVELS; ++l) {
+        for (int l = 1; l < VCT_MAX_LEVELS; ++l) {
             if (l < m.levels) {
-                uint32_t idx = m.off[l] + vct_brick_index(x >> l, y >> l, z >> l, m.nb[l]);
-                const long long* p = acc + (size_t)idx * 4;
-                longlong2 u = reinterpret_cast<const longlong2*>(p)[0];
-                longlong2 v = reinterpret_cast<const longlong2*>(p)[1];
-                s0 += u.x;
-                s1 += u.y;
-                s2 += v.x;
-                s3 += v.y;
+                const uint32_t idx = m.off[l] + vct_brick_index(bx >> (l - 1), by >> (l - 1), bz >> (l - 1), m.nb[l]);
+                const longlong2 u = reinterpret_cast<const longlong2*>(acc + (size_t)idx * 4)[0];
+                const longlong2 v = reinterpret_cast<const longlong2*>(acc + (size_t)idx * 4)[1];
+                a0 += u.x;
+                a1 += u.y;
+                a2 += v.x;
+                a3 += v.y;
             }
         }
-        float4 g;
-        if (bad) {
-            g = make_float4(__int_as_float(0x7fc00000), __int_as_float(0x7fc00000), __int_as_float(0x7fc00000),
-                            __int_as_float(0x7fc00000));
-        } else {
-            g = make_float4(ldexpf((float)s0, -E), ldexpf((float)s1, -E), ldexpf((float)s2, -E),
-                            ldexpf((float)s3, -E));
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int x = 2 * bx + (c & 1), y = 2 * by + ((c >> 1) & 1), z = 2 * bz + (c >> 2);
+            if (x >= n || y >= n || z >= n) continue;   // (n = 1)
+            const long long* p = acc + (size_t)(m.off[0] + vct_brick_index(x, y, z, m.nb[0])) * 4;
+            const longlong2 u = reinterpret_cast<const longlong2*>(p)[0];
+            const longlong2 v = reinterpret_cast<const longlong2*>(p)[1];
+            float4 g;
+            if (bad) {
+                g = make_float4(__int_as_float(0x7fc00000), __int_as_float(0x7fc00000), __int_as_float(0x7fc00000),
+                                __int_as_float(0x7fc00000));
+            } else {
+                g = make_float4(ldexpf((float)(a0 + u.x), -E), ldexpf((float)(a1 + u.y), -E),
+                                ldexpf((float)(a2 + v.x), -E), ldexpf((float)(a3 + v.y), -E));
+            }
+            grad[((size_t)z * n + y) * n + x] = g;
         }
-        grad[t] = g;
     }
 }
 
@@ -579,7 +597,8 @@ hipError_t run_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPl
         m.nb[l] = L.nb[l];
         m.off[l] = (uint32_t)L.off[l];
     }
-    uint32_t total = (uint32_t)L.n * L.n * L.n;
+    const uint32_t nbh = (uint32_t)((L.n + 1) / 2 + 3) / 4;
+    const uint32_t total = nbh * nbh * nbh * 64u;   // threads: one per block of 2x2x2 base texels, brick order
     int blocks = (int)((total + 255) / 256);
     if (blocks > 65536) blocks = 65536;
     es.mark(s);
