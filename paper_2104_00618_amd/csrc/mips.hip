@@ -20,7 +20,8 @@ constexpr int kMaxB = 16;
 struct MipPass {
     const float4* src;       // float32 logical [ns][ns][ns]
     int32_t ns;              // source side
-    int32_t B;               // block side
+    int32_t B;               // block side (a power of two)
+    int32_t lb;              // log2(B)
     int32_t nlev;            // levels produced after the first (<= log2 B)
     int32_t first;           // pyramid level of the source
     int32_t write_first;     // store the source level too
@@ -49,29 +50,45 @@ template <int DT>
 __global__ __launch_bounds__(kThreads) void k_mip_block(MipPass p) {
     __shared__ float4 bufA[kMaxB * kMaxB * kMaxB];
     __shared__ float4 bufB[(kMaxB / 2) * (kMaxB / 2) * (kMaxB / 2)];
-    const int B = p.B;
+    const int B = p.B, lb = p.lb;
     const int bid = blockIdx.x;
     const int bx = bid % p.nblk;
     const int by = (bid / p.nblk) % p.nblk;
     const int bz = bid / (p.nblk * p.nblk);
     const int cnt = B * B * B;
-    for (int t = threadIdx.x; t < cnt; t += kThreads) {
-        int x = t % B, y = (t / B) % B, z = t / (B * B);
-        int gx = bx * B + x, gy = by * B + y, gz = bz * B + z;
-        float4 v = p.src[((size_t)gz * p.ns + gy) * p.ns + gx];
-        bufA[t] = v;
-        if (p.write_first) put<DT>(p, p.first, gx, gy, gz, v);
+    // all of the thread's source loads first, then the stores: issued together,
+    // the loads overlap instead of each waiting behind the previous stores
+    constexpr int kPer = kMaxB * kMaxB * kMaxB / kThreads;
+    const float4* __restrict__ src = p.src;
+    float4 v[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int t = (int)threadIdx.x + i * kThreads;
+        if (t < cnt) {
+            const int x = t & (B - 1), y = (t >> lb) & (B - 1), z = t >> (2 * lb);
+            v[i] = src[((size_t)(bz * B + z) * p.ns + (by * B + y)) * p.ns + (bx * B + x)];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int t = (int)threadIdx.x + i * kThreads;
+        if (t < cnt) {
+            const int x = t & (B - 1), y = (t >> lb) & (B - 1), z = t >> (2 * lb);
+            bufA[t] = v[i];
+            if (p.write_first) put<DT>(p, p.first, bx * B + x, by * B + y, bz * B + z, v[i]);
+        }
     }
     __syncthreads();
     float4* cur = bufA;
     float4* nxt = bufB;
-    int m = B;
+    int m = B, lm = lb;
     for (int j = 1; j <= p.nlev; ++j) {
         const int pm = m;
         m >>= 1;
+        --lm;
         const int c = m * m * m;
         for (int t = threadIdx.x; t < c; t += kThreads) {
-            int x = t % m, y = (t / m) % m, z = t / (m * m);
+            const int x = t & (m - 1), y = (t >> lm) & (m - 1), z = t >> (2 * lm);
             float4 ch[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -230,6 +247,7 @@ hipError_t run_build(const PyrLayout& L, const float* base, void* pyr, hipStream
         p.src = src;
         p.ns = ns;
         p.B = B;
+        p.lb = lb;
         p.nlev = nlev;
         p.first = first;
         p.write_first = write_first;
