@@ -169,13 +169,16 @@ __global__ __launch_bounds__(256) void k_mip_aniso(AnisoPass p) {
               z = (int)(brick / (nb * nb)) * 4 + (int)(w >> 4);
     if (x >= p.side || y >= p.side || z >= p.side) return;
     const uint32_t at = vct_brick_index(x, y, z, p.nb);
-    float4 ch[8];
+    // every load before the first store: a store to the pyramid may alias the
+    // later loads as far as the compiler knows, so interleaved they would run
+    // one after another
+    float4 ch[8], r[6];
     if (p.level == 1) {
+        const float4* __restrict__ base = p.base;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int cx = 2 * x + (q & 1), cy = 2 * y + ((q >> 1) & 1), cz = 2 * z + (q >> 2);
-            ch[q] = p.base[((size_t)cz * p.n_base + cy) * p.n_base + cx];
-            vct_store_texel<DT>(p.pyr, vct_brick_index(cx, cy, cz, p.nb_child), ch[q]);
+            ch[q] = base[((size_t)cz * p.n_base + cy) * p.n_base + cx];
         }
     }
 #pragma unroll
@@ -187,8 +190,17 @@ __global__ __launch_bounds__(256) void k_mip_aniso(AnisoPass p) {
                     p.pyr, p.src[d] + vct_brick_index(2 * x + (q & 1), 2 * y + ((q >> 1) & 1), 2 * z + (q >> 2),
                                                       p.nb_child));
         }
-        vct_store_texel<DT>(p.pyr, p.dst[d] + at, reduce_dir(ch, d >> 1, (d & 1) == 0));
+        r[d] = reduce_dir(ch, d >> 1, (d & 1) == 0);
     }
+    if (p.level == 1) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            vct_store_texel<DT>(p.pyr,
+                                vct_brick_index(2 * x + (q & 1), 2 * y + ((q >> 1) & 1), 2 * z + (q >> 2), p.nb_child),
+                                ch[q]);
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) vct_store_texel<DT>(p.pyr, p.dst[d] + at, r[d]);
 }
 
 template <int DT>
