@@ -36,7 +36,7 @@ using namespace vct;
 constexpr int kThreads = 256;
 
 template <int DT, bool ANISO>
-__global__ __launch_bounds__(kThreads) void k_bwd_pass1(TraceArgs a, const float4* __restrict__ gout,
+__global__ __launch_bounds__(kThreads, 4) void k_bwd_pass1(TraceArgs a, const float4* __restrict__ gout,
                                                         LaneState* __restrict__ state, float* __restrict__ part) {
     __shared__ LevelTable T;
     __shared__ DirSlot<ANISO> D;
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_pass1(TraceArgs a, const float
 // Forward that also saves every cone's end state (training path: the
 // backward then skips pass 1).
 template <int DT, bool ANISO>
-__global__ __launch_bounds__(kThreads) void k_trace_save(TraceArgs a, float4* __restrict__ out,
+__global__ __launch_bounds__(kThreads, 4) void k_trace_save(TraceArgs a, float4* __restrict__ out,
                                                          LaneState* __restrict__ state) {
     __shared__ LevelTable T;
     __shared__ DirSlot<ANISO> D;
