@@ -239,6 +239,8 @@ template <bool ALPHA_ONLY>
 __device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, float wl, const float gs[4],
                                            const EmitLane& e, int E, int lev_shift, unsigned long long* __restrict__ acc,
                                            unsigned long long* small, uint32_t small_off, int lane) {
+    unsigned long long mask = __ballot(live);
+    if (mask == 0) return;   // (wave-uniform: no lane emits on this level)
     float wp[8];
     emit_weights(geo, wl, e, wp);
     float wpart[4];
@@ -248,7 +250,6 @@ __device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, floa
     const int kcl = (geo.dx == 0 ? 1 : 0) | (geo.dy == 0 ? 2 : 0) | (geo.dz == 0 ? 4 : 0);
     const bool emitter = ALPHA_ONLY ? ((lane & 0x31) == 0) : (lane < 32);
     const int ch = ALPHA_ONLY ? 3 : e.ch;
-    unsigned long long mask = __ballot(live);
     while (mask) {
         const int leader = __builtin_ctzll(mask);
         const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
