@@ -395,11 +395,13 @@ struct AdjArgs {
     uint32_t off[VCT_MAX_LEVELS];
 };
 
-// One thread per 2x2x2 block of base texels (a level-1 texel): the sum of
-// the block's ancestors on levels >= 1 is shared by its eight children, so
-// the coarse levels are read once per block rather than once per texel.  A
-// wave takes one 4x4x4 brick of blocks, i.e. eight whole base-level bricks.
-// Integer sums, so the result does not depend on this grouping.
+// Two threads per 2x2x2 block of base texels (a level-1 texel), one for each
+// x half: the sum of the block's ancestors on levels >= 1 is shared by the
+// four children a thread writes, so the coarse levels are read twice per block
+// rather than once per texel.  Lane pairs take the two x halves, so every
+// store instruction writes whole 128-byte rows of the gradient (8 texels in
+// x), and a wave reads whole lines of the base-level accumulator.  Integer
+// sums, so the result does not depend on this grouping.
 __global__ __launch_bounds__(256) void k_mip_adjoint(AdjArgs m, const long long* __restrict__ acc,
                                                      const int* __restrict__ ctl, float4* __restrict__ grad) {
     const int E = ctl[0];
@@ -407,13 +409,15 @@ __global__ __launch_bounds__(256) void k_mip_adjoint(AdjArgs m, const long long*
     const int n = m.n;
     const int nh = (n + 1) >> 1;             // blocks a side
     const uint32_t nbh = (uint32_t)(nh + 3) >> 2;
-    const uint32_t total = nbh * nbh * nbh * 64u;
+    const uint32_t total = nbh * nbh * nbh * 128u;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
-        const uint32_t brick = t >> 6, w = t & 63u;
+        const uint32_t brick = t >> 7, w = (t >> 1) & 63u;
+        const int dx = (int)(t & 1u);
         const int bx = (int)(brick % nbh) * 4 + (int)(w & 3u);
         const int by = (int)((brick / nbh) % nbh) * 4 + (int)((w >> 2) & 3u);
         const int bz = (int)(brick / (nbh * nbh)) * 4 + (int)(w >> 4);
-        if (bx >= nh || by >= nh || bz >= nh) continue;
+        const int x = 2 * bx + dx;
+        if (bx >= nh || by >= nh || bz >= nh || x >= n) continue;   // (x >= n: n = 1)
         long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
         for (int l = 1; l < VCT_MAX_LEVELS; ++l) {
@@ -428,9 +432,9 @@ __global__ __launch_bounds__(256) void k_mip_adjoint(AdjArgs m, const long long*
             }
         }
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int x = 2 * bx + (c & 1), y = 2 * by + ((c >> 1) & 1), z = 2 * bz + (c >> 2);
-            if (x >= n || y >= n || z >= n) continue;   // (n = 1)
+        for (int c = 0; c < 4; ++c) {
+            const int y = 2 * by + (c & 1), z = 2 * bz + (c >> 1);
+            if (y >= n || z >= n) continue;   // (n = 1)
             const long long* p = acc + (size_t)(m.off[0] + vct_brick_index(x, y, z, m.nb[0])) * 4;
             const longlong2 u = reinterpret_cast<const longlong2*>(p)[0];
             const longlong2 v = reinterpret_cast<const longlong2*>(p)[1];
@@ -599,7 +603,7 @@ hipError_t run_backward(const PyrLayout& L, const TraceArgs& a, const BackwardPl
         m.off[l] = (uint32_t)L.off[l];
     }
     const uint32_t nbh = (uint32_t)((L.n + 1) / 2 + 3) / 4;
-    const uint32_t total = nbh * nbh * nbh * 64u;   // threads: one per block of 2x2x2 base texels, brick order
+    const uint32_t total = nbh * nbh * nbh * 128u;   // threads: two per block of 2x2x2 base texels, brick order
     int blocks = (int)((total + 255) / 256);
     if (blocks > 65536) blocks = 65536;
     es.mark(s);
