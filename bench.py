@@ -111,9 +111,9 @@ def cpu_baseline(w, n_pix=12288, seed=0):
     n = info["samples"]
     parts = {"mips_s": t1 - t0, "forward_s": t2 - t1, "backward_s": t3 - t2, "samples": n, "pixels": n_pix}
     base = {"value": n / (t3 - t0), "unit": "cone samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"build_mips of the 256^3 grid + forward and adjoint of all 7 cones of {n_pix} seeded pixels "
-                      f"of the 1080p frame ({n} samples; {t1 - t0:.1f} + {t2 - t1:.1f} + {t3 - t2:.1f} s, NumPy "
-                      f"FP64, single thread)"}
+            "sample": f"build_mips of the {w.n}^3 grid + forward and adjoint of all {w.params.n_diffuse + int(w.params.enable_spec) + int(w.params.enable_occ)} cones of "
+                      f"{n_pix} seeded pixels of the {w.shape[2]}x{w.shape[1]} frame ({n} samples; {t1 - t0:.1f} + "
+                      f"{t2 - t1:.1f} + {t3 - t2:.1f} s, NumPy FP64, single thread)"}
     return base, parts
 
 
