@@ -226,3 +226,28 @@ def test_aniso_backward_f16_uses_stored_values():
         assert np.array_equal(sav.view(np.uint32), r.view(np.uint32)), "not reproducible"
     ref = va.trace_backward_aniso(dec, pr, nr, cam, p, gout)
     _check_grad(sav, ref, "aniso backward f16 (oracle on the stored values)")
+
+
+@pytest.mark.parametrize("n,levels", [(2, None), (4, None), (8, 2)])
+def test_aniso_backward_tiny_and_partial_pyramids(n, levels):
+    """Directional pyramids of a few texels (all levels in the workgroup LDS
+    table) and a two-level pyramid (level 1 is the top)."""
+    rng = np.random.default_rng(300 + n)
+    a = rng.uniform(0, 0.3, size=(n, n, n, 1))
+    base = np.concatenate([rng.uniform(0, 1, size=(n, n, n, 3)) * a, a], -1).astype(np.float32)
+    pr, nr, cam = random_gbuffer(1, 9, 11, seed=400 + n, n=max(n, 8))   # (points inside the cube)
+    d, w = cone_set("six")
+    p = ConeParams(d, w, alpha_thresh=0.99)
+    am = va.build_aniso_mips(base, levels)
+    fwd, info = va.trace_aniso(am, pr, nr, cam, p, return_info=True)
+    gout = rng.normal(size=fwd.shape)
+    gout[info["ambiguous"]] = 0.0
+    ref = va.trace_backward_aniso(am, pr, nr, cam, p, gout)
+    pyr, g = gpu_aniso(base, n, levels=levels)
+    t = [dev(x) for x in (pr, nr, cam)]
+    go = dev(gout.astype(np.float32))
+    rec = vct.trace_backward(pyr, g, *t, p, go).cpu().numpy()
+    _, state = vct.trace_save(pyr, g, *t, p)
+    sav = vct.trace_backward_saved(pyr, g, *t, p, state, go).cpu().numpy()
+    assert np.array_equal(rec.view(np.uint32), sav.view(np.uint32))
+    _check_grad(sav, ref, f"aniso backward tiny {n}^3 levels {levels}")

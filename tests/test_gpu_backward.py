@@ -194,3 +194,29 @@ def test_saved_state_backward_random_ragged_and_full_launch():
     w = workload("c3gt")
     gout = (rng.normal(size=w.shape + (8,)) * 1e-2).astype(np.float32)
     _saved_vs_recompute(w.base, w.n, w.pos_rough, w.normal, w.cam_pos, w.params, gout)
+
+
+@pytest.mark.parametrize("n,levels", [(1, None), (2, None), (4, None), (8, None), (16, 2)])
+def test_backward_tiny_and_partial_pyramids(n, levels):
+    """Grids below one brick, a single voxel, and a two-level pyramid: the
+    mip adjoint's block mapping has its edge cases here (a block wider than
+    the grid, one thread of a lane pair past the last column)."""
+    rng = np.random.default_rng(100 + n)
+    a = rng.uniform(0, 0.3, size=(n, n, n, 1))
+    base = np.concatenate([rng.uniform(0, 1, size=(n, n, n, 3)) * a, a], -1).astype(np.float32)
+    pr, nr, cam = random_gbuffer(1, 9, 11, seed=200 + n, n=max(n, 8))   # (points inside the cube)
+    d, wt = cone_set("five")
+    p = ConeParams(d, wt, alpha_thresh=0.99)
+    gout = rng.normal(size=(1, 9, 11, 8)).astype(np.float32)
+    mips = oracle.build_mips(base, levels)
+    _, info = oracle.trace(mips, pr, nr, cam, p, return_info=True)
+    gout[info["ambiguous"]] = 0.0
+    ref = oracle.trace_backward(mips, pr, nr, cam, p, gout)
+    g = vct.Grid(n, levels=levels)
+    pyr = vct.build_mips(dev(base), g)
+    t = [dev(x) for x in (pr, nr, cam)]
+    rec = vct.trace_backward(pyr, g, *t, p, dev(gout)).cpu().numpy()
+    _, state = vct.trace_save(pyr, g, *t, p)
+    sav = vct.trace_backward_saved(pyr, g, *t, p, state, dev(gout)).cpu().numpy()
+    assert np.array_equal(rec.view(np.uint32), sav.view(np.uint32))
+    _compare(rec, ref, f"tiny {n}^3 levels {levels}")
