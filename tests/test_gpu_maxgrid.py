@@ -65,20 +65,24 @@ def test_1024_cubed_f32_far_texels(aniso):
     assert np.abs(ref).max() > 0.05          # the cones do see the block
 
 
-def test_1024_cubed_f32_backward_saved():
+@pytest.mark.parametrize("aniso", [False, True])
+def test_1024_cubed_f32_backward_saved(aniso):
     """The training path at 1024^3 float32: trace_save + trace_backward_saved
     against the oracle's adjoint on the window; every voxel outside it gets
-    exactly zero."""
+    exactly zero.  The anisotropic accumulator (2.0e9 texels, 64 GB) is indexed
+    far past 2^32 bytes, and its per-level float adjoint runs over all six
+    directions of every level."""
     block = random_grid(N - W0, seed=79, alpha_max=0.25)
     base = torch.zeros((N, N, N, 4), dtype=torch.float32, device=DEV)
     base[W0:, W0:, W0:] = torch.from_numpy(block).to(DEV)
-    g = vct.Grid(N)
+    g = vct.Grid(N, anisotropic=aniso)
     pyr = vct.build_mips(base, g)
     del base
     pr, nr, cam, p = _inputs()
     origin, extent = (W0 / N,) * 3, (N - W0) / N
-    mips = oracle.build_mips(block)
-    ref_out, info = oracle.trace(mips, pr, nr, cam, p, origin, extent, return_info=True)
+    mips = va.build_aniso_mips(block) if aniso else oracle.build_mips(block)
+    fwd = va.trace_aniso if aniso else oracle.trace
+    ref_out, info = fwd(mips, pr, nr, cam, p, origin, extent, return_info=True)
     # pixels with a termination tie may take another step count on either side: no gradient through them
     gout = np.random.default_rng(80).normal(size=pr.shape[:3] + (8,)).astype(np.float32)
     gout[info["ambiguous"]] = 0.0
@@ -92,11 +96,13 @@ def test_1024_cubed_f32_backward_saved():
     del grad
     torch.cuda.empty_cache()
     e = range_errors(out.cpu().numpy(), ref_out, ~info["ambiguous"].reshape(-1))
-    ref = oracle.trace_backward(mips, pr, nr, cam, p, gout, origin, extent)
+    bwd = va.trace_backward_aniso if aniso else oracle.trace_backward
+    ref = bwd(mips, pr, nr, cam, p, gout, origin, extent)
     scale = np.abs(ref).max()
     err = np.abs(inside - ref).max() / scale
     rms = np.sqrt(np.mean((inside - ref) ** 2)) / scale
-    print(f"1024^3 f32 training path: forward {fmt(e)}; gradient max {err:.2e} rms {rms:.2e}; "
+    print(f"1024^3 f32 {'anisotropic' if aniso else 'isotropic'} training path: forward {fmt(e)}; "
+          f"gradient max {err:.2e} rms {rms:.2e}; "
           f"{outside_nonzero} nonzero outside the block; {int(info['ambiguous'].sum())} tie pixels without "
           f"gradient", flush=True)
     assert worst(e)[0] <= 1e-5 and err <= 1e-4 and rms <= 1e-5 and outside_nonzero == 0
