@@ -251,3 +251,32 @@ def test_aniso_backward_tiny_and_partial_pyramids(n, levels):
     sav = vct.trace_backward_saved(pyr, g, *t, p, state, go).cpu().numpy()
     assert np.array_equal(rec.view(np.uint32), sav.view(np.uint32))
     _check_grad(sav, ref, f"aniso backward tiny {n}^3 levels {levels}")
+
+
+def test_aniso_training_step_full_launch_sparse_grad_out():
+    """The training step the benchmark times, through an anisotropic pyramid:
+    the 1920x1080 frame at 256^3 (trace_save + trace_backward_saved), with
+    dL/d(out) nonzero on 64 seeded surface pixels only, so that the oracle can
+    form the whole gradient from those pixels."""
+    w = workload("c1")
+    b, h, wd = w.shape
+    rng = np.random.default_rng(91)
+    surf = np.argwhere(w.normal[..., 3] != 0)
+    pick = surf[rng.choice(len(surf), size=64, replace=False)]
+    vv, yy, xx = pick[:, 0], pick[:, 1], pick[:, 2]
+    am = va.build_aniso_mips(w.base)
+    pr = w.pos_rough[vv, yy, xx][None, None]
+    nr = w.normal[vv, yy, xx][None, None]
+    fwd, info = va.trace_aniso(am, pr, nr, w.cam_pos[:1], w.params, return_info=True)
+    go = rng.normal(size=fwd.shape)
+    go[info["ambiguous"]] = 0.0              # (termination ties: no gradient through them)
+    ref = va.trace_backward_aniso(am, pr, nr, w.cam_pos[:1], w.params, go)
+    gout = np.zeros((b, h, wd, 8), np.float32)
+    gout[vv, yy, xx] = go[0, 0]
+    pyr, g = gpu_aniso(w.base, w.n)
+    t = [dev(x) for x in (w.pos_rough, w.normal, w.cam_pos)]
+    out, state = vct.trace_save(pyr, g, *t, w.params)
+    got = vct.trace_backward_saved(pyr, g, *t, w.params, state, dev(gout)).cpu().numpy()
+    check(out.cpu().numpy()[vv, yy, xx].reshape(1, 1, -1, 8), fwd, ~info["ambiguous"].reshape(-1), TOL,
+          "aniso trace_save c1 1080p sampled")
+    _check_grad(got, ref, "aniso training step c1 256^3 1920x1080, 64 pixels of gradient")
