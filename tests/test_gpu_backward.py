@@ -220,3 +220,30 @@ def test_backward_tiny_and_partial_pyramids(n, levels):
     sav = vct.trace_backward_saved(pyr, g, *t, p, state, dev(gout)).cpu().numpy()
     assert np.array_equal(rec.view(np.uint32), sav.view(np.uint32))
     _compare(rec, ref, f"tiny {n}^3 levels {levels}")
+
+
+def test_training_step_bench_launch_sparse_grad_out():
+    """The training step the benchmark times (256^3, 1920x1080, trace_save +
+    trace_backward_saved), with dL/d(out) nonzero on 64 seeded surface pixels
+    only, so that the oracle can form the whole gradient from those pixels."""
+    w = workload("c1")
+    b, h, wd = w.shape
+    rng = np.random.default_rng(92)
+    surf = np.argwhere(w.normal[..., 3] != 0)
+    pick = surf[rng.choice(len(surf), size=64, replace=False)]
+    vv, yy, xx = pick[:, 0], pick[:, 1], pick[:, 2]
+    mips = oracle.build_mips(w.base)
+    pr = w.pos_rough[vv, yy, xx][None, None]
+    nr = w.normal[vv, yy, xx][None, None]
+    _, info = oracle.trace(mips, pr, nr, w.cam_pos[:1], w.params, return_info=True)
+    go = rng.normal(size=(1, 1, 64, 8))
+    go[info["ambiguous"]] = 0.0              # (termination ties: no gradient through them)
+    ref = oracle.trace_backward(mips, pr, nr, w.cam_pos[:1], w.params, go)
+    gout = np.zeros((b, h, wd, 8), np.float32)
+    gout[vv, yy, xx] = go[0, 0]
+    g = vct.Grid(w.n)
+    pyr = vct.build_mips(dev(w.base), g)
+    t = [dev(x) for x in (w.pos_rough, w.normal, w.cam_pos)]
+    _, state = vct.trace_save(pyr, g, *t, w.params)
+    got = vct.trace_backward_saved(pyr, g, *t, w.params, state, dev(gout)).cpu().numpy()
+    _compare(got, ref, "training step c1 256^3 1920x1080, 64 pixels of gradient")
