@@ -63,12 +63,23 @@ PASS2_SOURCES = ["backward.hip", "bwd_pixel.h", "march.h", "texel.h", "vct_inter
 PROFILE = os.path.join(ROOT, "profiles", "cone_trace_256cubed_1080p_f32.md")
 
 
-def kernel_source_digest():
+def code_text(text):
+    """C++ source with comments removed and whitespace collapsed: the part of
+    a file that can change a kernel."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_digest(csrc=None):
+    """Digest of the code (not the comments) of the scatter pass's sources."""
     import hashlib
+    csrc = csrc or os.path.join(ROOT, "paper_2104_00618_amd", "csrc")
     h = hashlib.sha256()
     for f in PASS2_SOURCES:
-        with open(os.path.join(ROOT, "paper_2104_00618_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            h.update(code_text(fh.read()).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 

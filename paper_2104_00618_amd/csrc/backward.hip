@@ -27,6 +27,12 @@
 //   k_bwd_scale   one workgroup: fixed-order sum of the bounds -> E
 //   k_bwd_pass2   per pixel: re-march, emit fixed-point tap gradients
 //   k_mip_adjoint per 2x2x2 block of base texels: gather over levels, convert to float32
+//
+// Anisotropic pyramids (Section 5.1.3) use the same kernels instantiated for
+// six directional pyramids: every level accumulates at the scale 2^E, and
+// k_aniso_adjoint, one launch per level from the top, replaces k_mip_adjoint
+// (the adjoint of a directional texel depends on the stored texels, so it is
+// no longer a fixed factor per level).
 #include "bwd_pixel.h"
 
 namespace {

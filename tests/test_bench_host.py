@@ -55,3 +55,19 @@ def test_oracle_baseline_record_on_a_small_frame():
     assert base["value"] > 0 and parts["samples"] > 0 and parts["pixels"] == 48
     assert f"{w.n}^3" in base["sample"] and "48 seeded pixels" in base["sample"]
     assert parts["mips_s"] >= 0 and parts["forward_s"] > 0 and parts["backward_s"] > 0
+
+
+def test_digest_follows_code_not_comments(tmp_path):
+    import shutil
+    src = os.path.join(ROOT, "paper_2104_00618_amd", "csrc")
+    copy = tmp_path / "csrc"
+    shutil.copytree(src, copy)
+    base = bench.kernel_source_digest(str(copy))
+    assert base == bench.kernel_source_digest()
+    f = copy / "backward.hip"
+    text = f.read_text()
+    f.write_text("// a new comment line\n" + text.replace("\n", "\n\n", 3) + "\n/* and a block\n comment */\n")
+    assert bench.kernel_source_digest(str(copy)) == base
+    f.write_text(text.replace("constexpr int kThreads = 256;", "constexpr int kThreads = 128;"))
+    assert bench.kernel_source_digest(str(copy)) != base
+    assert bench.code_text("a; // b\n/* c\n d */  e;") == "a; e;"
