@@ -325,6 +325,7 @@ def main():
     shade_out = torch.empty(w.shape + (4,), dtype=torch.float32, device=dev)
     shade_ms = {f"{nl}_lights": timed(lambda nl=nl: vct.shade(pyr, grid, pr, nr, cam, mat, w.params, scene_lights(nl),
                                                                 shade_out), args.steps) for nl in (1, 3)}
+    shade_samples = vct.count_shade_samples(pyr, grid, pr, nr, cam, mat, w.params, scene_lights(3))
     recompute_bwd_ms = timed(lambda: vct.trace_backward(pyr, grid, pr, nr, cam, w.params, gout, ws, gbase),
                              max(args.steps // 2, 1))
     # per-frame revoxelization: voxelize the Cornell mesh (direct-light injection) into the 256^3 base grid
@@ -461,8 +462,14 @@ def main():
                         "logical_tap_GBps": trace_gbs},
         "a7_backward": dict(roofline, ms=bwd_ms),
         "f1_shade": {"kernel": "k_shade", "ms": shade_ms["3_lights"], "pixels_per_s": npix / (shade_ms["3_lights"] * 1e-3),
-                     "bound": "alu", "achieved": None,
-                     "model": "the sampler and march of k_trace; its cone samples are not counted, so no rate"},
+                     "samples": shade_samples, "samples_per_s": shade_samples / (shade_ms["3_lights"] * 1e-3),
+                     "bound": "alu",
+                     "achieved": FLOPS_FWD_SAMPLE * shade_samples / (shade_ms["3_lights"] * 1e-3) / 1e12,
+                     "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": FLOPS_FWD_SAMPLE * shade_samples / (shade_ms["3_lights"] * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+                     "model": f"{FLOPS_FWD_SAMPLE} FP32 ops per cone sample (the trace's count: a lower bound, the "
+                              f"per-light terms are left out) x {shade_samples} samples (vct_count_shade_samples, "
+                              f"3 lights, the thesis's variants)"},
         "f2_voxelize": {"kernel": "k_clear + k_tri_setup + k_chunk_scan + k_raster + k_resolve", "ms": vox_ms,
                         "bound": "hbm", "achieved": vox_bytes / (vox_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": vox_bytes / (vox_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,

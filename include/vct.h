@@ -276,6 +276,16 @@ int vct_trace_backward_saved(const vct_grid* grid, const void* pyramid, const vc
 int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf, const float* material,
               const vct_cone_params* params, const vct_shade_params* shade, float* out, hipStream_t stream);
 
+/* Same marches as vct_shade (diffuse cones first-hit or accumulated, the
+ * specular cone, one occlusion cone per light with or without falloff), but
+ * instead of radiance it writes the total number of cone samples they take
+ * over all pixels to *count (device uint64, overwritten; 0 with no pixels).
+ * Used to state the shading pass's throughput in samples per second.
+ * Errors: those of vct_shade, with `count` in place of `out`. */
+int vct_count_shade_samples(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                            const float* material, const vct_cone_params* params, const vct_shade_params* shade,
+                            unsigned long long* count, hipStream_t stream);
+
 /* Voxelize a triangle mesh with direct-light injection into a base grid
  * (Section 4.4 "Voxelization Process": rasterization onto an N x N viewport,
  * dominant axis selection, 3D texture storage; Section 5.4.4 "Voxelization").

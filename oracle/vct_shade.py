@@ -81,7 +81,7 @@ def _march_variant(mips, lanes, cone_params, mode, shade, origin=(0.0, 0.0, 0.0)
     """The two modified marches: mode "first_hit" (S2) returns rgb [m,3];
     mode "falloff" returns accumulated alpha [m] with every sample's alpha
     scaled by smoothstep(0, max_dist, sqrt(t) * shadow_strength).  Also
-    returns the ambiguity flag per lane."""
+    returns the ambiguity flag and the number of samples taken per lane."""
     n0 = mips[0].shape[0]
     nlev = len(mips)
     v0 = extent / n0
@@ -92,6 +92,7 @@ def _march_variant(mips, lanes, cone_params, mode, shade, origin=(0.0, 0.0, 0.0)
     t = np.full(m, float(cone_params.t0))
     rgb = np.zeros((m, 3))
     occ = np.zeros(m)
+    taken = np.zeros(m, dtype=np.int64)
     amb = (np.abs(t - tmax) < AMBIG_T_REL * np.abs(tmax)) | lanes["tie"]
     active = t <= tmax
     if mode == "falloff":
@@ -107,6 +108,7 @@ def _march_variant(mips, lanes, cone_params, mode, shade, origin=(0.0, 0.0, 0.0)
         lam = np.clip(np.log2(d / v0), 0.0, nlev - 1)
         p = x[idx] + ti[:, None] * w[idx]
         s = sample(mips, p, lam, origin, extent) if sampler is None else sampler(p, lam, w[idx])
+        taken[idx] += 1
         if mode == "first_hit":
             hit = s[:, 3] > shade.first_hit_alpha
             amb[idx] |= np.abs(s[:, 3] - shade.first_hit_alpha) < AMBIG_HIT
@@ -122,7 +124,7 @@ def _march_variant(mips, lanes, cone_params, mode, shade, origin=(0.0, 0.0, 0.0)
                 amb[idx] |= np.abs(occ[idx] - thresh) < 1e-5
             amb[idx] |= np.abs(t[idx] - tmax[idx]) < AMBIG_T_REL * np.abs(tmax[idx])
             active[idx] = (t[idx] <= tmax[idx]) & (occ[idx] < thresh)
-    return (rgb if mode == "first_hit" else occ), amb
+    return (rgb if mode == "first_hit" else occ), amb, taken
 
 
 def _occlusion_lanes(pos_rough, normal, cone_params, light, n, origin, extent):
@@ -158,6 +160,7 @@ def shade(mips, pos_rough, normal, material, cam_pos, cone_params, shade, origin
     pix = np.nonzero(valid)[0]
     view = np.repeat(np.arange(b), h * w)
     amb = np.zeros(npix, dtype=bool)
+    samples = 0                      # cone samples taken by every march (diffuse, specular, occlusion)
 
     # diffuse + specular lanes (Section 4.2 cone set)
     p = copy.copy(cone_params)
@@ -172,14 +175,16 @@ def shade(mips, pos_rough, normal, material, cam_pos, cone_params, shade, origin
     if dsel.any():
         dl = {k: v[dsel] for k, v in lanes.items()}
         if shade.diffuse_first_hit:
-            c, a = _march_variant(mips, dl, cone_params, "first_hit", shade, origin, extent, sampler)
+            c, a, k = _march_variant(mips, dl, cone_params, "first_hit", shade, origin, extent, sampler)
         else:
             r = march(mips, dl, cone_params, origin, extent, sampler=sampler)
-            c, a = r["c"], r["ambiguous"]
+            c, a, k = r["c"], r["ambiguous"], r["K"]
+        samples += int(np.sum(k))
         np.add.at(diffuse, dl["pix"], wq[dl["slot"]][:, None] * c)
         np.logical_or.at(amb, dl["pix"], a)
     sl = {k: v[ssel] for k, v in lanes.items()}
     rs = march(mips, sl, cone_params, origin, extent, sampler=sampler)
+    samples += int(np.sum(rs["K"]))
     c_spec = np.zeros((npix, 3))
     c_spec[sl["pix"]] = rs["c"]
     np.logical_or.at(amb, sl["pix"], rs["ambiguous"])
@@ -203,10 +208,11 @@ def shade(mips, pos_rough, normal, material, cam_pos, cone_params, shade, origin
         light = np.asarray(shade.light_pos[s], dtype=np.float64)
         ol = _occlusion_lanes(pos_rough, normal, cone_params, light, n0, origin, extent)
         if shade.occlusion_falloff:
-            occ, a = _march_variant(mips, ol, cone_params, "falloff", shade, origin, extent, sampler)
+            occ, a, k = _march_variant(mips, ol, cone_params, "falloff", shade, origin, extent, sampler)
         else:
             r = march(mips, ol, cone_params, origin, extent, sampler=sampler)
-            occ, a = r["alpha"], r["ambiguous"]
+            occ, a, k = r["alpha"], r["ambiguous"], r["K"]
+        samples += int(np.sum(k))
         np.logical_or.at(amb, ol["pix"], a)
         vis = np.ones(npix)
         vis[ol["pix"]] = 1.0 - occ
@@ -230,5 +236,5 @@ def shade(mips, pos_rough, normal, material, cam_pos, cone_params, shade, origin
     out[pix, 3] = o_min[pix]
     out = out.reshape(b, h, w, 4)
     if return_info:
-        return out, {"ambiguous": amb.reshape(shape)}
+        return out, {"ambiguous": amb.reshape(shape), "samples": samples}
     return out

@@ -69,6 +69,7 @@ def lib():
         "vct_trace": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
         "vct_count_samples": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
         "vct_shade": [P(CGrid), vp, P(CGBuffer), vp, P(CConeParams), P(CShadeParams), vp, vp],
+        "vct_count_shade_samples": [P(CGrid), vp, P(CGBuffer), vp, P(CConeParams), P(CShadeParams), vp, vp],
         "vct_voxelize_workspace_bytes": [P(CGrid), ctypes.c_int64, ctypes.c_int32, P(sz)],
         "vct_voxelize": [P(CGrid), vp, vp, ctypes.c_int64, P(CVoxelizeParams), vp, vp, vp, vp, sz, vp],
         "vct_bounce_workspace_bytes": [P(CGrid), P(sz)],
@@ -376,6 +377,20 @@ def shade(pyramid, grid, pos_rough, normal, cam_pos, material, params, sparams, 
                                _stream(dev)))
     return out
 
+
+
+def count_shade_samples(pyramid, grid, pos_rough, normal, cam_pos, material, params, sparams):
+    """Total cone samples the marches of shade() take (integer, exact)."""
+    gb = _gbuf(pos_rough, normal, cam_pos)
+    dev = pos_rough.device
+    _need(pyramid, "pyramid", torch.uint8, None, dev)
+    _need(material, "material", torch.float32, tuple(pos_rough.shape), dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib().vct_count_shade_samples(ctypes.byref(grid.c()), _ptr(pyramid), ctypes.byref(gb), _ptr(material),
+                                             ctypes.byref(cone_params(params)), ctypes.byref(shade_params(sparams)),
+                                             _ptr(cnt), _stream(dev)))
+    return int(cnt.item())
 
 def voxelize_workspace_bytes(grid, n_tris, surface=False):
     n = ctypes.c_size_t()

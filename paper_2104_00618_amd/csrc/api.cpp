@@ -266,9 +266,9 @@ int vct_count_samples(const vct_grid* grid, const void* pyramid, const vct_gbuff
     return trace_common("vct_count_samples", grid, pyramid, gbuf, params, nullptr, count, true, stream);
 }
 
-int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf, const float* material,
-              const vct_cone_params* params, const vct_shade_params* shade, float* out, hipStream_t stream) {
-    const char* fn = "vct_shade";
+static int shade_common(const char* fn, const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                        const float* material, const vct_cone_params* params, const vct_shade_params* shade,
+                        float* out, unsigned long long* count, bool counting, hipStream_t stream) {
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
@@ -294,18 +294,33 @@ int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf
     for (auto& e : nonneg)
         if (!finite(e.v) || e.v < 0.f) return fail(VCT_EINVAL, fn, "%s must be finite and >= 0", e.name);
     long long np = (long long)gbuf->b * gbuf->h * gbuf->w;
-    if (np > 0 && (!pyramid || !material || !out))
-        return fail(VCT_EINVAL, fn, "pyramid, material and out must be non-null");
+    if (counting && !count) return fail(VCT_EINVAL, fn, "count is null");
+    if (np > 0 && (!pyramid || !material || (!counting && !out)))
+        return fail(VCT_EINVAL, fn, counting ? "pyramid and material must be non-null"
+                                             : "pyramid, material and out must be non-null");
     PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype, grid->anisotropic);
     TraceArgs a = make_args(grid, L, pyramid, gbuf, params);
-    if (a.n_tiles == 0) {
+    if (a.n_tiles == 0 && !counting) {
         ok();
         return VCT_OK;
     }
-    hipError_t e = vct_launch_shade(a, grid->dtype, shade, material, out, stream, es);
+    hipError_t e = vct_launch_shade(a, grid->dtype, shade, material, counting ? nullptr : out,
+                                    counting ? count : nullptr, stream, es);
     if (e != hipSuccess) return device_error(fn, e);
     ok();
     return VCT_OK;
+}
+
+int vct_shade(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf, const float* material,
+              const vct_cone_params* params, const vct_shade_params* shade, float* out, hipStream_t stream) {
+    return shade_common("vct_shade", grid, pyramid, gbuf, material, params, shade, out, nullptr, false, stream);
+}
+
+int vct_count_shade_samples(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                            const float* material, const vct_cone_params* params, const vct_shade_params* shade,
+                            unsigned long long* count, hipStream_t stream) {
+    return shade_common("vct_count_shade_samples", grid, pyramid, gbuf, material, params, shade, nullptr, count,
+                        true, stream);
 }
 
 int vct_voxelize_workspace_bytes(const vct_grid* grid, int64_t n_tris, int32_t surface, size_t* bytes) {

@@ -20,32 +20,62 @@ namespace {
 
 using namespace vct;
 
-template <int DT, bool ANISO>
-__global__ __launch_bounds__(256) void k_shade(TraceArgs a, ShadeArgs s, float4* __restrict__ out) {
+// COUNT: instead of the shaded pixels, add the number of cone samples every
+// march takes (diffuse, specular, one occlusion cone per light) to *count.
+template <int DT, bool ANISO, bool COUNT>
+__global__ __launch_bounds__(256) void k_shade(TraceArgs a, ShadeArgs s, float4* __restrict__ out,
+                                               unsigned long long* __restrict__ count) {
     __shared__ LevelTable T;
     __shared__ DirSlot<ANISO> D;
+    __shared__ unsigned long long s_cnt;
     load_level_table(a, &T);
     load_dir_table(a, &D);
+    if (COUNT && threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
     const int tile = xcd_tile(blockIdx.x, a.n_tiles);
     int view, y, x;
     tile_pixel(a, tile, threadIdx.x, view, y, x);
-    if (!(x < a.w && y < a.h)) return;
+    const bool inb = x < a.w && y < a.h;
     const size_t pix = ((size_t)view * a.h + y) * a.w + x;
-    const float4 nr = a.normal[pix];
-    out[pix] = nr.w == 0.0f ? make_float4(0.f, 0.f, 0.f, 0.f) : shade_pixel<DT, ANISO>(a, T, dir_ptr(D), s, view, pix, nr);
+    unsigned int n = 0;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (inb) {
+        const float4 nr = a.normal[pix];
+        if (nr.w != 0.0f) v = shade_pixel<DT, ANISO>(a, T, dir_ptr(D), s, view, pix, nr, n);
+    }
+    if constexpr (COUNT) {
+        if (n) atomicAdd(&s_cnt, (unsigned long long)n);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_cnt) atomicAdd(count, s_cnt);
+    } else {
+        if (inb) out[pix] = v;
+    }
+}
+
+__global__ void k_zero_count(unsigned long long* p) { *p = 0ull; }
+
+template <int DT, bool ANISO>
+void launch_shade(const TraceArgs& a, const ShadeArgs& s, float* out, unsigned long long* count, hipStream_t st) {
+    if (count)
+        hipLaunchKernelGGL((k_shade<DT, ANISO, true>), dim3(a.n_tiles), dim3(256), 0, st, a, s, nullptr, count);
+    else
+        hipLaunchKernelGGL((k_shade<DT, ANISO, false>), dim3(a.n_tiles), dim3(256), 0, st, a, s,
+                           reinterpret_cast<float4*>(out), nullptr);
 }
 
 template <int DT>
-hipError_t run_shade(const TraceArgs& a, const ShadeArgs& s, float* out, hipStream_t st, EventSink& es) {
+hipError_t run_shade(const TraceArgs& a, const ShadeArgs& s, float* out, unsigned long long* count, hipStream_t st,
+                     EventSink& es) {
+    if (count) {
+        es.mark(st);
+        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, count);
+    }
     if (a.n_tiles > 0) {
         es.mark(st);
         if (a.aniso)
-            hipLaunchKernelGGL((k_shade<DT, true>), dim3(a.n_tiles), dim3(256), 0, st, a, s,
-                               reinterpret_cast<float4*>(out));
+            launch_shade<DT, true>(a, s, out, count, st);
         else
-            hipLaunchKernelGGL((k_shade<DT, false>), dim3(a.n_tiles), dim3(256), 0, st, a, s,
-                               reinterpret_cast<float4*>(out));
+            launch_shade<DT, false>(a, s, out, count, st);
     }
     es.mark(st);
     return hipGetLastError();
@@ -54,7 +84,7 @@ hipError_t run_shade(const TraceArgs& a, const ShadeArgs& s, float* out, hipStre
 }  // namespace
 
 hipError_t vct_launch_shade(const TraceArgs& a, int dtype, const vct_shade_params* p, const float* material,
-                            float* out, hipStream_t st, EventSink& es) {
+                            float* out, unsigned long long* count, hipStream_t st, EventSink& es) {
     ShadeArgs s{};
     s.n_lights = p->n_lights;
     const double scale = (double)a.scale_hi + (double)a.scale_lo;
@@ -77,5 +107,5 @@ hipError_t vct_launch_shade(const TraceArgs& a, int dtype, const vct_shade_param
     s.q = p->shininess_falloff;
     s.material = reinterpret_cast<const float4*>(material);
     return vct_dispatch_dt(dtype, a.wide != 0,
-                           [&](auto dt) { return run_shade<decltype(dt)::value>(a, s, out, st, es); });
+                           [&](auto dt) { return run_shade<decltype(dt)::value>(a, s, out, count, st, es); });
 }

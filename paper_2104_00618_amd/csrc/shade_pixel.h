@@ -20,16 +20,18 @@ struct ShadeArgs {
 };
 
 // First-hit diffuse cone: march until a sample's alpha exceeds `thresh` and
-// return that sample's (premultiplied) colour; 0 if none before t_max.
+// return that sample's (premultiplied) colour; 0 if none before t_max.  The
+// samples taken are added to n.
 template <int DT, bool ANISO>
 __device__ __forceinline__ float3 march_first_hit(const TraceArgs& a, const LevelTable& T, const DirTable* dirs,
-                                                  const Cone& c, float thresh) {
+                                                  const Cone& c, float thresh, unsigned int& n) {
     float3 rgb = make_float3(0.f, 0.f, 0.f);
     df t = {a.t0, 0.0f};
     for (int k = 0; k < a.max_steps; ++k) {
         if (!t_within(t, c.tmax)) break;
         const float d = fmaxf(c.two_tan * t.hi, a.voxel);
         const float4 s = sample_at<DT, ANISO>(a, T, c, t, lod_of(a, d), dirs);
+        ++n;
         if (s.w > thresh) {
             rgb = make_float3(s.x, s.y, s.z);
             break;
@@ -40,10 +42,11 @@ __device__ __forceinline__ float3 march_first_hit(const TraceArgs& a, const Leve
 }
 
 // Occlusion cone with distance falloff: A += (1 - A) s.a smoothstep(0,
-// max_dist, sqrt(t) * strength) while t <= t_max and A < alpha_thresh.
+// max_dist, sqrt(t) * strength) while t <= t_max and A < alpha_thresh.  The
+// samples taken are added to n.
 template <int DT, bool ANISO>
 __device__ __forceinline__ float march_falloff(const TraceArgs& a, const LevelTable& T, const DirTable* dirs,
-                                               const Cone& c, float strength) {
+                                               const Cone& c, float strength, unsigned int& n) {
     float A = 0.f;
     df t = {a.t0, 0.0f};
     const float inv = 1.0f / a.max_dist;
@@ -51,6 +54,7 @@ __device__ __forceinline__ float march_falloff(const TraceArgs& a, const LevelTa
         if (!t_within(t, c.tmax) || !(A < a.alpha_thresh)) break;
         const float d = fmaxf(c.two_tan * t.hi, a.voxel);
         const float4 s = sample_at<DT, ANISO>(a, T, c, t, lod_of(a, d), dirs);
+        ++n;
         const float h = fminf(fmaxf(sqrtf(t.hi) * strength * inv, 0.0f), 1.0f);
         A = __builtin_fmaf(1.0f - A, s.w * (h * h * (3.0f - 2.0f * h)), A);
         t = df_add(t, a.step_factor * d);
@@ -69,10 +73,10 @@ __device__ __forceinline__ Cone light_cone(const TraceArgs& a, const PixelSetup&
     return make_cone(a, P, w, a.occ_aperture, fminf(a.max_dist, dist));
 }
 
-// (L.rgb, o_min) of one valid pixel.
+// (L.rgb, o_min) of one valid pixel; the samples of all its cones are added to n.
 template <int DT, bool ANISO>
 __device__ __forceinline__ float4 shade_pixel(const TraceArgs& a, const LevelTable& T, const DirTable* dirs,
-                                              const ShadeArgs& s, int view, size_t pix, float4 nr) {
+                                              const ShadeArgs& s, int view, size_t pix, float4 nr, unsigned int& n) {
     const float4 pr = a.pos_rough[pix];
     const float4 mat = s.material[pix];
     const PixelSetup P = pixel_setup(a, pr, nr);
@@ -84,10 +88,11 @@ __device__ __forceinline__ float4 shade_pixel(const TraceArgs& a, const LevelTab
         const Cone c = cone_for_slot(a, P, q, cam);
         float3 col;
         if (s.first_hit) {
-            col = march_first_hit<DT, ANISO>(a, T, dirs, c, s.first_hit_alpha);
+            col = march_first_hit<DT, ANISO>(a, T, dirs, c, s.first_hit_alpha, n);
         } else {
             const MarchResult m = march<DT, ANISO>(a, T, c, dirs);
             col = make_float3(m.r, m.g, m.b);
+            n += (unsigned int)m.k;
         }
         const float wq = a.weight[q];
         D.x = __builtin_fmaf(wq, col.x, D.x);
@@ -96,6 +101,7 @@ __device__ __forceinline__ float4 shade_pixel(const TraceArgs& a, const LevelTab
     }
     // indirect specular: one trace along the reflection axis
     const MarchResult ms = march<DT, ANISO>(a, T, cone_for_slot(a, P, a.n_diffuse, cam), dirs);
+    n += (unsigned int)ms.k;
     // unit reflection axis (as in the specular cone) and view direction
     const float3 v = normalize3(P.px - cam.x, P.py - cam.y, P.pz - cam.z);
     const float vn = v.x * P.nx + v.y * P.ny + v.z * P.nz;
@@ -107,8 +113,14 @@ __device__ __forceinline__ float4 shade_pixel(const TraceArgs& a, const LevelTab
     float3 direct = make_float3(0.f, 0.f, 0.f);
     for (int l = 0; l < s.n_lights; ++l) {
         const Cone co = light_cone(a, P, s.light_tex[l]);
-        const float A = s.falloff ? march_falloff<DT, ANISO>(a, T, dirs, co, s.shadow_strength)
-                                  : march<DT, ANISO>(a, T, co, dirs).a;
+        float A;
+        if (s.falloff) {
+            A = march_falloff<DT, ANISO>(a, T, dirs, co, s.shadow_strength, n);
+        } else {
+            const MarchResult mo = march<DT, ANISO>(a, T, co, dirs);
+            A = mo.a;
+            n += (unsigned int)mo.k;
+        }
         const float V = 1.0f - A;
         omin = fminf(omin, V);
         const float3 L = normalize3(s.light_pos[l][0] - P.px, s.light_pos[l][1] - P.py, s.light_pos[l][2] - P.pz);

@@ -178,8 +178,9 @@ hipError_t vct_launch_voxelize(const vct_grid* g, const float* tris, const float
 size_t vct_bounce_workspace_size(int n);
 hipError_t vct_launch_bounce(const TraceArgs& a, int dtype, const float* base, const float* normal,
                              const float* albedo, float* out, void* ws, hipStream_t s, EventSink& es);
+// count != nullptr: no shading; *count = the cone samples all marches take
 hipError_t vct_launch_shade(const TraceArgs& a, int dtype, const vct_shade_params* p, const float* material,
-                            float* out, hipStream_t s, EventSink& es);
+                            float* out, unsigned long long* count, hipStream_t s, EventSink& es);
 
 struct BackwardPlan {
     int64_t n_lanes;          // pixels * cones

@@ -354,6 +354,28 @@ def test_shade_rejects_non_finite_lights_and_null_buffers():
                          None) == 0
 
 
+def test_count_shade_samples_validates_like_shade():
+    lib = vct.lib()
+    g = vct.Grid(16).c()
+    p = B.cone_params(_params(alpha_thresh=0.99))
+    s = _shade_params()
+    gb = _empty_gbuf()
+    rc = lib.vct_count_shade_samples(ctypes.byref(g), None, ctypes.byref(gb), None, ctypes.byref(p), ctypes.byref(s),
+                                     None, None)
+    assert rc == EINVAL and "count" in lib.vct_last_error().decode()
+    s.first_hit_alpha = 1.5
+    rc = lib.vct_count_shade_samples(ctypes.byref(g), None, ctypes.byref(gb), None, ctypes.byref(p), ctypes.byref(s),
+                                     ctypes.c_void_p(0x1000), None)
+    assert rc == EINVAL and "first_hit_alpha" in lib.vct_last_error().decode()
+    s = _shade_params()
+    gb = B.CGBuffer()
+    gb.b, gb.h, gb.w = 1, 2, 2
+    gb.pos_rough = gb.normal = gb.cam_pos = 0x1000
+    rc = lib.vct_count_shade_samples(ctypes.byref(g), ctypes.c_void_p(0x1000), ctypes.byref(gb), None,
+                                     ctypes.byref(p), ctypes.byref(s), ctypes.c_void_p(0x1000), None)
+    assert rc == EINVAL and "material" in lib.vct_last_error().decode()
+
+
 def test_voxelize_validation_and_workspace_size():
     lib = vct.lib()
     g = vct.Grid(32).c()

@@ -102,3 +102,31 @@ def test_shade_empty_gbuffer():
     z = torch.zeros((1, 0, 5, 4), device=DEV)
     out = vct.shade(pyr, g, z, z, torch.zeros((1, 3), device=DEV), z, workload("c0").params, scene_lights(1))
     assert out.shape == (1, 0, 5, 4)
+
+
+@pytest.mark.parametrize("flags", [{}, dict(diffuse_first_hit=False, occlusion_falloff=False, specular_brdf=False)],
+                         ids=["variants", "unmodified"])
+def test_shade_sample_count_matches_oracle(flags):
+    """vct_count_shade_samples counts the samples of every shading march
+    exactly: pixels where the oracle sees a tie (termination, first hit) are
+    dropped from the G-buffer on both sides, and the counts must then agree to
+    the sample.  alpha_thresh 0.99, since with 1 a float32 alpha reaches 1.0
+    one step before the float64 one."""
+    w = workload("c0")
+    p = w.params.replace(alpha_thresh=0.99)
+    mat = random_material(w.shape, seed=8)
+    sp = scene_lights(2, **flags)
+    mips = oracle.build_mips(w.base)
+    _, info = oracle.shade(mips, w.pos_rough, w.normal, mat, w.cam_pos, p, sp, return_info=True)
+    nr = w.normal.copy()
+    nr[info["ambiguous"], 3] = 0.0
+    _, ref = oracle.shade(mips, w.pos_rough, nr, mat, w.cam_pos, p, sp, return_info=True)
+    assert not ref["ambiguous"].any() and ref["samples"] > 0
+    g = vct.Grid(w.n)
+    pyr = vct.build_mips(dev(w.base), g)
+    cnt = vct.count_shade_samples(pyr, g, dev(w.pos_rough), dev(nr), dev(w.cam_pos), dev(mat), p, sp)
+    print(f"shade samples {flags or 'variants'}: gpu {cnt}, oracle {ref['samples']} "
+          f"({int(info['ambiguous'].sum())} tie pixels dropped)", flush=True)
+    assert cnt == ref["samples"]
+    e = torch.zeros((1, 0, 3, 4), device=DEV)
+    assert vct.count_shade_samples(pyr, g, e, e.clone(), dev(w.cam_pos), e.clone(), p, sp) == 0

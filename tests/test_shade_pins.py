@@ -203,3 +203,71 @@ def test_duplicated_light_doubles_the_light_sums():
     light_part1 = o1[..., 0:3] - o1[..., 3:4] * diffuse
     light_part2 = o2[..., 0:3] - o2[..., 3:4] * diffuse
     np.testing.assert_allclose(light_part2, 2 * light_part1, rtol=1e-12, atol=1e-15)
+
+
+# --- sample count --------------------------------------------------------------
+
+def _schedule_length(gamma, tmax, p, v0):
+    """Samples of a cone of aperture gamma through an empty grid: the t
+    recurrence t_0 = t0, d = max(2 t tan(gamma / 2), v0), t += beta d, one
+    sample while t <= t_max (written out as a scalar loop)."""
+    t, k = float(p.t0), 0
+    while t <= tmax:
+        d = max(2.0 * t * math.tan(gamma / 2.0), v0)
+        t += float(p.step_factor) * d
+        k += 1
+    return k
+
+
+@pytest.mark.parametrize("first_hit,falloff", [(True, True), (False, False)])
+def test_sample_count_in_an_empty_grid_is_the_schedule_length(first_hit, falloff):
+    """Nothing stops a cone early in an empty grid (no first hit, no opacity),
+    so the shading pass takes exactly the schedule length of every cone: u
+    diffuse, one specular, one occlusion cone per light with t_max = min(max_dist,
+    distance to the light)."""
+    n = 16
+    v0 = 1.0 / n
+    mips = uniform_mips(n, (0.0, 0.0, 0.0, 0.0))
+    pr, nr, mat, cam = one_pixel((0.3, 0.4, 0.5), (0.0, 0.6, 0.8), (0.5, 0.5, 1.5), rough=0.3)
+    p = cone_params(max_dist=0.6)
+    sp = ShadeParams(*lights((0.5, 0.9, 0.5), (0.32, 0.45, 0.6)), diffuse_first_hit=first_hit,
+                     occlusion_falloff=falloff)
+    _, info = oracle.shade(mips, pr, nr, mat, cam, p, sp, return_info=True)
+    lanes = oracle.cone_lanes(pr, nr, cam, p.replace(enable_occ=False), n)
+    expect = sum(_schedule_length(g, tm, p, v0) for g, tm in zip(lanes["gamma"], lanes["tmax"]))
+    o = lanes["o"][0]
+    for light in sp.light_pos:
+        dist = float(np.linalg.norm(np.asarray(light, np.float64) - o))
+        expect += _schedule_length(p.occ_aperture, min(p.max_dist, dist), p, v0)
+    assert len(lanes["gamma"]) == len(p.diffuse_dirs) + 1
+    assert info["samples"] == expect and expect > 0
+    assert not info["ambiguous"].any()
+    # the near light cuts its occlusion cone short
+    assert _schedule_length(p.occ_aperture, min(p.max_dist, float(np.linalg.norm(sp.light_pos[1] - o))), p, v0) < \
+        _schedule_length(p.occ_aperture, p.max_dist, p, v0)
+
+
+def test_opaque_grid_stops_every_cone_but_the_falloff_one_at_its_first_sample():
+    """In a grid of alpha 1 a first-hit diffuse cone takes exactly one sample,
+    and so do the accumulated diffuse, specular and plain occlusion cones (alpha
+    reaches the threshold at once).  The occlusion cone with falloff scales each
+    sample's alpha by a Hermite step of sqrt(t) * strength: with strength 0 the
+    step is 0, nothing accumulates, and the cone takes its whole schedule even
+    through the opaque grid; with strength 2 it takes more than one sample."""
+    n = 16
+    mips = uniform_mips(n, (0.2, 0.3, 0.4, 1.0))
+    pr, nr, mat, cam = one_pixel((0.3, 0.4, 0.5), (0.0, 0.6, 0.8), (0.5, 0.5, 1.5))
+    p = cone_params()
+    sp = ShadeParams(*lights((0.5, 0.9, 0.5)), shadow_strength=2.0)
+    u = len(p.diffuse_dirs)
+    _, plain = oracle.shade(mips, pr, nr, mat, cam, p, sp.replace(occlusion_falloff=False), return_info=True)
+    _, acc = oracle.shade(mips, pr, nr, mat, cam, p, sp.replace(diffuse_first_hit=False, occlusion_falloff=False),
+                          return_info=True)
+    _, fall = oracle.shade(mips, pr, nr, mat, cam, p, sp, return_info=True)
+    _, zero = oracle.shade(mips, pr, nr, mat, cam, p, sp.replace(shadow_strength=0.0), return_info=True)
+    assert plain["samples"] == u + 2 and acc["samples"] == u + 2
+    lanes = oracle.cone_lanes(pr, nr, cam, p.replace(enable_occ=False), n)
+    dist = float(np.linalg.norm(np.asarray(sp.light_pos[0], np.float64) - lanes["o"][0]))
+    full = _schedule_length(p.occ_aperture, min(p.max_dist, dist), p, 1.0 / n)
+    assert zero["samples"] == u + 1 + full
+    assert u + 2 < fall["samples"] < u + 1 + full
