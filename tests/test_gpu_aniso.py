@@ -209,23 +209,24 @@ def test_aniso_backward_matches_oracle(case):
     _check_grad(sav, ref, f"aniso backward {case} {n}^3")
 
 
-def test_aniso_backward_f16_uses_stored_values():
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_aniso_backward_f16_uses_stored_values(dtype):
     n = 16
     base = random_grid(n, seed=64, alpha_max=0.35)
     pr, nr, cam = random_gbuffer(1, 19, 21, seed=65, n=n)
     d, w = cone_set("five")
     p = ConeParams(d, w, alpha_thresh=0.99)
     gout = np.random.default_rng(66).normal(size=pr.shape[:3] + (8,))
-    rec, sav, again, out, pyr, g = _aniso_grads(base, n, pr, nr, cam, p, gout, dtype="f16")
+    rec, sav, again, out, pyr, g = _aniso_grads(base, n, pr, nr, cam, p, gout, dtype=dtype)
     dec = decoded(pyr, g)
     _, info = va.trace_aniso(dec, pr, nr, cam, p, return_info=True)
     gout[info["ambiguous"]] = 0.0
-    rec, sav, again, out, pyr, g = _aniso_grads(base, n, pr, nr, cam, p, gout, dtype="f16")
+    rec, sav, again, out, pyr, g = _aniso_grads(base, n, pr, nr, cam, p, gout, dtype=dtype)
     assert np.array_equal(rec.view(np.uint32), sav.view(np.uint32))
     for r in again:
         assert np.array_equal(sav.view(np.uint32), r.view(np.uint32)), "not reproducible"
     ref = va.trace_backward_aniso(dec, pr, nr, cam, p, gout)
-    _check_grad(sav, ref, "aniso backward f16 (oracle on the stored values)")
+    _check_grad(sav, ref, f"aniso backward {dtype} (oracle on the stored values)")
 
 
 @pytest.mark.parametrize("n,levels", [(2, None), (4, None), (8, 2)])

@@ -86,18 +86,19 @@ def test_backward_is_bitwise_deterministic_and_scales_exactly():
     assert np.abs(runs[0]).max() > 0
 
 
-def test_backward_fp16_pyramid_uses_stored_values():
-    """With a float16 pyramid the gradient is that of the march over the
-    decoded pyramid (rounding treated as identity)."""
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_backward_fp16_pyramid_uses_stored_values(dtype):
+    """With a float16 or bfloat16 pyramid the gradient is that of the march
+    over the decoded pyramid (rounding treated as identity)."""
     w, g, gout = _case_fd()
     gout = _zero_ties(w, g, w.pos_rough, w.normal, w.cam_pos, w.params, gout)
-    gpu, pyr, grid = _gpu_grad(g, w.n, w.pos_rough, w.normal, w.cam_pos, w.params, gout, dtype="f16")
+    gpu, pyr, grid = _gpu_grad(g, w.n, w.pos_rough, w.normal, w.cam_pos, w.params, gout, dtype=dtype)
     decoded = [vct.unpack_level(pyr, grid, l).cpu().numpy().astype(np.float64) for l in range(grid.levels)]
     _, info = oracle.trace(decoded, w.pos_rough, w.normal, w.cam_pos, w.params, return_info=True)
     gout[info["ambiguous"]] = 0.0
-    gpu, _, _ = _gpu_grad(g, w.n, w.pos_rough, w.normal, w.cam_pos, w.params, gout, dtype="f16")
+    gpu, _, _ = _gpu_grad(g, w.n, w.pos_rough, w.normal, w.cam_pos, w.params, gout, dtype=dtype)
     ref = oracle.trace_backward(decoded, w.pos_rough, w.normal, w.cam_pos, w.params, gout)
-    _compare(gpu, ref, "c3fd f16 pyramid")
+    _compare(gpu, ref, f"c3fd {dtype} pyramid")
 
 
 def test_autograd_function_matches_backward_entry_point():
@@ -166,7 +167,7 @@ def _saved_vs_recompute(base, n, pr, nr, cam, params, gout, dtype="f32"):
     return out.cpu().numpy(), fwd.cpu().numpy()
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 def test_saved_state_backward_equals_recompute_and_forward_matches_oracle(dtype):
     """trace_save + trace_backward_saved give the gradient of trace_backward bit
     for bit; the saved forward's output meets the forward's parity bar."""

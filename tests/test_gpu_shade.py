@@ -86,14 +86,15 @@ def test_shade_c1_full_launch_sampled_pixels():
     check(got[v, y, x], ref, amb, "shade c1 256^3 1080p sampled")
 
 
-def test_shade_f16_pyramid_uses_the_stored_values():
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_shade_f16_pyramid_uses_the_stored_values(dtype):
     w = workload("c0")
     mat = random_material(w.shape, seed=9)
     sp = scene_lights(2)
-    got, pyr, g = gpu_shade(w.base, w.n, w.pos_rough, w.normal, w.cam_pos, mat, w.params, sp, dtype="f16")
+    got, pyr, g = gpu_shade(w.base, w.n, w.pos_rough, w.normal, w.cam_pos, mat, w.params, sp, dtype=dtype)
     decoded = [vct.unpack_level(pyr, g, l).cpu().numpy().astype(np.float64) for l in range(g.levels)]
     ref, info = oracle.shade(decoded, w.pos_rough, w.normal, mat, w.cam_pos, w.params, sp, return_info=True)
-    check(got, ref, info["ambiguous"], "shade c0 f16 pyramid")
+    check(got, ref, info["ambiguous"], f"shade c0 {dtype} pyramid")
 
 
 def test_shade_empty_gbuffer():
