@@ -101,9 +101,10 @@ def test_backward_fp16_pyramid_uses_stored_values(dtype):
     _compare(gpu, ref, f"c3fd {dtype} pyramid")
 
 
-def test_autograd_function_matches_backward_entry_point():
+@pytest.mark.parametrize("aniso", [False, True])
+def test_autograd_function_matches_backward_entry_point(aniso):
     w, g, gout = _case_fd()
-    grid = vct.Grid(w.n)
+    grid = vct.Grid(w.n, anisotropic=aniso)
     base = dev(g).requires_grad_(True)
     out = vct.render(base, grid, dev(w.pos_rough), dev(w.normal), dev(w.cam_pos), w.params)
     (out * dev(gout)).sum().backward()
