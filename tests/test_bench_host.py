@@ -71,3 +71,13 @@ def test_digest_follows_code_not_comments(tmp_path):
     f.write_text(text.replace("constexpr int kThreads = 256;", "constexpr int kThreads = 128;"))
     assert bench.kernel_source_digest(str(copy)) != base
     assert bench.code_text("a; // b\n/* c\n d */  e;") == "a; e;"
+
+
+def test_oracle_baseline_runs_on_one_thread():
+    """The baseline says "cores": 1: bench.py times the oracle under a
+    one-thread limit for every threaded library NumPy may call."""
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    assert "threadpool_limits(limits=1)" in src
+    from threadpoolctl import threadpool_info, threadpool_limits
+    with threadpool_limits(limits=1):
+        assert all(p["num_threads"] == 1 for p in threadpool_info())
