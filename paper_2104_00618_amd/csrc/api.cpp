@@ -137,6 +137,7 @@ TraceArgs make_args(const vct_grid* g, const PyrLayout& L, const void* pyr, cons
     }
     a.pyr = pyr;
     a.rsrc = vct_pyr_rsrc(pyr, g->dtype == VCT_F32 ? 16 : 8, (uint32_t)L.total_texels);
+    a.rraw = vct_pyr_raw_rsrc(pyr, (uint64_t)L.total_texels * (uint64_t)L.texel_bytes);
     for (int d = 0; d < 6; ++d)
         for (int l = 0; l < VCT_MAX_LEVELS; ++l)
             a.ddelta[d][l] = l < g->levels ? (uint32_t)(L.doff[d][l] - L.off[l]) : 0u;

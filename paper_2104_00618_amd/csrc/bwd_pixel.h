@@ -315,20 +315,19 @@ __device__ __forceinline__ LevelGeom level_geom(const LevelTable& T, int l, df U
 
 // The level's sample: the same taps, weights and products as level_taps +
 // gather of the forward, so the recomputed samples equal the forward's.
+// (Per-tap loads for every storage type: the forward's paired float16 /
+// bfloat16 loads would save texture-address requests here too, but this pass
+// is bound by VALU issue, and their extra branch made it 2-3 % slower.  The
+// texels and the accumulation order are the same, so the samples are too.)
 template <int DT>
-__device__ __forceinline__ float4 gather_geom(const vct_v4i& rsrc, const LevelGeom& g) {
+__device__ __forceinline__ float4 gather_geom(const TraceArgs& a, const LevelGeom& g) {
     const float wx0 = 1.0f - g.wx, wy0 = 1.0f - g.wy, wz0 = 1.0f - g.wz;
     const float wxy[4] = {wx0 * wy0, g.wx * wy0, wx0 * g.wy, g.wx * g.wy};
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const uint32_t idx = g.base + ((q & 1) ? g.dx : 0u) + ((q & 2) ? g.dy : 0u) + ((q & 4) ? g.dz : 0u);
-        const float w = wxy[q & 3] * ((q & 4) ? g.wz : wz0);
-        float4 v = vct_fetch_texel<DT>(rsrc, idx);
-        s.x = __builtin_fmaf(w, v.x, s.x);
-        s.y = __builtin_fmaf(w, v.y, s.y);
-        s.z = __builtin_fmaf(w, v.z, s.z);
-        s.w = __builtin_fmaf(w, v.w, s.w);
+        acc_tap(s, wxy[q & 3] * ((q & 4) ? g.wz : wz0), vct_fetch_texel<DT>(a.rsrc, idx));
     }
     return s;
 }
@@ -339,7 +338,7 @@ __device__ __forceinline__ float4 gather_geom(const vct_v4i& rsrc, const LevelGe
 template <int DT>
 __device__ __forceinline__ float4 gather_geom_aniso(const TraceArgs& a, const DirTable* D, const Cone& c,
                                                     const LevelGeom& g) {
-    if (g.level == 0) return gather_geom<DT>(a.rsrc, g);
+    if (g.level == 0) return gather_geom<DT>(a, g);
     const float W[3] = {c.Wx, c.Wy, c.Wz};
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
@@ -348,7 +347,7 @@ __device__ __forceinline__ float4 gather_geom_aniso(const TraceArgs& a, const Di
         if (wt == 0.0f) continue;
         LevelGeom gd = g;
         gd.base += D->delta[2 * ax + (W[ax] < 0.0f ? 1 : 0)][g.level];
-        const float4 v = gather_geom<DT>(a.rsrc, gd);
+        const float4 v = gather_geom<DT>(a, gd);
         s.x = __builtin_fmaf(wt, v.x, s.x);
         s.y = __builtin_fmaf(wt, v.y, s.y);
         s.z = __builtin_fmaf(wt, v.z, s.z);
@@ -376,10 +375,10 @@ __device__ __forceinline__ void pass2_step(const TraceArgs& a, const LevelTable&
     const int l0 = (int)lam;
     st.f = lam - (float)l0;
     st.g0 = level_geom(T, l0, Ux, Uy, Uz);
-    float4 s = ANISO ? gather_geom_aniso<DT>(a, D, L.c, st.g0) : gather_geom<DT>(a.rsrc, st.g0);
+    float4 s = ANISO ? gather_geom_aniso<DT>(a, D, L.c, st.g0) : gather_geom<DT>(a, st.g0);
     if (st.f > 0.0f) {
         st.g1 = level_geom(T, min(l0 + 1, a.levels - 1), Ux, Uy, Uz);
-        float4 s1 = ANISO ? gather_geom_aniso<DT>(a, D, L.c, st.g1) : gather_geom<DT>(a.rsrc, st.g1);
+        float4 s1 = ANISO ? gather_geom_aniso<DT>(a, D, L.c, st.g1) : gather_geom<DT>(a, st.g1);
         float gg = 1.0f - st.f;
         s.x = __builtin_fmaf(st.f, s1.x, gg * s.x);
         s.y = __builtin_fmaf(st.f, s1.y, gg * s.y);

@@ -171,16 +171,49 @@ __device__ __forceinline__ void load_dir_table(const TraceArgs& a, DirTable* t) 
             if ((int)threadIdx.x == d * VCT_MAX_LEVELS + l) t->delta[d][l] = a.ddelta[d][l];
 }
 
+// s += w * v on the four channels (the accumulation step of every gather).
+__device__ __forceinline__ void acc_tap(float4& s, float w, float4 v) {
+    s.x = __builtin_fmaf(w, v.x, s.x);
+    s.y = __builtin_fmaf(w, v.y, s.y);
+    s.z = __builtin_fmaf(w, v.z, s.z);
+    s.w = __builtin_fmaf(w, v.w, s.w);
+}
+
 template <int DT>
-__device__ __forceinline__ float4 gather(const vct_v4i& rsrc, const Taps& tp) {
+__device__ __forceinline__ float4 gather(const TraceArgs& a, const Taps& tp) {
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (DT == VCT_F16 || DT == VCT_BF16) {
+        // 8-byte texels: the two x taps of a (y, z) row are the neighbouring
+        // texels idx and idx + 1 unless the pair crosses a brick (x0 = 3 mod
+        // 4) or x clamps (one texel twice), so one 16-byte load fetches both;
+        // lanes of those two kinds (the clamp only at the grid's edge) load
+        // the second texel on their own, over the upper half of the pair.
+        // (Texture-address requests per level: 4 plus those lanes' instead of
+        // 8.)  Taps are accumulated in the order 0..7 of the other paths.
+        const bool apart = tp.idx[1] - tp.idx[0] != 1u;
+        vct_v4i pr[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        float4 v = vct_fetch_texel<DT>(rsrc, tp.idx[q]);
-        s.x = __builtin_fmaf(tp.w[q], v.x, s.x);
-        s.y = __builtin_fmaf(tp.w[q], v.y, s.y);
-        s.z = __builtin_fmaf(tp.w[q], v.z, s.z);
-        s.w = __builtin_fmaf(tp.w[q], v.w, s.w);
+        for (int p = 0; p < 4; ++p) {
+            VCT_CHECK_TEXEL(tp.idx[2 * p]);
+            pr[p] = vct_raw_load_v4i32(a.rraw, (int32_t)(tp.idx[2 * p] * 8u), 0, 0);
+        }
+        if (apart) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                VCT_CHECK_TEXEL(tp.idx[2 * p + 1]);
+                const vct_v2i u = vct_raw_load_v2i32(a.rraw, (int32_t)(tp.idx[2 * p + 1] * 8u), 0, 0);
+                pr[p].z = u.x;
+                pr[p].w = u.y;
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            acc_tap(s, tp.w[2 * p], vct_decode_texel<DT>((uint32_t)pr[p].x, (uint32_t)pr[p].y));
+            acc_tap(s, tp.w[2 * p + 1], vct_decode_texel<DT>((uint32_t)pr[p].z, (uint32_t)pr[p].w));
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc_tap(s, tp.w[q], vct_fetch_texel<DT>(a.rsrc, tp.idx[q]));
     }
     return s;
 }
@@ -321,7 +354,7 @@ __device__ __forceinline__ float4 level_sample(const TraceArgs& a, const LevelTa
                 Taps td = tp;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) td.idx[q] += delta;
-                const float4 g = gather<DT>(a.rsrc, td);
+                const float4 g = gather<DT>(a, td);
                 s.x = __builtin_fmaf(wt, g.x, s.x);
                 s.y = __builtin_fmaf(wt, g.y, s.y);
                 s.z = __builtin_fmaf(wt, g.z, s.z);
@@ -330,7 +363,7 @@ __device__ __forceinline__ float4 level_sample(const TraceArgs& a, const LevelTa
             return s;
         }
     }
-    return gather<DT>(a.rsrc, tp);
+    return gather<DT>(a, tp);
 }
 
 // Quadrilinear sample at distance t along the cone.

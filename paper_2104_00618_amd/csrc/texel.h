@@ -26,7 +26,25 @@ inline vct_v4i vct_pyr_rsrc(const void* pyr, int texel_bytes, uint32_t n_texels)
     return r;
 }
 
+// Raw (byte-offset) resource over the same pyramid, for loads that span two
+// neighbouring 8-byte texels: stride 0, `bytes` records of one byte (at most
+// 2^32 - 1; dwords past it read as zero).
+inline vct_v4i vct_pyr_raw_rsrc(const void* pyr, uint64_t bytes) {
+    const uint64_t base = (uint64_t)(uintptr_t)pyr;
+    vct_v4i r;
+    r.x = (int32_t)(uint32_t)base;
+    r.y = (int32_t)((uint32_t)(base >> 32) & 0xffffu);
+    r.z = (int32_t)(uint32_t)(bytes > 0xffffffffull ? 0xffffffffull : bytes);
+    r.w = 0x00020000;
+    return r;
+}
+
 #ifndef VCT_HOST_EMULATION
+// buffer_load_dwordx4 / _dwordx2 with offen (voffset = byte offset)
+__device__ vct_v4i vct_raw_load_v4i32(vct_v4i rsrc, int32_t voffset, int32_t soffset,
+                                      int32_t aux) __asm("llvm.amdgcn.raw.buffer.load.v4i32");
+__device__ vct_v2i vct_raw_load_v2i32(vct_v4i rsrc, int32_t voffset, int32_t soffset,
+                                      int32_t aux) __asm("llvm.amdgcn.raw.buffer.load.v2i32");
 // buffer_load_dwordx4 / _dwordx2 with idxen (vindex = record index)
 __device__ vct_v4f vct_struct_load_v4f32(vct_v4i rsrc, int32_t vindex, int32_t voffset, int32_t soffset,
                                          int32_t aux) __asm("llvm.amdgcn.struct.buffer.load.v4f32");
@@ -34,9 +52,26 @@ __device__ vct_v2i vct_struct_load_v2i32(vct_v4i rsrc, int32_t vindex, int32_t v
                                          int32_t aux) __asm("llvm.amdgcn.struct.buffer.load.v2i32");
 #else
 // host-side verification builds supply these
+vct_v4i vct_raw_load_v4i32(vct_v4i rsrc, int32_t voffset, int32_t soffset, int32_t aux);
+vct_v2i vct_raw_load_v2i32(vct_v4i rsrc, int32_t voffset, int32_t soffset, int32_t aux);
 vct_v4f vct_struct_load_v4f32(vct_v4i rsrc, int32_t vindex, int32_t voffset, int32_t soffset, int32_t aux);
 vct_v2i vct_struct_load_v2i32(vct_v4i rsrc, int32_t vindex, int32_t voffset, int32_t soffset, int32_t aux);
 #endif
+
+// float16 / bfloat16 texel from its two 32-bit words (the decode of vct_fetch_texel).
+template <int DT>
+__device__ __forceinline__ float4 vct_decode_texel(uint32_t x, uint32_t y) {
+    if constexpr (DT == VCT_F16) {
+        vct_v2i u;
+        u.x = (int32_t)x;
+        u.y = (int32_t)y;
+        const vct_half4 h = __builtin_bit_cast(vct_half4, u);
+        return make_float4((float)h.x, (float)h.y, (float)h.z, (float)h.w);
+    } else {
+        return make_float4(__uint_as_float(x << 16), __uint_as_float(x & 0xffff0000u), __uint_as_float(y << 16),
+                           __uint_as_float(y & 0xffff0000u));
+    }
+}
 
 // Index hook for host-side verification builds (empty in the library).
 #ifndef VCT_CHECK_TEXEL

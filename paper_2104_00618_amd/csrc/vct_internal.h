@@ -119,6 +119,7 @@ struct TraceArgs {
     LevelInfo lv[VCT_MAX_LEVELS];
     const void* pyr;
     vct_v4i rsrc;                  // structured buffer resource over pyr (one record per texel)
+    vct_v4i rraw;                  // raw (byte-offset) resource over pyr (paired float16 / bfloat16 loads)
     uint32_t ddelta[6][VCT_MAX_LEVELS];   // anisotropic: texel offset of direction d's level l minus lv[l].off
     float inv_scale2;              // (extent / N)^2: unit-axis weights w_a^2 = W_a^2 * inv_scale2
     int32_t aniso;                 // six directional pyramids (levels >= 1)
