@@ -189,7 +189,7 @@ __global__ __launch_bounds__(1024) void k_gather(TraceArgs a, BounceArgs b) {
                 const float x = (float)(v & mask), y = (float)((v >> b.lg) & mask), z = (float)(v >> (2 * b.lg));
                 set_origin(a, P, df{x + 0.5f, 0.0f}, df{y + 0.5f, 0.0f}, df{z + 0.5f, 0.0f});
                 const Cone c = cone_for_slot(a, P, q, make_float3(0.f, 0.f, 0.f));   // diffuse: no camera
-                const MarchResult m = march<DT, ANISO>(a, T, c, dir_ptr(D));
+                const MarchResult m = march<DT, ANISO, kShareFootprint<DT>>(a, T, c, dir_ptr(D));
                 r = m.r;
                 g = m.g;
                 bl = m.b;

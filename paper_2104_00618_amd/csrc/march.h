@@ -179,9 +179,49 @@ __device__ __forceinline__ void acc_tap(float4& s, float w, float4 v) {
     s.w = __builtin_fmaf(w, v.w, s.w);
 }
 
+// Storage types whose forward marches (trace, shading, bounce) take SHARE
+// below: float32.  float16 / bfloat16 marches already halve their requests
+// with paired loads, and there the check and the registers it holds cost
+// more than the loads it saves.
 template <int DT>
+constexpr bool kShareFootprint = (DT & ~VCT_WIDE) == VCT_F32;
+
+// SHARE: when every active lane of the wave samples the same 8 texels (same
+// level, base texel and clamp pattern, as the lanes of a wave usually do on
+// the coarse levels), the texel addresses are wave-uniform, so the 8 texels
+// are read once with scalar loads and every lane's FMAs take them from scalar
+// registers, instead of every lane issuing texture-address requests (which
+// bound these marches).  Same texels, same accumulation order, so the same
+// sample bits.  (Pyramids above 4 GiB, whose byte offsets do not fit the
+// scalar load's 32-bit offset, keep the vector loads.)
+template <int DT, bool SHARE = false>
 __device__ __forceinline__ float4 gather(const TraceArgs& a, const Taps& tp) {
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (SHARE && (DT & VCT_WIDE) == 0) {
+        const uint32_t i0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)tp.idx[0]);
+        const int c0 = __builtin_amdgcn_readfirstlane(tp.clamp);
+        if (__ballot(tp.idx[0] != i0 || tp.clamp != c0) == 0) {
+            // (the steps to the +x / +y / +z taps follow from the base texel and
+            // the clamp pattern, so they are wave-uniform too)
+            const uint32_t d1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tp.idx[1] - tp.idx[0]));
+            const uint32_t d2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tp.idx[2] - tp.idx[0]));
+            const uint32_t d4 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tp.idx[4] - tp.idx[0]));
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t idx = i0 + ((q & 1) ? d1 : 0u) + ((q & 2) ? d2 : 0u) + ((q & 4) ? d4 : 0u);
+                VCT_CHECK_TEXEL(idx);
+                if constexpr (DT == VCT_F32) {
+                    const vct_v4i v = vct_scalar_load_v4i32(a.rraw, (int32_t)(idx * 16u), 0);
+                    acc_tap(s, tp.w[q], make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z),
+                                                    __int_as_float(v.w)));
+                } else {
+                    const vct_v2i v = vct_scalar_load_v2i32(a.rraw, (int32_t)(idx * 8u), 0);
+                    acc_tap(s, tp.w[q], vct_decode_texel<DT>((uint32_t)v.x, (uint32_t)v.y));
+                }
+            }
+            return s;
+        }
+    }
     if constexpr (DT == VCT_F16 || DT == VCT_BF16) {
         // 8-byte texels: the two x taps of a (y, z) row are the neighbouring
         // texels idx and idx + 1 unless the pair crosses a brick (x0 = 3 mod
@@ -337,7 +377,7 @@ __device__ __forceinline__ Cone cone_for_slot(const TraceArgs& a, const PixelSet
 // over the three axes of w_a^2 times the sample of the direction sign(w_a)
 // (the taps are the same in every direction, only the level's offset moves);
 // axes with w_a = 0 are skipped.
-template <int DT, bool ANISO>
+template <int DT, bool ANISO, bool SHARE = false>
 __device__ __forceinline__ float4 level_sample(const TraceArgs& a, const LevelTable& T, const DirTable* D,
                                                const Cone& c, int l, df Ux, df Uy, df Uz) {
     Taps tp;
@@ -354,7 +394,7 @@ __device__ __forceinline__ float4 level_sample(const TraceArgs& a, const LevelTa
                 Taps td = tp;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) td.idx[q] += delta;
-                const float4 g = gather<DT>(a, td);
+                const float4 g = gather<DT, SHARE>(a, td);
                 s.x = __builtin_fmaf(wt, g.x, s.x);
                 s.y = __builtin_fmaf(wt, g.y, s.y);
                 s.z = __builtin_fmaf(wt, g.z, s.z);
@@ -363,11 +403,11 @@ __device__ __forceinline__ float4 level_sample(const TraceArgs& a, const LevelTa
             return s;
         }
     }
-    return gather<DT>(a, tp);
+    return gather<DT, SHARE>(a, tp);
 }
 
-// Quadrilinear sample at distance t along the cone.
-template <int DT, bool ANISO = false>
+// Quadrilinear sample at distance t along the cone (SHARE: see gather).
+template <int DT, bool ANISO = false, bool SHARE = false>
 __device__ __forceinline__ float4 sample_at(const TraceArgs& a, const LevelTable& T, const Cone& c, df t,
                                             float lam, const DirTable* D = nullptr) {
     df Ux = df_axis(c.Ox, t, c.Wx);
@@ -375,10 +415,10 @@ __device__ __forceinline__ float4 sample_at(const TraceArgs& a, const LevelTable
     df Uz = df_axis(c.Oz, t, c.Wz);
     int l0 = (int)lam;
     float f = lam - (float)l0;
-    float4 s0 = level_sample<DT, ANISO>(a, T, D, c, l0, Ux, Uy, Uz);
+    float4 s0 = level_sample<DT, ANISO, SHARE>(a, T, D, c, l0, Ux, Uy, Uz);
     if (f > 0.0f) {
         int l1 = min(l0 + 1, a.levels - 1);
-        float4 s1 = level_sample<DT, ANISO>(a, T, D, c, l1, Ux, Uy, Uz);
+        float4 s1 = level_sample<DT, ANISO, SHARE>(a, T, D, c, l1, Ux, Uy, Uz);
         float g = 1.0f - f;
         s0.x = __builtin_fmaf(f, s1.x, g * s0.x);
         s0.y = __builtin_fmaf(f, s1.y, g * s0.y);
@@ -399,7 +439,7 @@ struct MarchResult {
 
 // Forward march of one cone (Section 4.3.2): sample while t <= t_max and
 // A < alpha_thresh; C += (1 - A) s.rgb, A += (1 - A) s.a, t += beta d.
-template <int DT, bool ANISO = false>
+template <int DT, bool ANISO = false, bool SHARE = false>
 __device__ __forceinline__ MarchResult march(const TraceArgs& a, const LevelTable& T, const Cone& c,
                                              const DirTable* D = nullptr) {
     MarchResult m = {0.f, 0.f, 0.f, 0.f, 0};
@@ -408,7 +448,7 @@ __device__ __forceinline__ MarchResult march(const TraceArgs& a, const LevelTabl
         if (!t_within(t, c.tmax) || !(m.a < a.alpha_thresh)) break;
         float d = fmaxf(c.two_tan * t.hi, a.voxel);
         float lam = lod_of(a, d);
-        float4 s = sample_at<DT, ANISO>(a, T, c, t, lam, D);
+        float4 s = sample_at<DT, ANISO, SHARE>(a, T, c, t, lam, D);
         float tr = 1.0f - m.a;
         m.r = __builtin_fmaf(tr, s.x, m.r);
         m.g = __builtin_fmaf(tr, s.y, m.g);
@@ -436,7 +476,7 @@ __device__ __forceinline__ void trace_pixel(const TraceArgs& a, const LevelTable
     float3 cam = make_float3(a.cam_pos[3 * view], a.cam_pos[3 * view + 1], a.cam_pos[3 * view + 2]);
     for (int q = 0; q < a.n_diffuse; ++q) {
         Cone c = cone_for_slot(a, P, q, cam);
-        MarchResult m = march<DT, ANISO>(a, T, c, D);
+        MarchResult m = march<DT, ANISO, kShareFootprint<DT>>(a, T, c, D);
         float wq = a.weight[q];
         o0.x = __builtin_fmaf(wq, m.r, o0.x);
         o0.y = __builtin_fmaf(wq, m.g, o0.y);
@@ -446,7 +486,7 @@ __device__ __forceinline__ void trace_pixel(const TraceArgs& a, const LevelTable
     }
     if (a.enable_spec) {
         Cone c = cone_for_slot(a, P, a.n_diffuse, cam);
-        MarchResult m = march<DT, ANISO>(a, T, c, D);
+        MarchResult m = march<DT, ANISO, kShareFootprint<DT>>(a, T, c, D);
         o1.x = m.r;
         o1.y = m.g;
         o1.z = m.b;
@@ -454,7 +494,7 @@ __device__ __forceinline__ void trace_pixel(const TraceArgs& a, const LevelTable
     }
     if (a.enable_occ) {
         Cone c = cone_for_slot(a, P, a.n_diffuse + 1, cam);
-        MarchResult m = march<DT, ANISO>(a, T, c, D);
+        MarchResult m = march<DT, ANISO, kShareFootprint<DT>>(a, T, c, D);
         o1.w = m.a;
         ksum += m.k;
     }

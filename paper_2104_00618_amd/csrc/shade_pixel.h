@@ -30,7 +30,7 @@ __device__ __forceinline__ float3 march_first_hit(const TraceArgs& a, const Leve
     for (int k = 0; k < a.max_steps; ++k) {
         if (!t_within(t, c.tmax)) break;
         const float d = fmaxf(c.two_tan * t.hi, a.voxel);
-        const float4 s = sample_at<DT, ANISO>(a, T, c, t, lod_of(a, d), dirs);
+        const float4 s = sample_at<DT, ANISO, kShareFootprint<DT>>(a, T, c, t, lod_of(a, d), dirs);
         ++n;
         if (s.w > thresh) {
             rgb = make_float3(s.x, s.y, s.z);
@@ -53,7 +53,7 @@ __device__ __forceinline__ float march_falloff(const TraceArgs& a, const LevelTa
     for (int k = 0; k < a.max_steps; ++k) {
         if (!t_within(t, c.tmax) || !(A < a.alpha_thresh)) break;
         const float d = fmaxf(c.two_tan * t.hi, a.voxel);
-        const float4 s = sample_at<DT, ANISO>(a, T, c, t, lod_of(a, d), dirs);
+        const float4 s = sample_at<DT, ANISO, kShareFootprint<DT>>(a, T, c, t, lod_of(a, d), dirs);
         ++n;
         const float h = fminf(fmaxf(sqrtf(t.hi) * strength * inv, 0.0f), 1.0f);
         A = __builtin_fmaf(1.0f - A, s.w * (h * h * (3.0f - 2.0f * h)), A);
@@ -90,7 +90,7 @@ __device__ __forceinline__ float4 shade_pixel(const TraceArgs& a, const LevelTab
         if (s.first_hit) {
             col = march_first_hit<DT, ANISO>(a, T, dirs, c, s.first_hit_alpha, n);
         } else {
-            const MarchResult m = march<DT, ANISO>(a, T, c, dirs);
+            const MarchResult m = march<DT, ANISO, kShareFootprint<DT>>(a, T, c, dirs);
             col = make_float3(m.r, m.g, m.b);
             n += (unsigned int)m.k;
         }
@@ -100,7 +100,7 @@ __device__ __forceinline__ float4 shade_pixel(const TraceArgs& a, const LevelTab
         D.z = __builtin_fmaf(wq, col.z, D.z);
     }
     // indirect specular: one trace along the reflection axis
-    const MarchResult ms = march<DT, ANISO>(a, T, cone_for_slot(a, P, a.n_diffuse, cam), dirs);
+    const MarchResult ms = march<DT, ANISO, kShareFootprint<DT>>(a, T, cone_for_slot(a, P, a.n_diffuse, cam), dirs);
     n += (unsigned int)ms.k;
     // unit reflection axis (as in the specular cone) and view direction
     const float3 v = normalize3(P.px - cam.x, P.py - cam.y, P.pz - cam.z);
@@ -117,7 +117,7 @@ __device__ __forceinline__ float4 shade_pixel(const TraceArgs& a, const LevelTab
         if (s.falloff) {
             A = march_falloff<DT, ANISO>(a, T, dirs, co, s.shadow_strength, n);
         } else {
-            const MarchResult mo = march<DT, ANISO>(a, T, co, dirs);
+            const MarchResult mo = march<DT, ANISO, kShareFootprint<DT>>(a, T, co, dirs);
             A = mo.a;
             n += (unsigned int)mo.k;
         }
