@@ -236,15 +236,62 @@ __device__ __forceinline__ void emit_weights(const LevelGeom& g, float wl, const
     for (int k = 0; k < 8; ++k) wp[k] = wl * (wxy[k & 3] * ((k >> 2) ? zb : za));
 }
 
+// A group's fixed-point values held back while the wave's next samples on the
+// same level parity fall on the same footprint (same base texel and clamp
+// pattern): they are summed in registers and added to the accumulator once.
+// Integer addition is associative, so the accumulator ends bitwise the same
+// as with one atomic per sample.  The key and the index steps are
+// wave-uniform; qv is the lane's value (zero outside the emitting lanes).
+struct Held {
+    uint32_t key;          // base texel, kNoKey when empty
+    int kc;                // clamp pattern
+    uint32_t dx, dy, dz;   // index steps of the footprint
+    long long qv;
+};
+constexpr uint32_t kNoKey = 0xffffffffu;
+
+// Add a lane's value for texel idx, channel ch to the workgroup's LDS table
+// (coarse levels) or to the global accumulator.
+__device__ __forceinline__ void add_fixed(uint32_t idx, int ch, long long qv, unsigned long long* __restrict__ acc,
+                                          unsigned long long* small, uint32_t small_off) {
+    VCT_CHECK_ACC(idx);
+    if (qv != 0 && idx >= small_off) atomicAdd(&small[(idx - small_off) * 4 + ch], (unsigned long long)qv);
+    if (qv != 0 && idx < small_off) atomicAdd(&acc[(size_t)idx * 4 + ch], (unsigned long long)qv);
+}
+
+__device__ __forceinline__ void flush_held(Held& h, const EmitLane& e, int ch, unsigned long long* __restrict__ acc,
+                                           unsigned long long* small, uint32_t small_off) {
+    if (h.key != kNoKey)
+        add_fixed(h.key + (h.dx & e.xm) + (h.dy & e.ym) + (h.dz & e.zm), ch, h.qv, acc, small, small_off);
+    h.key = kNoKey;
+}
+
+__device__ __forceinline__ void hold(Held& h, uint32_t k, int kc, uint32_t dx, uint32_t dy, uint32_t dz, long long qv,
+                                     const EmitLane& e, int ch, unsigned long long* __restrict__ acc,
+                                     unsigned long long* small, uint32_t small_off) {
+    if (h.key == k && h.kc == kc) {
+        h.qv += qv;
+        return;
+    }
+    flush_held(h, e, ch, acc, small, small_off);
+    h.key = k;
+    h.kc = kc;
+    h.dx = dx;
+    h.dy = dy;
+    h.dz = dz;
+    h.qv = qv;
+}
+
 // Emit one level's tap gradients of the wave.  Lanes whose samples share the
 // same base texel and clamp pattern have the same 8 taps; each such group is
 // summed across the wave (fixed order) and 32 lanes (8 for alpha only) then
 // add its taps x channels as fixed-point integers: to the workgroup's LDS
 // table for the coarse levels (side <= 8), to the global accumulator otherwise.
-template <bool ALPHA_ONLY>
+template <bool ALPHA_ONLY, bool HOLD = false>
 __device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, float wl, const float gs[4],
-                                           const EmitLane& e, int E, int lev_shift, unsigned long long* __restrict__ acc,
-                                           unsigned long long* small, uint32_t small_off, int lane) {
+                                           const EmitLane& e, int E, int lev_shift,
+                                           unsigned long long* __restrict__ acc, unsigned long long* small,
+                                           uint32_t small_off, int lane, Held* held = nullptr) {
     unsigned long long mask = __ballot(live);
     if (mask == 0) return;   // (wave-uniform: no lane emits on this level)
     float wp[8];
@@ -275,11 +322,17 @@ __device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, floa
         const uint32_t dx = (uint32_t)__builtin_amdgcn_readlane((int)geo.dx, leader);
         const uint32_t dy = (uint32_t)__builtin_amdgcn_readlane((int)geo.dy, leader);
         const uint32_t dz = (uint32_t)__builtin_amdgcn_readlane((int)geo.dz, leader);
-        const uint32_t idx = k + (dx & e.xm) + (dy & e.ym) + (dz & e.zm);
         const long long qv = emitter ? fixed_point(sum, E - lev_shift * lev) : 0;
-        VCT_CHECK_ACC(idx);
-        if (qv != 0 && idx >= small_off) atomicAdd(&small[(idx - small_off) * 4 + ch], (unsigned long long)qv);
-        if (qv != 0 && idx < small_off) atomicAdd(&acc[(size_t)idx * 4 + ch], (unsigned long long)qv);
+        if constexpr (HOLD) {
+            // (the two levels of a sample differ in parity, and a level keeps
+            // its parity stream as the march moves up)
+            if (lev & 1)
+                hold(held[1], k, kc, dx, dy, dz, qv, e, ch, acc, small, small_off);
+            else
+                hold(held[0], k, kc, dx, dy, dz, qv, e, ch, acc, small, small_off);
+        } else {
+            add_fixed(k + (dx & e.xm) + (dy & e.ym) + (dz & e.zm), ch, qv, acc, small, small_off);
+        }
         mask &= ~gm;
     }
 }
@@ -290,13 +343,13 @@ __device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, floa
 // fixed factor); above level 0 the sample read the three directions of its
 // axis signs with weights w_a^2, so each gets the gradient with that weight at
 // its direction's offset (a separate group key, since the base index moves).
-template <bool ALPHA_ONLY, bool ANISO>
+template <bool ALPHA_ONLY, bool ANISO, bool HOLD>
 __device__ __forceinline__ void emit_dirs(const TraceArgs& a, const DirTable* D, const Cone& c, bool live,
                                           const LevelGeom& geo, float wl, const float gs[4], const EmitLane& e, int E,
                                           unsigned long long* __restrict__ acc, unsigned long long* small,
-                                          uint32_t small_off, int lane) {
+                                          uint32_t small_off, int lane, Held* held) {
     if constexpr (!ANISO) {
-        emit_level<ALPHA_ONLY>(live, geo, wl, gs, e, E, 3, acc, small, small_off, lane);
+        emit_level<ALPHA_ONLY, HOLD>(live, geo, wl, gs, e, E, 3, acc, small, small_off, lane, held);
     } else {
         const bool base_level = live && geo.level == 0;
         emit_level<ALPHA_ONLY>(base_level, geo, wl, gs, e, E, 0, acc, small, small_off, lane);
@@ -356,7 +409,18 @@ __global__ __launch_bounds__(kThreads, 4) void k_bwd_pass2(TraceArgs a, const fl
         int Kw = L.K;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) Kw = max(Kw, __shfl_xor(Kw, o));
+        Kw = __builtin_amdgcn_readfirstlane(Kw);   // (equal in every lane: the loop is wave-uniform)
         const bool occ = slot == a.n_diffuse + 1;
+        // Held emissions (isotropic float16 / bfloat16 pyramids): the scatter
+        // pass ran 7.04 -> 6.31 ms with them.  The float32 kernel, whose
+        // gather holds twice the texel registers, ran 7.14 -> 8.08 ms, so it
+        // adds every group at once.
+        constexpr bool kHold = !ANISO && (DT & ~VCT_WIDE) != VCT_F32;
+        Held held[2];
+        held[0].key = held[1].key = kNoKey;
+        held[0].kc = held[1].kc = 0;
+        held[0].dx = held[0].dy = held[0].dz = held[1].dx = held[1].dy = held[1].dz = 0u;
+        held[0].qv = held[1].qv = 0;
         for (int k = 0; k < Kw; ++k) {
             const bool live = k < L.K;
             // lanes past their K only need finite weights for the butterfly
@@ -367,20 +431,25 @@ __global__ __launch_bounds__(kThreads, 4) void k_bwd_pass2(TraceArgs a, const fl
             if constexpr (ANISO) st.g0.level = st.g1.level = 0;   // (a dead lane's direction-table row)
             if (live) pass2_step<DT, ANISO>(a, T, L, k, st, dir_ptr(D));
             if (occ) {
-                emit_dirs<true, ANISO>(a, dir_ptr(D), L.c, live, st.g0, 1.0f - st.f, st.g, e, E, acc, s_small,
-                                       small_off, lane);
-                emit_dirs<true, ANISO>(a, dir_ptr(D), L.c, live && st.f > 0.0f, st.g1, st.f, st.g, e, E, acc, s_small,
-                                       small_off, lane);
+                emit_dirs<true, ANISO, kHold>(a, dir_ptr(D), L.c, live, st.g0, 1.0f - st.f, st.g, e, E, acc,
+                                              s_small, small_off, lane, held);
+                emit_dirs<true, ANISO, kHold>(a, dir_ptr(D), L.c, live && st.f > 0.0f, st.g1, st.f, st.g, e, E,
+                                              acc, s_small, small_off, lane, held);
             } else {
                 // gradient in the lane's slot order (channel bit 1 flipped where cf);
                 // selects on values: an index select would move st to scratch memory
                 const float g0 = st.g[0], g1 = st.g[1], g2 = st.g[2], g3 = st.g[3];
                 const float gs[4] = {e.cf ? g2 : g0, e.cf ? g3 : g1, e.cf ? g0 : g2, e.cf ? g1 : g3};
-                emit_dirs<false, ANISO>(a, dir_ptr(D), L.c, live, st.g0, 1.0f - st.f, gs, e, E, acc, s_small,
-                                        small_off, lane);
-                emit_dirs<false, ANISO>(a, dir_ptr(D), L.c, live && st.f > 0.0f, st.g1, st.f, gs, e, E, acc,
-                                        s_small, small_off, lane);
+                emit_dirs<false, ANISO, kHold>(a, dir_ptr(D), L.c, live, st.g0, 1.0f - st.f, gs, e, E, acc,
+                                               s_small, small_off, lane, held);
+                emit_dirs<false, ANISO, kHold>(a, dir_ptr(D), L.c, live && st.f > 0.0f, st.g1, st.f, gs, e, E,
+                                               acc, s_small, small_off, lane, held);
             }
+        }
+        if constexpr (kHold) {
+            // (the occlusion cone's values are all channel 3)
+            flush_held(held[0], e, occ ? 3 : e.ch, acc, s_small, small_off);
+            flush_held(held[1], e, occ ? 3 : e.ch, acc, s_small, small_off);
         }
     }
     __syncthreads();

@@ -53,8 +53,10 @@ __device__ vct_v2i vct_struct_load_v2i32(vct_v4i rsrc, int32_t vindex, int32_t v
 // s_buffer_load_dwordx4 / _dwordx2 (byte offset): a read whose resource and
 // offset are the same in every lane of the wave, through the scalar data
 // cache into scalar registers; dwords past the resource's range read as zero.
-__device__ vct_v4i vct_scalar_load_v4i32(vct_v4i rsrc, int32_t offset, int32_t aux) __asm("llvm.amdgcn.s.buffer.load.v4i32");
-__device__ vct_v2i vct_scalar_load_v2i32(vct_v4i rsrc, int32_t offset, int32_t aux) __asm("llvm.amdgcn.s.buffer.load.v2i32");
+__device__ vct_v4i vct_scalar_load_v4i32(vct_v4i rsrc, int32_t offset,
+                                         int32_t aux) __asm("llvm.amdgcn.s.buffer.load.v4i32");
+__device__ vct_v2i vct_scalar_load_v2i32(vct_v4i rsrc, int32_t offset,
+                                         int32_t aux) __asm("llvm.amdgcn.s.buffer.load.v2i32");
 #else
 // host-side verification builds supply these
 vct_v4i vct_raw_load_v4i32(vct_v4i rsrc, int32_t voffset, int32_t soffset, int32_t aux);
