@@ -417,11 +417,21 @@ def main():
         torch.cuda.synchronize()
         m16 = e[0].elapsed_time(e[1]) / args.steps
         f16 = e[1].elapsed_time(e[2]) / args.steps
+        # the training step on the float16 pyramid (same lane-state buffer and gradient)
+        ws16 = torch.empty(vct.backward_workspace_bytes(g16, pr, nr, cam, w.params) - st_bytes, dtype=torch.uint8,
+                           device=dev)
+        save16 = timed(lambda: vct.trace_save(p16, g16, pr, nr, cam, w.params, o16, state), args.steps)
+        bwd16 = timed(lambda: vct.trace_backward_saved(p16, g16, pr, nr, cam, w.params, state, gout, ws16, gbase),
+                      args.steps)
+        step16 = m16 + save16 + bwd16
         breakdown["f16_storage"] = {
             "build_mips_ms": m16, "trace_ms": f16, "samples_per_frame": s16,
             "trace_speedup_vs_f32": fwd_ms / f16, "fwd_speedup_vs_f32": (mips_ms + fwd_ms) / (m16 + f16),
-            "trace_logical_GBps": (s16 * 128 + npix * 64) / (f16 * 1e-3) / 1e9}
-        log(f"f16 storage: mips {m16:.3f} ms, trace {f16:.3f} ms ({fwd_ms / f16:.2f}x vs f32)")
+            "trace_logical_GBps": (s16 * 128 + npix * 64) / (f16 * 1e-3) / 1e9,
+            "trace_save_ms": save16, "trace_backward_saved_ms": bwd16, "fwd_bwd_ms_per_frame": step16,
+            "fwd_bwd_speedup_vs_f32": breakdown["fwd_bwd_ms_per_frame"] / step16}
+        log(f"f16 storage: mips {m16:.3f} ms, trace {f16:.3f} ms ({fwd_ms / f16:.2f}x vs f32); training step "
+            f"{step16:.3f} ms ({breakdown['fwd_bwd_ms_per_frame'] / step16:.2f}x vs f32)")
 
     # dominant kernel of the step: the backward scatter pass (issue-bound VALU work)
     p2_ms = float(bwd_k[3])

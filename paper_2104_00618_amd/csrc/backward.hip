@@ -411,11 +411,9 @@ __global__ __launch_bounds__(kThreads, 4) void k_bwd_pass2(TraceArgs a, const fl
         for (int o = 32; o > 0; o >>= 1) Kw = max(Kw, __shfl_xor(Kw, o));
         Kw = __builtin_amdgcn_readfirstlane(Kw);   // (equal in every lane: the loop is wave-uniform)
         const bool occ = slot == a.n_diffuse + 1;
-        // Held emissions (isotropic float16 / bfloat16 pyramids): the scatter
-        // pass ran 7.04 -> 6.31 ms with them.  The float32 kernel, whose
-        // gather holds twice the texel registers, ran 7.14 -> 8.08 ms, so it
-        // adds every group at once.
-        constexpr bool kHold = !ANISO && (DT & ~VCT_WIDE) != VCT_F32;
+        // Held emissions (isotropic pyramids; the anisotropic ones emit four
+        // interleaved direction keys per level and add every group at once).
+        constexpr bool kHold = !ANISO;
         Held held[2];
         held[0].key = held[1].key = kNoKey;
         held[0].kc = held[1].kc = 0;

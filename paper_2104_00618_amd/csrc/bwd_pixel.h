@@ -319,7 +319,11 @@ __device__ __forceinline__ LevelGeom level_geom(const LevelTable& T, int l, df U
 // bfloat16 loads would save texture-address requests here too, but this pass
 // is bound by VALU issue, and their extra branch made it 2-3 % slower.  The
 // texels and the accumulation order are the same, so the samples are too.)
-template <int DT>
+// SPLIT (float32): taps 4..7 are loaded after taps 0..3 are accumulated, so
+// at most four 16-byte texels are in flight; with the held emissions of the
+// scatter pass the kernel is at its register cap, and the full set of eight
+// made it slower (7.14 -> 8.08 ms, against 6.62 -> 6.09 ms split).
+template <int DT, bool SPLIT = false>
 __device__ __forceinline__ float4 gather_geom(const TraceArgs& a, const LevelGeom& g) {
     const float wx0 = 1.0f - g.wx, wy0 = 1.0f - g.wy, wz0 = 1.0f - g.wz;
     const float wxy[4] = {wx0 * wy0, g.wx * wy0, wx0 * g.wy, g.wx * g.wy};
@@ -328,6 +332,7 @@ __device__ __forceinline__ float4 gather_geom(const TraceArgs& a, const LevelGeo
     for (int q = 0; q < 8; ++q) {
         const uint32_t idx = g.base + ((q & 1) ? g.dx : 0u) + ((q & 2) ? g.dy : 0u) + ((q & 4) ? g.dz : 0u);
         acc_tap(s, wxy[q & 3] * ((q & 4) ? g.wz : wz0), vct_fetch_texel<DT>(a.rsrc, idx));
+        if (SPLIT && (DT & ~VCT_WIDE) == VCT_F32 && q == 3) __builtin_amdgcn_sched_barrier(0);
     }
     return s;
 }
@@ -375,10 +380,10 @@ __device__ __forceinline__ void pass2_step(const TraceArgs& a, const LevelTable&
     const int l0 = (int)lam;
     st.f = lam - (float)l0;
     st.g0 = level_geom(T, l0, Ux, Uy, Uz);
-    float4 s = ANISO ? gather_geom_aniso<DT>(a, D, L.c, st.g0) : gather_geom<DT>(a, st.g0);
+    float4 s = ANISO ? gather_geom_aniso<DT>(a, D, L.c, st.g0) : gather_geom<DT, true>(a, st.g0);
     if (st.f > 0.0f) {
         st.g1 = level_geom(T, min(l0 + 1, a.levels - 1), Ux, Uy, Uz);
-        float4 s1 = ANISO ? gather_geom_aniso<DT>(a, D, L.c, st.g1) : gather_geom<DT>(a, st.g1);
+        float4 s1 = ANISO ? gather_geom_aniso<DT>(a, D, L.c, st.g1) : gather_geom<DT, true>(a, st.g1);
         float gg = 1.0f - st.f;
         s.x = __builtin_fmaf(st.f, s1.x, gg * s.x);
         s.y = __builtin_fmaf(st.f, s1.y, gg * s.y);
