@@ -143,7 +143,9 @@ TraceArgs make_args(const vct_grid* g, const PyrLayout& L, const void* pyr, cons
             a.ddelta[d][l] = l < g->levels ? (uint32_t)(L.doff[d][l] - L.off[l]) : 0u;
     a.inv_scale2 = (float)(((double)g->extent / g->n) * ((double)g->extent / g->n));
     a.aniso = g->anisotropic ? 1 : 0;
-    a.wide = L.total_texels * (int64_t)L.texel_bytes > (int64_t(1) << 32) ? 1 : 0;
+    // (narrow pyramids keep every byte offset below 2^32, within the raw
+    // resource's range of 2^32 - 1 bytes)
+    a.wide = L.total_texels * (int64_t)L.texel_bytes >= (int64_t(1) << 32) ? 1 : 0;
     a.b = gb->b;
     a.h = gb->h;
     a.w = gb->w;
