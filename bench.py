@@ -230,8 +230,8 @@ def bench_bounce(vct, torch, grid, vt, vc, vlights, params, timed, steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path has no multi-GPU "
-              f"implementation in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU "
+              f"implementation", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -47,7 +47,7 @@ extern "C" {
 #define VCT_EINVAL (-1)        /* a shape, size or parameter is out of range, or a pointer is null */
 #define VCT_EWORKSPACE (-2)    /* a caller buffer is smaller than the size query requires */
 #define VCT_EDEVICE (-3)       /* the HIP runtime refused a launch; the message carries its error */
-#define VCT_EUNSUPPORTED (-4)  /* valid request that this build does not implement (kept for ABI
+#define VCT_EUNSUPPORTED (-4)  /* valid request that the library does not implement (kept for ABI
                                   stability; no entry point returns it at present) */
 
 #define VCT_MAX_DIFFUSE 16
