@@ -202,6 +202,14 @@ int vct_trace(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf
 int vct_count_samples(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
                       const vct_cone_params* params, unsigned long long* count, hipStream_t stream);
 
+/* The same count split by the levels a sample reads (Section 4.3.3: linear
+ * blend of the two levels around the LOD): counts[0] = all cone samples,
+ * counts[1] = those whose LOD is fractional, so that they read two levels
+ * (the others read one).  counts: device uint64 [2], overwritten.  Used to
+ * state the arithmetic a march performs.  Errors: those of vct_count_samples. */
+int vct_count_sample_levels(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                            const vct_cone_params* params, unsigned long long* counts, hipStream_t stream);
+
 /* Device workspace bytes needed by vct_trace_backward for these shapes (host only). */
 int vct_backward_workspace_bytes(const vct_grid* grid, const vct_gbuffer* gbuf,
                                  const vct_cone_params* params, size_t* bytes);

@@ -68,6 +68,7 @@ def lib():
         "vct_unpack_level_dir": [P(CGrid), vp, ctypes.c_int32, ctypes.c_int32, vp, vp],
         "vct_trace": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
         "vct_count_samples": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
+        "vct_count_sample_levels": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp],
         "vct_shade": [P(CGrid), vp, P(CGBuffer), vp, P(CConeParams), P(CShadeParams), vp, vp],
         "vct_count_shade_samples": [P(CGrid), vp, P(CGBuffer), vp, P(CConeParams), P(CShadeParams), vp, vp],
         "vct_voxelize_workspace_bytes": [P(CGrid), ctypes.c_int64, ctypes.c_int32, P(sz)],
@@ -467,6 +468,18 @@ def count_samples(pyramid, grid, pos_rough, normal, cam_pos, params):
         _check(lib().vct_count_samples(ctypes.byref(grid.c()), _ptr(pyramid), ctypes.byref(gb),
                                        ctypes.byref(cone_params(params)), _ptr(cnt), _stream(pos_rough.device)))
     return int(cnt.item())
+
+
+def count_sample_levels(pyramid, grid, pos_rough, normal, cam_pos, params):
+    """(all cone samples, samples that read two levels) of the forward march."""
+    gb = _gbuf(pos_rough, normal, cam_pos)
+    cnt = torch.zeros(2, dtype=torch.int64, device=pos_rough.device)
+    with torch.cuda.device(pos_rough.device):
+        _check(lib().vct_count_sample_levels(ctypes.byref(grid.c()), _ptr(pyramid), ctypes.byref(gb),
+                                             ctypes.byref(cone_params(params)), _ptr(cnt),
+                                             _stream(pos_rough.device)))
+    c = cnt.cpu().tolist()
+    return int(c[0]), int(c[1])
 
 
 def backward_workspace_bytes(grid, pos_rough, normal, cam_pos, params):

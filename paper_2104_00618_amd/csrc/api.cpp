@@ -237,8 +237,9 @@ int vct_unpack_level_dir(const vct_grid* grid, const void* pyramid, int32_t leve
 }
 
 static int trace_common(const char* fn, const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
-                        const vct_cone_params* params, float* out, unsigned long long* count, bool counting,
+                        const vct_cone_params* params, float* out, unsigned long long* count, int n_counts,
                         hipStream_t stream) {
+    const bool counting = n_counts > 0;
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
@@ -253,7 +254,7 @@ static int trace_common(const char* fn, const vct_grid* grid, const void* pyrami
         ok();
         return VCT_OK;
     }
-    hipError_t e = vct_launch_trace(a, grid->dtype, out, count, stream, es);
+    hipError_t e = vct_launch_trace(a, grid->dtype, out, counting ? count : nullptr, n_counts, stream, es);
     if (e != hipSuccess) return device_error(fn, e);
     ok();
     return VCT_OK;
@@ -261,12 +262,17 @@ static int trace_common(const char* fn, const vct_grid* grid, const void* pyrami
 
 int vct_trace(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf, const vct_cone_params* params,
               float* out, hipStream_t stream) {
-    return trace_common("vct_trace", grid, pyramid, gbuf, params, out, nullptr, false, stream);
+    return trace_common("vct_trace", grid, pyramid, gbuf, params, out, nullptr, 0, stream);
 }
 
 int vct_count_samples(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
                       const vct_cone_params* params, unsigned long long* count, hipStream_t stream) {
-    return trace_common("vct_count_samples", grid, pyramid, gbuf, params, nullptr, count, true, stream);
+    return trace_common("vct_count_samples", grid, pyramid, gbuf, params, nullptr, count, 1, stream);
+}
+
+int vct_count_sample_levels(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                            const vct_cone_params* params, unsigned long long* counts, hipStream_t stream) {
+    return trace_common("vct_count_sample_levels", grid, pyramid, gbuf, params, nullptr, counts, 2, stream);
 }
 
 static int shade_common(const char* fn, const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,

@@ -84,14 +84,14 @@ struct LevelTable {
     uint32_t off[VCT_MAX_LEVELS];
 };
 
+// (Both table loaders stride over the workgroup, so they fill every entry for
+// any workgroup size; the caller synchronises before the tables are read.)
 __device__ __forceinline__ void load_level_table(const TraceArgs& a, LevelTable* t) {
-#pragma unroll
-    for (int l = 0; l < VCT_MAX_LEVELS; ++l)
-        if ((int)threadIdx.x == l) {
-            t->top[l] = (float)(a.lv[l].n - 1);
-            t->lnb[l] = 31 - __builtin_clz(a.lv[l].nb);
-            t->off[l] = a.lv[l].off;
-        }
+    for (int l = (int)threadIdx.x; l < VCT_MAX_LEVELS; l += (int)blockDim.x) {
+        t->top[l] = (float)(a.lv[l].n - 1);
+        t->lnb[l] = 31 - __builtin_clz(a.lv[l].nb);
+        t->off[l] = a.lv[l].off;
+    }
 }
 
 // Texel-space coordinate split into base tap and fraction, for level scale 2^-l.
@@ -164,11 +164,8 @@ __device__ __forceinline__ const DirTable* dir_ptr(const NoDirTable&) { return n
 __device__ __forceinline__ void load_dir_table(const TraceArgs&, NoDirTable*) {}
 
 __device__ __forceinline__ void load_dir_table(const TraceArgs& a, DirTable* t) {
-#pragma unroll
-    for (int d = 0; d < 6; ++d)
-#pragma unroll
-        for (int l = 0; l < VCT_MAX_LEVELS; ++l)
-            if ((int)threadIdx.x == d * VCT_MAX_LEVELS + l) t->delta[d][l] = a.ddelta[d][l];
+    for (int i = (int)threadIdx.x; i < 6 * VCT_MAX_LEVELS; i += (int)blockDim.x)
+        t->delta[i / VCT_MAX_LEVELS][i % VCT_MAX_LEVELS] = a.ddelta[i / VCT_MAX_LEVELS][i % VCT_MAX_LEVELS];
 }
 
 // s += w * v on the four channels (the accumulation step of every gather).
@@ -192,8 +189,11 @@ constexpr bool kShareFootprint = (DT & ~VCT_WIDE) == VCT_F32;
 // are read once with scalar loads and every lane's FMAs take them from scalar
 // registers, instead of every lane issuing texture-address requests (which
 // bound these marches).  Same texels, same accumulation order, so the same
-// sample bits.  (Pyramids above 4 GiB, whose byte offsets do not fit the
-// scalar load's 32-bit offset, keep the vector loads.)
+// sample bits.  The scalar loads go through a copy of the raw resource whose
+// base is moved to the footprint's base texel (wave-uniform 64-bit arithmetic
+// in scalar registers), so each load's offset is the tap's small step inside
+// the level, never a byte offset of 2 GiB or more, whatever the pyramid's size
+// below 4 GiB.  (Pyramids above 4 GiB keep the vector loads.)
 template <int DT, bool SHARE = false>
 __device__ __forceinline__ float4 gather(const TraceArgs& a, const Taps& tp) {
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -206,16 +206,18 @@ __device__ __forceinline__ float4 gather(const TraceArgs& a, const Taps& tp) {
             const uint32_t d1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tp.idx[1] - tp.idx[0]));
             const uint32_t d2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tp.idx[2] - tp.idx[0]));
             const uint32_t d4 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tp.idx[4] - tp.idx[0]));
+            constexpr uint32_t tb = DT == VCT_F32 ? 16u : 8u;
+            const vct_v4i rs = vct_rebase_raw(a.rraw, (uint64_t)i0 * tb);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const uint32_t idx = i0 + ((q & 1) ? d1 : 0u) + ((q & 2) ? d2 : 0u) + ((q & 4) ? d4 : 0u);
-                VCT_CHECK_TEXEL(idx);
+                const uint32_t step = ((q & 1) ? d1 : 0u) + ((q & 2) ? d2 : 0u) + ((q & 4) ? d4 : 0u);
+                VCT_CHECK_TEXEL(i0 + step);
                 if constexpr (DT == VCT_F32) {
-                    const vct_v4i v = vct_scalar_load_v4i32(a.rraw, (int32_t)(idx * 16u), 0);
+                    const vct_v4i v = vct_scalar_load_v4i32(rs, (int32_t)(step * tb), 0);
                     acc_tap(s, tp.w[q], make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z),
                                                     __int_as_float(v.w)));
                 } else {
-                    const vct_v2i v = vct_scalar_load_v2i32(a.rraw, (int32_t)(idx * 8u), 0);
+                    const vct_v2i v = vct_scalar_load_v2i32(rs, (int32_t)(step * tb), 0);
                     acc_tap(s, tp.w[q], vct_decode_texel<DT>((uint32_t)v.x, (uint32_t)v.y));
                 }
             }
@@ -434,7 +436,8 @@ __device__ __forceinline__ bool t_within(df t, float tmax) {
 
 struct MarchResult {
     float r, g, b, a;
-    int k;
+    int k;    // samples taken
+    int k2;   // of those, samples that read two levels (fractional LOD)
 };
 
 // Forward march of one cone (Section 4.3.2): sample while t <= t_max and
@@ -442,7 +445,7 @@ struct MarchResult {
 template <int DT, bool ANISO = false, bool SHARE = false>
 __device__ __forceinline__ MarchResult march(const TraceArgs& a, const LevelTable& T, const Cone& c,
                                              const DirTable* D = nullptr) {
-    MarchResult m = {0.f, 0.f, 0.f, 0.f, 0};
+    MarchResult m = {0.f, 0.f, 0.f, 0.f, 0, 0};
     df t = {a.t0, 0.0f};
     for (int k = 0; k < a.max_steps; ++k) {
         if (!t_within(t, c.tmax) || !(m.a < a.alpha_thresh)) break;
@@ -455,20 +458,23 @@ __device__ __forceinline__ MarchResult march(const TraceArgs& a, const LevelTabl
         m.b = __builtin_fmaf(tr, s.z, m.b);
         m.a = __builtin_fmaf(tr, s.w, m.a);
         m.k = k + 1;
+        m.k2 += lam > (float)(int)lam ? 1 : 0;   // (sample_at reads level l0 + 1 too)
         t = df_add(t, a.step_factor * d);
     }
     return m;
 }
 
 // All cones of one pixel (slots 0..u-1 diffuse, specular, occlusion); the
-// 8-float epilogue (D.rgb, D.a, S.rgb, O) goes to o0, o1, the sample count to k.
+// 8-float epilogue (D.rgb, D.a, S.rgb, O) goes to o0, o1, the sample count to
+// ksum and the count of two-level samples to k2sum.
 template <int DT, bool ANISO = false>
 __device__ __forceinline__ void trace_pixel(const TraceArgs& a, const LevelTable& T, int view, size_t pix,
-                                            float4& o0, float4& o1, unsigned int& ksum,
+                                            float4& o0, float4& o1, unsigned int& ksum, unsigned int& k2sum,
                                             const DirTable* D = nullptr) {
     o0 = make_float4(0.f, 0.f, 0.f, 0.f);
     o1 = o0;
     ksum = 0;
+    k2sum = 0;
     float4 nr = a.normal[pix];
     if (nr.w == 0.0f) return;
     float4 pr = a.pos_rough[pix];
@@ -483,6 +489,7 @@ __device__ __forceinline__ void trace_pixel(const TraceArgs& a, const LevelTable
         o0.z = __builtin_fmaf(wq, m.b, o0.z);
         o0.w = __builtin_fmaf(wq, m.a, o0.w);
         ksum += m.k;
+        k2sum += m.k2;
     }
     if (a.enable_spec) {
         Cone c = cone_for_slot(a, P, a.n_diffuse, cam);
@@ -491,12 +498,14 @@ __device__ __forceinline__ void trace_pixel(const TraceArgs& a, const LevelTable
         o1.y = m.g;
         o1.z = m.b;
         ksum += m.k;
+        k2sum += m.k2;
     }
     if (a.enable_occ) {
         Cone c = cone_for_slot(a, P, a.n_diffuse + 1, cam);
         MarchResult m = march<DT, ANISO, kShareFootprint<DT>>(a, T, c, D);
         o1.w = m.a;
         ksum += m.k;
+        k2sum += m.k2;
     }
 }
 

@@ -39,6 +39,21 @@ inline vct_v4i vct_pyr_raw_rsrc(const void* pyr, uint64_t bytes) {
     return r;
 }
 
+// The raw resource r with its base moved `by` bytes forward and its range
+// shortened by as much (empty once `by` reaches it), so that an offset o into
+// the result reads what offset by + o reads from r.  Used with wave-uniform
+// values, where it is a handful of scalar instructions.
+__host__ __device__ inline vct_v4i vct_rebase_raw(vct_v4i r, uint64_t by) {
+    const uint64_t base = ((uint64_t)(uint32_t)r.x | ((uint64_t)((uint32_t)r.y & 0xffffu) << 32)) + by;
+    const uint32_t n = (uint32_t)r.z;
+    vct_v4i o;
+    o.x = (int32_t)(uint32_t)base;
+    o.y = (int32_t)(((uint32_t)(base >> 32) & 0xffffu) | ((uint32_t)r.y & 0xffff0000u));
+    o.z = (int32_t)(by < (uint64_t)n ? n - (uint32_t)by : 0u);
+    o.w = r.w;
+    return o;
+}
+
 #ifndef VCT_HOST_EMULATION
 // buffer_load_dwordx4 / _dwordx2 with offen (voffset = byte offset)
 __device__ vct_v4i vct_raw_load_v4i32(vct_v4i rsrc, int32_t voffset, int32_t soffset,

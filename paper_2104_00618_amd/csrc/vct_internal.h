@@ -169,7 +169,9 @@ struct EventSink {
 hipError_t vct_launch_build_mips(const PyrLayout& L, const float* base, void* pyr, hipStream_t s, EventSink& es);
 hipError_t vct_launch_unpack(const PyrLayout& L, const void* pyr, int level, int direction, float* out,
                              hipStream_t s);
-hipError_t vct_launch_trace(const TraceArgs& a, int dtype, float* out, unsigned long long* count,
+// count != nullptr: no output; count[0] = the cone samples taken and, with
+// n_counts = 2, count[1] = those that read two levels
+hipError_t vct_launch_trace(const TraceArgs& a, int dtype, float* out, unsigned long long* count, int n_counts,
                             hipStream_t s, EventSink& es);
 size_t vct_voxelize_acc_bytes(int n, bool surface);
 size_t vct_voxelize_workspace_size(int n, long long n_tris, bool surface);

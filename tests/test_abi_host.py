@@ -164,6 +164,8 @@ def test_null_outputs_are_rejected():
     assert rc == EINVAL
     rc = vct.lib().vct_count_samples(ctypes.byref(g), None, ctypes.byref(gb), ctypes.byref(p), None, None)
     assert rc == EINVAL and "count" in vct.lib().vct_last_error().decode()
+    rc = vct.lib().vct_count_sample_levels(ctypes.byref(g), None, ctypes.byref(gb), ctypes.byref(p), None, None)
+    assert rc == EINVAL and vct.lib().vct_last_error().decode().startswith("vct_count_sample_levels: count")
     rc = vct.lib().vct_build_mips(ctypes.byref(g), None, None, 0, None)
     assert rc == EINVAL and "non-null" in vct.lib().vct_last_error().decode()
 

@@ -217,3 +217,47 @@ def test_bounce_full_launch_sampled_voxels():
     assert worst(e)[0] <= TOL["f32"]
     untouched = ~vb.surface_mask(rb, rn)
     assert np.array_equal(got[untouched].view(np.uint32), rb[untouched].view(np.uint32))
+
+
+def test_bounce_one_cone_anisotropic_512_reaches_the_top_levels():
+    """One diffuse cone (a 64-thread gather workgroup) through a 512^3
+    anisotropic float16 pyramid, from voxels facing -z near the front of the
+    grid: the cones travel far enough to blend levels 8 and 9 of the -z
+    pyramid, the last entries of the per-direction offset table, which a
+    64-thread workgroup must load as well as a larger one.  Path parity on
+    seeded voxels: the oracle samples the GPU's decoded pyramids."""
+    from oracle import vct_aniso as va
+    n = 512
+    rng = np.random.default_rng(41)
+    # a faint random medium everywhere (the cones keep going), random colours
+    a = rng.uniform(0.0, 0.004, size=(n, n, n, 1)).astype(np.float32)
+    base = np.concatenate([rng.uniform(0.0, 1.0, size=(n, n, n, 3)).astype(np.float32) * a, a], -1)
+    # 256 surface voxels facing -z in the front slab z in [440, 480); all others have no normal
+    pick = np.stack([rng.integers(440, 480, 256), rng.integers(64, 448, 256), rng.integers(64, 448, 256)], 1)
+    pick = np.unique(pick, axis=0)
+    nrm = np.zeros((n, n, n, 4), np.float32)
+    nrm[pick[:, 0], pick[:, 1], pick[:, 2]] = (0.0, 0.0, -1.0, 1.0)
+    base[pick[:, 0], pick[:, 1], pick[:, 2], 3] = 0.5
+    alb = np.full((n, n, n, 4), 0.5, np.float32)
+    p = ConeParams(np.array([[0.0, 0.0, 1.0]], np.float32), np.array([1.0], np.float32), alpha_thresh=0.99)
+    g = vct.Grid(n, dtype="f16", anisotropic=True)
+    pyr = vct.build_mips(dev(base), g)
+    print("bounce 512^3 f16 anisotropic, one -z cone", flush=True)
+    got = vct.bounce(pyr, g, dev(base), dev(nrm), dev(alb), p)
+    z, y, x = pick[:, 0], pick[:, 1], pick[:, 2]
+    got = got[torch.from_numpy(z), torch.from_numpy(y), torch.from_numpy(x)].cpu().numpy()
+    am = [[vct.unpack_level_dir(pyr, g, lv, d).cpu().numpy().astype(np.float64) for lv in range(g.levels)]
+          for d in range(6)]
+    del pyr
+    torch.cuda.empty_cache()
+    ref, amb = vb.bounce(base, nrm, alb, p, mips=am[0], sampler=va.aniso_sampler(am), voxels=pick,
+                         return_info=True)
+    # the march blends levels 8 and 9 of the -z pyramid (the cones reach LOD > 8 at t > 0.433)
+    assert ((z / n) - 0.433 > 0.2).all()
+    inc_g = got[:, 0:3] - base[z, y, x, 0:3]
+    inc_r = ref[:, 0:3] - base[z, y, x, 0:3].astype(np.float64)
+    e = range_errors(inc_g, inc_r, ~amb)
+    print(f"bounce 512^3 f16 anisotropic, one -z cone: {len(pick)} voxels ({int(amb.sum())} ambiguous): {fmt(e)}",
+          flush=True)
+    assert worst(e)[0] <= TOL["f32"]
+    assert np.abs(inc_r).max() > 0

@@ -182,6 +182,35 @@ def test_count_samples_matches_oracle():
     print(f"count {cnt}, oracle {int(res['K'].sum())}, lanes near alpha 1: {int(loose.sum())}", flush=True)
 
 
+def test_count_sample_levels_matches_oracle():
+    """The samples of the march split by the levels they read: every sample
+    counted once, and those with a fractional LOD (two levels blended) counted
+    again, lane by lane as the oracle's march records them."""
+    w = workload("c0")
+    g = vct.Grid(w.n)
+    pyr = vct.build_mips(dev(w.base), g)
+    args = (pyr, g, dev(w.pos_rough), dev(w.normal), dev(w.cam_pos), w.params)
+    n, n2 = vct.count_sample_levels(*args)
+    assert n == vct.count_samples(*args)
+    mips = oracle.build_mips(w.base)
+    lanes = oracle.cone_lanes(w.pos_rough, w.normal, w.cam_pos, w.params, w.n)
+    res = oracle.march(mips, lanes, w.params, record=True)
+    two = np.zeros(len(res["K"]), dtype=np.int64)
+    near = np.zeros(len(res["K"]), dtype=np.int64)
+    for idx, _, _, lam, _, _ in res["steps"]:
+        frac = lam - np.floor(lam)
+        np.add.at(two, idx, (frac > 0).astype(np.int64))
+        # a float32 LOD within rounding of an integer may land on either side
+        np.add.at(near, idx, ((frac > 0) & (np.minimum(frac, 1 - frac) < 1e-5)).astype(np.int64))
+    loose = res["ambiguous"] | (res["alpha"] > 1 - 1e-6) | (near > 0)
+    strict2 = int(two[~loose].sum())
+    print(f"two-level samples {n2} of {n}; oracle {int(two.sum())} ({strict2} on strict lanes, "
+          f"{int(loose.sum())} loose lanes)", flush=True)
+    assert 0 < n2 < n
+    assert strict2 > 0.9 * two.sum()
+    assert strict2 <= n2 <= int(two.sum()) + 2 * int(loose.sum()) + int(near.sum())
+
+
 def test_empty_gbuffer_and_all_background():
     w = workload("c0")
     g = vct.Grid(w.n)
