@@ -131,10 +131,10 @@ class Workload:
         return self.pos_rough.shape[:3]
 
 
-def _views(sc, cams, h, w):
+def _views(sc, cams, h, w, device=None):
     pr, nr = [], []
     for eye, tgt in cams:
-        a, b = cornell.render_gbuffer(sc, eye, tgt, h, w)
+        a, b = cornell.render_gbuffer(sc, eye, tgt, h, w, device=device)
         pr.append(a)
         nr.append(b)
     cam = np.asarray([c[0] for c in cams], dtype=np.float32)
@@ -144,9 +144,11 @@ def _views(sc, cams, h, w):
 C0_CAM = ((0.5, 0.5, 1.866), (0.5, 0.5, 0.0))
 
 
-def make_workload(name, h=None, w=None, n=None, views=None):
+def make_workload(name, h=None, w=None, n=None, views=None, device=None):
     """Build one of the named workloads.  ``h``, ``w``, ``n`` and ``views``
     override the sizes (used by the small parity and finite-difference cases).
+    ``device``: where the generator's torch operations run (default the CPU;
+    a GPU gives the same bits, faster for the large workloads).
 
     c0     64^3 / 7 levels, 2 boxes, 1 x 256^2 fixed camera, 6+1+1 cones, alpha_thresh 1
     c1     256^3 / 9 levels, 4-8 boxes and spheres, 1 x 1920x1080 camera inside the box,
@@ -157,7 +159,7 @@ def make_workload(name, h=None, w=None, n=None, views=None):
     """
     if name == "c0":
         n = n or 64
-        sc = cornell.make_scene(n, seed=0, n_boxes=(2, 2))
+        sc = cornell.make_scene(n, seed=0, n_boxes=(2, 2), device=device)
         cams = [C0_CAM]
         h, w = h or 256, w or 256
         d, wt = cone_set("six")
@@ -165,7 +167,7 @@ def make_workload(name, h=None, w=None, n=None, views=None):
     elif name == "c1":
         n = n or 256
         cam = cornell.random_camera(101)
-        sc = cornell.make_scene(n, seed=1, n_boxes=(2, 4), n_spheres=(2, 4), avoid=[cam[0]])
+        sc = cornell.make_scene(n, seed=1, n_boxes=(2, 4), n_spheres=(2, 4), avoid=[cam[0]], device=device)
         cams = [cam]
         h, w = h or 1080, w or 1920
         d, wt = cone_set("five")
@@ -175,7 +177,7 @@ def make_workload(name, h=None, w=None, n=None, views=None):
         nv = views or 8
         cams = [cornell.random_camera(301 + i) for i in range(nv)]
         sc = cornell.make_scene(n, seed=3, n_boxes=(2, 4), n_spheres=(2, 4),
-                                avoid=[c[0] for c in cams])
+                                avoid=[c[0] for c in cams], device=device)
         h, w = h or 512, w or 512
         d, wt = cone_set("six")
         params = ConeParams(d, wt, alpha_thresh=0.99)
@@ -183,7 +185,7 @@ def make_workload(name, h=None, w=None, n=None, views=None):
         n = n or 16
         nv = views or 2
         cams = [C0_CAM] + [cornell.random_camera(400 + i) for i in range(nv - 1)]
-        sc = cornell.make_scene(n, seed=4, n_boxes=(2, 2), avoid=[c[0] for c in cams])
+        sc = cornell.make_scene(n, seed=4, n_boxes=(2, 2), avoid=[c[0] for c in cams], device=device)
         h, w = h or 32, w or 32
         d, wt = cone_set("six")
         params = ConeParams(d, wt, alpha_thresh=0.99)
@@ -192,13 +194,13 @@ def make_workload(name, h=None, w=None, n=None, views=None):
         nv = views or 4
         cams = [cornell.random_camera(501 + i) for i in range(nv)]
         sc = cornell.make_scene(n, seed=5, n_boxes=(4, 8), n_spheres=(4, 8),
-                                avoid=[c[0] for c in cams])
+                                avoid=[c[0] for c in cams], device=device)
         h, w = h or 2160, w or 3840
         d, wt = cone_set("five")
         params = ConeParams(d, wt, alpha_thresh=0.99)
     else:
         raise ValueError(name)
-    pr, nr, cam = _views(sc, cams, h, w)
+    pr, nr, cam = _views(sc, cams, h, w, device)
     levels = int(round(math.log2(n))) + 1
     return Workload(name, n, levels, sc, pr, nr, cam, params)
 

@@ -74,7 +74,7 @@ def _snap_box(lo, hi, n):
 
 
 def make_scene(n, seed, n_boxes=(2, 2), n_spheres=(0, 0), box_edge=(0.15, 0.35),
-               avoid=None, voxelize=True):
+               avoid=None, voxelize=True, device=None):
     """Draw a seeded scene.  ``n_boxes``/``n_spheres`` are inclusive count
     ranges.  ``avoid`` is a list of points (camera eyes) that no solid may
     contain."""
@@ -117,15 +117,34 @@ def make_scene(n, seed, n_boxes=(2, 2), n_spheres=(0, 0), box_edge=(0.15, 0.35),
         spheres.append(Sphere(c, float(r), alb, rough))
     sc = Scene(n, boxes, spheres, walls, wall_rough, LIGHT_POS)
     if voxelize:
-        sc.base = voxelize_scene(sc)
+        sc.base = voxelize_scene(sc, device)
     return sc
 
 
-def _solid_and_albedo(sc):
+def _device(device):
+    import torch
+
+    return torch.device(device if device is not None else "cpu")
+
+
+def _norm3(v):
+    """Euclidean length of the rows of an [m, 3] float64 tensor as
+    sqrt((x*x + y*y) + z*z): elementwise IEEE operations only, so the result
+    is the same bits on any device."""
+    import torch
+
+    return torch.sqrt((v[:, 0] * v[:, 0] + v[:, 1] * v[:, 1]) + v[:, 2] * v[:, 2])
+
+
+def _solid_and_albedo(sc, device=None):
+    import torch
+
+    dev = _device(device)
     n = sc.n
-    c = (np.arange(n) + 0.5) / n
-    solid = np.zeros((n, n, n), dtype=bool)
-    alb = np.zeros((n, n, n, 3), dtype=np.float32)
+    c = (torch.arange(n, dtype=torch.float64, device=dev) + 0.5) / n
+    solid = torch.zeros((n, n, n), dtype=torch.bool, device=dev)
+    alb = torch.zeros((n, n, n, 3), dtype=torch.float32, device=dev)
+    f32 = lambda v: torch.tensor(np.asarray(v, dtype=np.float64), dtype=torch.float64).to(torch.float32).to(dev)  # noqa: E731
     # walls: outer voxel layers (z=0 back, y=0 floor, y=n-1 ceiling, x=0 left, x=n-1 right)
     for name, sl in (("back", (0, slice(None), slice(None))),
                      ("floor", (slice(None), 0, slice(None))),
@@ -133,41 +152,43 @@ def _solid_and_albedo(sc):
                      ("left", (slice(None), slice(None), 0)),
                      ("right", (slice(None), slice(None), n - 1))):
         solid[sl] = True
-        alb[sl] = sc.wall_albedo[name]
+        alb[sl] = f32(sc.wall_albedo[name])
     for b in sc.boxes:
         ilo = np.rint(b.lo * n).astype(int)
         ihi = np.rint(b.hi * n).astype(int)
         sl = (slice(ilo[2], ihi[2]), slice(ilo[1], ihi[1]), slice(ilo[0], ihi[0]))
         solid[sl] = True
-        alb[sl] = b.albedo
+        alb[sl] = f32(b.albedo)
     for s in sc.spheres:
         lo = np.maximum(np.floor((s.centre - s.radius) * n).astype(int) - 1, 0)
         hi = np.minimum(np.ceil((s.centre + s.radius) * n).astype(int) + 1, n)
-        zz, yy, xx = np.meshgrid(c[lo[2]:hi[2]], c[lo[1]:hi[1]], c[lo[0]:hi[0]], indexing="ij")
-        inside = ((xx - s.centre[0]) ** 2 + (yy - s.centre[1]) ** 2 + (zz - s.centre[2]) ** 2
-                  <= s.radius ** 2)
+        zz, yy, xx = torch.meshgrid(c[lo[2]:hi[2]], c[lo[1]:hi[1]], c[lo[0]:hi[0]], indexing="ij")
+        dx, dy, dz = xx - float(s.centre[0]), yy - float(s.centre[1]), zz - float(s.centre[2])
+        inside = (dx * dx + dy * dy) + dz * dz <= s.radius ** 2
         sub = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
         solid[sub] |= inside
-        alb[sub][inside] = s.albedo
+        alb[sub] = torch.where(inside[..., None], f32(s.albedo), alb[sub])
     return solid, alb
 
 
 def _shadow(solid, start, light, n):
     """Hard shadow: march from ``start`` toward the light in steps of half a
     voxel, looking up the nearest voxel; returns 1 where nothing solid is hit.
-    Elementwise float64 torch ops on the CPU (multi-threaded, deterministic)."""
+    Elementwise float64 torch operations on the tensors' device (the same
+    bits on the CPU and a GPU)."""
     import torch
 
-    light = torch.tensor(np.asarray(light, dtype=np.float64))
-    st = torch.from_numpy(np.ascontiguousarray(start, dtype=np.float64))
-    occ = torch.from_numpy(np.ascontiguousarray(solid)).reshape(-1)
+    dev = solid.device
+    light = torch.tensor(np.asarray(light, dtype=np.float64), device=dev)
+    st = start
+    occ = solid.reshape(-1)
     delta = light[None, :] - st
-    dist = torch.linalg.vector_norm(delta, dim=1)
+    dist = _norm3(delta)
     dirn = delta / torch.clamp(dist, min=1e-12)[:, None]
     step = 0.5 / n
-    vis = torch.ones(len(st), dtype=torch.bool)
-    idx = torch.arange(len(st))
-    t = torch.zeros(len(st), dtype=torch.float64)
+    vis = torch.ones(len(st), dtype=torch.bool, device=dev)
+    idx = torch.arange(len(st), device=dev)
+    t = torch.zeros(len(st), dtype=torch.float64, device=dev)
     while len(idx):
         p = st[idx] + t[idx, None] * dirn[idx]
         ijk = torch.clamp(torch.floor(p * n).to(torch.int64), 0, n - 1)
@@ -176,42 +197,48 @@ def _shadow(solid, start, light, n):
         t[idx] += step
         keep = (~hit) & (t[idx] < dist[idx])
         idx = idx[keep]
-    return vis.numpy()
+    return vis
 
 
-def voxelize_scene(sc):
-    """Premultiplied RGBA float32 grid [z][y][x][4] of one-bounce direct light."""
+def voxelize_scene(sc, device=None):
+    """Premultiplied RGBA float32 grid [z][y][x][4] of one-bounce direct light
+    (numpy).  ``device``: where the torch operations run (default the CPU);
+    they are elementwise IEEE operations, so every device gives the same bits."""
+    import torch
+
     n = sc.n
-    solid, alb = _solid_and_albedo(sc)
-    pad = np.pad(solid, 1, constant_values=True)          # outside counts as solid
-    nrm = np.zeros((n, n, n, 3), dtype=np.float32)
-    surf = np.zeros((n, n, n), dtype=bool)
+    solid, alb = _solid_and_albedo(sc, device)
+    dev = solid.device
+    pad = torch.ones((n + 2, n + 2, n + 2), dtype=torch.bool, device=dev)   # outside counts as solid
+    pad[1:-1, 1:-1, 1:-1] = solid
+    nrm = torch.zeros((n, n, n, 3), dtype=torch.float32, device=dev)
+    surf = torch.zeros((n, n, n), dtype=torch.bool, device=dev)
     # (axis in [z,y,x] order, sign) -> unit vector in (x,y,z)
-    for ax, vec in ((2, (1, 0, 0)), (1, (0, 1, 0)), (0, (0, 0, 1))):
+    for ax, comp in ((2, 0), (1, 1), (0, 2)):
         for sgn in (1, -1):
             sl = [slice(1, -1)] * 3
             sl[ax] = slice(1 + sgn, n + 1 + sgn)
-            empty_nb = ~pad[tuple(sl)]
-            e = solid & empty_nb
+            e = solid & ~pad[tuple(sl)]
             surf |= e
-            nrm[e] += sgn * np.asarray(vec, dtype=np.float32)
-    base = np.zeros((n, n, n, 4), dtype=np.float32)
-    base[..., 3] = solid.astype(np.float32)
-    zi, yi, xi = np.nonzero(surf)
+            nrm[..., comp] += e.to(torch.float32) * float(sgn)
+    base = torch.zeros((n, n, n, 4), dtype=torch.float32, device=dev)
+    base[..., 3] = solid.to(torch.float32)
+    zi, yi, xi = torch.nonzero(surf, as_tuple=True)
     if len(zi):
-        nv = nrm[zi, yi, xi].astype(np.float64)
-        nl = np.linalg.norm(nv, axis=1)
+        nv = nrm[zi, yi, xi].to(torch.float64)
+        nl = _norm3(nv)
         ok = nl > 0
-        nv[ok] /= nl[ok, None]
-        centre = (np.stack([xi, yi, zi], axis=1) + 0.5) / n
-        light = np.asarray(sc.light, dtype=np.float64)
+        nv = torch.where(ok[:, None], nv / torch.where(ok, nl, 1.0)[:, None], nv)
+        centre = (torch.stack([xi, yi, zi], dim=1).to(torch.float64) + 0.5) / n
+        light = torch.tensor(np.asarray(sc.light, dtype=np.float64), device=dev)
         ldir = light[None, :] - centre
-        ldir /= np.maximum(np.linalg.norm(ldir, axis=1), 1e-12)[:, None]
-        lam = np.maximum(0.0, np.sum(nv * ldir, axis=1)) * ok
-        vis = _shadow(solid, centre + 1.5 / n * nv, light, n)
-        rad = alb[zi, yi, xi].astype(np.float64) * (lam * vis)[:, None]
-        base[zi, yi, xi, 0:3] = rad.astype(np.float32)
-    return base
+        ldir = ldir / torch.clamp(_norm3(ldir), min=1e-12)[:, None]
+        lam = torch.clamp((nv[:, 0] * ldir[:, 0] + nv[:, 1] * ldir[:, 1]) + nv[:, 2] * ldir[:, 2], min=0.0)
+        lam = lam * ok.to(torch.float64)
+        vis = _shadow(solid, centre + (1.5 / n) * nv, sc.light, n)
+        rad = alb[zi, yi, xi].to(torch.float64) * (lam * vis.to(torch.float64))[:, None]
+        base[zi, yi, xi, 0:3] = rad.to(torch.float32)
+    return base.cpu().numpy()
 
 
 # --------------------------------------------------------------------------
@@ -255,57 +282,59 @@ def _planes(sc):
     return out
 
 
-def render_gbuffer(sc, eye, target, h, w, fov_deg=60.0):
-    """Analytic G-buffer: (pos_rough [h,w,4], normal [h,w,4]) float32.
+def render_gbuffer(sc, eye, target, h, w, fov_deg=60.0, device=None):
+    """Analytic G-buffer: (pos_rough [h,w,4], normal [h,w,4]) float32 numpy.
     pos_rough = (x, y, z, roughness); normal = (nx, ny, nz, valid).
-    Elementwise float64 torch ops on the CPU (multi-threaded, deterministic)."""
+    Elementwise float64 torch operations on ``device`` (default the CPU); every
+    device gives the same bits."""
     import torch
 
+    dev = _device(device)
     o_np, d_np = camera_rays(eye, target, h, w, fov_deg)
-    o = torch.tensor(o_np, dtype=torch.float64)
-    d = torch.from_numpy(d_np)
+    o = torch.tensor(o_np, dtype=torch.float64, device=dev)
+    d = torch.from_numpy(d_np).to(dev)
     m = d.shape[0]
-    best_t = torch.full((m,), float("inf"), dtype=torch.float64)
-    best_n = torch.zeros((m, 3), dtype=torch.float64)
-    best_r = torch.zeros(m, dtype=torch.float64)
-    best_plane = torch.zeros(m, dtype=torch.bool)
+    best_t = torch.full((m,), float("inf"), dtype=torch.float64, device=dev)
+    best_n = torch.zeros((m, 3), dtype=torch.float64, device=dev)
+    best_r = torch.zeros(m, dtype=torch.float64, device=dev)
+    best_plane = torch.zeros(m, dtype=torch.bool, device=dev)
     eps = 1e-9
     for ax, val, sgn, rlo, rhi, rough in _planes(sc):
         dd = d[:, ax]
-        t = (float(val) - o[ax]) / dd
+        t = (float(val) - float(o_np[ax])) / dd
         facing = dd * sgn < 0
-        inside = torch.ones(m, dtype=torch.bool)
+        inside = torch.ones(m, dtype=torch.bool, device=dev)
         for a2 in range(3):
             if a2 == ax:
                 continue
-            pa = o[a2] + t * d[:, a2]
+            pa = float(o_np[a2]) + t * d[:, a2]
             inside &= (pa >= float(rlo[a2]) - eps) & (pa <= float(rhi[a2]) + eps)
         ok = facing & inside & (t > 1e-9) & (t < best_t)
         best_t = torch.where(ok, t, best_t)
-        nv = torch.zeros(3, dtype=torch.float64)
+        nv = torch.zeros(3, dtype=torch.float64, device=dev)
         nv[ax] = sgn
         best_n[ok] = nv
         best_r[ok] = float(rough)
         best_plane[ok] = True
     for s in sc.spheres:
-        c = torch.tensor(s.centre, dtype=torch.float64)
-        oc = o - c
-        bq = d @ oc
-        cq = float(oc @ oc) - s.radius ** 2
+        oc = o_np - np.asarray(s.centre, dtype=np.float64)
+        c = torch.tensor(s.centre, dtype=torch.float64, device=dev)
+        bq = (d[:, 0] * float(oc[0]) + d[:, 1] * float(oc[1])) + d[:, 2] * float(oc[2])
+        cq = float((oc[0] * oc[0] + oc[1] * oc[1]) + oc[2] * oc[2]) - s.radius ** 2
         disc = bq * bq - cq
         t = -bq - torch.sqrt(torch.clamp(disc, min=0.0))
         ok = (disc >= 0) & (t > 1e-9) & (t < best_t)
         best_t = torch.where(ok, t, best_t)
         p = o[None, :] + t[ok, None] * d[ok]
         nv = (p - c[None, :]) / s.radius
-        best_n[ok] = nv / torch.linalg.vector_norm(nv, dim=1, keepdim=True)
+        best_n[ok] = nv / _norm3(nv)[:, None]
         best_r[ok] = s.roughness
         best_plane[ok] = False
     valid = torch.isfinite(best_t)
     pos = torch.where(valid[:, None], o[None, :] + torch.where(valid, best_t, 0.0)[:, None] * d,
-                      torch.zeros((), dtype=torch.float64))
-    pr = torch.zeros((m, 4), dtype=torch.float32)
-    nr = torch.zeros((m, 4), dtype=torch.float32)
+                      torch.zeros((), dtype=torch.float64, device=dev))
+    pr = torch.zeros((m, 4), dtype=torch.float32, device=dev)
+    nr = torch.zeros((m, 4), dtype=torch.float32, device=dev)
     pr[:, 0:3] = pos.to(torch.float32)
     pr[:, 3] = torch.where(valid, best_r, 0.0).to(torch.float32)
     nr[:, 0:3] = best_n.to(torch.float32)
@@ -314,7 +343,7 @@ def render_gbuffer(sc, eye, target, h, w, fov_deg=60.0):
     for ax in range(3):
         on_plane = valid & best_plane & (best_n[:, ax].abs() == 1.0)
         pr[on_plane, ax] = (torch.round(pos[on_plane, ax] * sc.n) / sc.n).to(torch.float32)
-    return pr.numpy().reshape(h, w, 4), nr.numpy().reshape(h, w, 4)
+    return pr.cpu().numpy().reshape(h, w, 4), nr.cpu().numpy().reshape(h, w, 4)
 
 
 def random_camera(seed):

@@ -20,7 +20,7 @@ def dev(a):
 
 @pytest.fixture(scope="module")
 def c4():
-    w = workload("c4")
+    w = workload("c4", device=DEV)      # (the generator on the GPU: the same bits as on the CPU, faster)
     g = vct.Grid(w.n, dtype="f16")
     base = dev(w.base)
     pyr = vct.build_mips(base, g)
@@ -60,6 +60,58 @@ def test_c4_backward_full_launch_is_deterministic_and_exact_under_scaling(c4):
     assert torch.equal(a, b)
     assert torch.equal(c, a * 2)
     assert a.abs().max() > 0
+
+
+def test_c4_training_step_sparse_grad_out_matches_oracle(c4):
+    """The c4 training step at its full launch (512^3 float16 pyramid,
+    4 x 3840x2160, trace_save + trace_backward_saved) with dL/d(out) nonzero
+    on 64 seeded surface pixels spread over the four views, so that the oracle
+    can form the whole gradient from those pixels.  Path parity: the oracle
+    marches the GPU's decoded float16 levels, and the gradient is taken with
+    respect to the float32 base with the storage rounding as the identity."""
+    w, g, base, pyr, (pr, nr, cam) = c4
+    b, h, wd = w.shape
+    rng = np.random.default_rng(94)
+    surf = np.argwhere(w.normal[..., 3] != 0)
+    pick = surf[rng.choice(len(surf), size=64, replace=False)]
+    vv, yy, xx = pick[:, 0], pick[:, 1], pick[:, 2]
+    go = rng.normal(size=(64, 8))
+    gout = torch.zeros((b, h, wd, 8), dtype=torch.float32, device=DEV)
+    gout[torch.from_numpy(vv), torch.from_numpy(yy), torch.from_numpy(xx)] = torch.from_numpy(go).float().to(DEV)
+    out, state = vct.trace_save(pyr, g, pr, nr, cam, w.params)
+    got_out = out[torch.from_numpy(vv), torch.from_numpy(yy), torch.from_numpy(xx)].cpu().numpy()
+    del out
+    decoded = [vct.unpack_level(pyr, g, l).cpu().numpy().astype(np.float64) for l in range(g.levels)]
+    # one oracle call over all views (each pixel keeps its camera): view v's
+    # picked pixels in row v, padded with background pixels (no output, no gradient)
+    m = max(int((vv == v).sum()) for v in range(b))
+    prv = np.zeros((b, 1, m, 4), np.float32)
+    nrv = np.zeros((b, 1, m, 4), np.float32)
+    slot = np.zeros(64, dtype=int)
+    for v in range(b):
+        sel = np.nonzero(vv == v)[0]
+        slot[sel] = np.arange(len(sel))
+        prv[v, 0, :len(sel)] = w.pos_rough[v, yy[sel], xx[sel]]
+        nrv[v, 0, :len(sel)] = w.normal[v, yy[sel], xx[sel]]
+    o, info = oracle.trace(decoded, prv, nrv, w.cam_pos, w.params, return_info=True)
+    ref_out = o[vv, 0, slot]
+    amb = info["ambiguous"][vv, 0, slot]          # ties get no gradient on either side
+    gv = np.zeros((b, 1, m, 8))
+    gv[vv, 0, slot] = np.where(amb[:, None], 0.0, go)
+    ref = oracle.trace_backward(decoded, prv, nrv, w.cam_pos, w.params, gv)
+    del decoded
+    go[amb] = 0.0
+    gout[torch.from_numpy(vv), torch.from_numpy(yy), torch.from_numpy(xx)] = torch.from_numpy(go).float().to(DEV)
+    got = vct.trace_backward_saved(pyr, g, pr, nr, cam, w.params, state, gout).cpu().numpy()
+    del state
+    e = range_errors(got_out, ref_out, ~amb)
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max() / scale
+    rms = np.sqrt(np.mean((got - ref) ** 2)) / scale
+    print(f"c4 training step, 64 pixels of gradient ({int(amb.sum())} ties): forward {fmt(e)}; gradient max "
+          f"{err:.2e} rms {rms:.2e}", flush=True)
+    assert worst(e)[0] <= 1e-5
+    assert err <= 1e-4 and rms <= 1e-5
 
 
 def test_c3_fitting_loop_reduces_the_loss():
