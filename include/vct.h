@@ -265,6 +265,29 @@ int vct_trace_backward_saved(const vct_grid* grid, const void* pyramid, const vc
                              const float* grad_out, float* grad_base, void* workspace, size_t workspace_bytes,
                              hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the same
+ * backward as vct_trace_backward_saved, bitwise the same result, with no
+ * workspace argument.  Its accumulator, bound partials and control word live
+ * in a device array of VCT_NOALLOC_SCRATCH_BYTES inside the library, one per
+ * GPU (each GPU the library runs on holds it until the process ends); the
+ * call allocates nothing and clears what it uses with kernels.
+ *   - Shapes whose workspace (vct_backward_workspace_bytes minus
+ *     vct_lane_state_bytes) exceeds VCT_NOALLOC_SCRATCH_BYTES are rejected with
+ *     VCT_EWORKSPACE before anything is enqueued (128 MiB covers a 128^3
+ *     grid, isotropic or anisotropic, with any G-buffer up to 2 million
+ *     16x16 tiles).
+ *   - Every call on a GPU shares that GPU's array: calls that overlap on one
+ *     GPU (on different streams, or from several threads) race and corrupt
+ *     each other's result; serialise them.
+ *   - `stream` must belong to the current device (else VCT_EINVAL); the first
+ *     call on a device looks up the array's address there (VCT_EDEVICE if the
+ *     runtime refuses). */
+#define VCT_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int vct_trace_backward_saved_noalloc(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                                     const vct_cone_params* params, const void* lane_state, size_t lane_state_bytes,
+                                     const float* grad_out, float* grad_base, hipStream_t stream);
+
 /* Shaded radiance with the thesis's cone variants (Section 5.4.4, "Cone
  * Tracing", the implemented shading equation):
  *   L = o_min * sum_q w_q C_diff,q + sum_s f_spec,s C_spec

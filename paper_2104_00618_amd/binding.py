@@ -80,6 +80,7 @@ def lib():
         "vct_lane_state_bytes": [P(CGBuffer), P(CConeParams), P(sz)],
         "vct_trace_save": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, vp, sz, vp],
         "vct_trace_backward_saved": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, sz, vp, vp, vp, sz, vp],
+        "vct_trace_backward_saved_noalloc": [P(CGrid), vp, P(CGBuffer), P(CConeParams), vp, sz, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -553,6 +554,26 @@ def trace_backward_saved(pyramid, grid, pos_rough, normal, cam_pos, params, lane
                                               ctypes.byref(cone_params(params)), _ptr(lane_state), lane_state.numel(),
                                               _ptr(grad_out), _ptr(grad_base), _ptr(workspace), workspace.numel(),
                                               _stream(dev)))
+    return grad_base
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def trace_backward_saved_noalloc(pyramid, grid, pos_rough, normal, cam_pos, params, lane_state, grad_out,
+                                 grad_base):
+    """trace_backward_saved through the entry point that allocates nothing (its
+    scratch is the library's per-GPU array; grad_base is the caller's output)."""
+    gb = _gbuf(pos_rough, normal, cam_pos)
+    dev = pos_rough.device
+    _need(grad_out, "grad_out", torch.float32, tuple(pos_rough.shape[:3]) + (8,), dev)
+    _need(lane_state, "lane_state", torch.uint8, None, dev)
+    _need(grad_base, "grad_base", torch.float32, (grid.n, grid.n, grid.n, 4), dev)
+    with torch.cuda.device(dev):
+        _check(lib().vct_trace_backward_saved_noalloc(ctypes.byref(grid.c()), _ptr(pyramid), ctypes.byref(gb),
+                                                      ctypes.byref(cone_params(params)), _ptr(lane_state),
+                                                      lane_state.numel(), _ptr(grad_out), _ptr(grad_base),
+                                                      _stream(dev)))
     return grad_base
 
 

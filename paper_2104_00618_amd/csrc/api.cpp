@@ -8,9 +8,17 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "vct_internal.h"
+
+// Scratch of the allocation-free backward (vct_trace_backward_saved_noalloc):
+// its accumulator, bound partials and control word, in place of a caller
+// workspace.  Every GPU the library runs on holds its own copy until the
+// process ends.  Host code must not use this name as a device address: the
+// address on each device comes from hipGetSymbolAddress (scratch_on_device).
+static __device__ __align__(256) unsigned char scratch[VCT_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -181,6 +189,38 @@ TraceArgs make_args(const vct_grid* g, const PyrLayout& L, const void* pyr, cons
 
 int device_error(const char* fn, hipError_t e) {
     return fail(VCT_EDEVICE, fn, "HIP error %d (%s)", (int)e, hipGetErrorString(e));
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept; the stream must belong to the
+// current device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_on_device(const char* fn, hipStream_t stream, void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_error(fn, e);
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(VCT_EDEVICE, fn, "device %d is beyond the %d devices the scratch table covers", dev, kMaxDevices);
+    if (stream) {
+        hipDevice_t sdev = -1;
+        e = hipStreamGetDevice(stream, &sdev);
+        if (e != hipSuccess) return device_error(fn, e);
+        if (sdev != dev)
+            return fail(VCT_EINVAL, fn, "stream belongs to device %d but device %d is current", (int)sdev, dev);
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return device_error(fn, e);
+        if (!p) return fail(VCT_EDEVICE, fn, "hipGetSymbolAddress gave a null scratch address on device %d", dev);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return VCT_OK;
 }
 
 }  // namespace
@@ -428,10 +468,12 @@ int vct_trace_save(const vct_grid* grid, const void* pyramid, const vct_gbuffer*
     return VCT_OK;
 }
 
+// noalloc: the workspace is the library's device scratch (workspace and
+// workspace_bytes are ignored); sizes beyond it are rejected.
 static int backward_common(const char* fn, const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
                            const vct_cone_params* params, const void* lane_state, size_t lane_state_bytes,
                            bool saved, const float* grad_out, float* grad_base, void* workspace,
-                           size_t workspace_bytes, hipStream_t stream) {
+                           size_t workspace_bytes, hipStream_t stream, bool noalloc = false) {
     EventSink es = take_events();
     if (int r = check_grid(fn, grid)) return r;
     if (int r = check_gbuffer(fn, gbuf)) return r;
@@ -439,15 +481,20 @@ static int backward_common(const char* fn, const vct_grid* grid, const void* pyr
     if (!(params->alpha_thresh <= 1.0f))
         return fail(VCT_EINVAL, fn, "alpha_thresh = %g: the adjoint needs alpha_thresh <= 1 (transmittance of a "
                     "continuing cone must stay positive)", (double)params->alpha_thresh);
-    if (!pyramid || !grad_base || !workspace)
-        return fail(VCT_EINVAL, fn, "pyramid, grad_base and workspace must be non-null");
+    if (!pyramid || !grad_base || (!noalloc && !workspace))
+        return fail(VCT_EINVAL, fn, noalloc ? "pyramid and grad_base must be non-null"
+                                            : "pyramid, grad_base and workspace must be non-null");
     long long np = (long long)gbuf->b * gbuf->h * gbuf->w;
     if (np > 0 && !grad_out) return fail(VCT_EINVAL, fn, "grad_out is null");
     PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype, grid->anisotropic);
     TraceArgs a = make_args(grid, L, pyramid, gbuf, params);
     BackwardPlan P = vct_plan_backward(L, a);
     const int64_t need = saved ? P.state_off : P.bytes;
-    if (workspace_bytes < (size_t)need)
+    if (noalloc && need > (int64_t)VCT_NOALLOC_SCRATCH_BYTES)
+        return fail(VCT_EWORKSPACE, fn, "these shapes need %lld bytes of scratch; the allocation-free entry point "
+                    "has %lld (VCT_NOALLOC_SCRATCH_BYTES): use vct_trace_backward_saved with a workspace",
+                    (long long)need, (long long)VCT_NOALLOC_SCRATCH_BYTES);
+    if (!noalloc && workspace_bytes < (size_t)need)
         return fail(VCT_EWORKSPACE, fn, "workspace has %zu bytes, needs %lld", workspace_bytes, (long long)need);
     if (saved) {
         if (np > 0 && !lane_state) return fail(VCT_EINVAL, fn, "lane_state is null");
@@ -455,6 +502,8 @@ static int backward_common(const char* fn, const vct_grid* grid, const void* pyr
             return fail(VCT_EWORKSPACE, fn, "lane_state has %zu bytes, needs %lld", lane_state_bytes,
                         (long long)P.state_bytes);
     }
+    if (noalloc)
+        if (int r = scratch_on_device(fn, stream, &workspace)) return r;
     hipError_t e = vct_launch_backward(L, a, P, grad_out, grad_base, workspace, saved ? lane_state : nullptr, stream,
                                        es);
     if (e != hipSuccess) return device_error(fn, e);
@@ -475,6 +524,13 @@ int vct_trace_backward_saved(const vct_grid* grid, const void* pyramid, const vc
                              hipStream_t stream) {
     return backward_common("vct_trace_backward_saved", grid, pyramid, gbuf, params, lane_state, lane_state_bytes,
                            true, grad_out, grad_base, workspace, workspace_bytes, stream);
+}
+
+int vct_trace_backward_saved_noalloc(const vct_grid* grid, const void* pyramid, const vct_gbuffer* gbuf,
+                                     const vct_cone_params* params, const void* lane_state, size_t lane_state_bytes,
+                                     const float* grad_out, float* grad_base, hipStream_t stream) {
+    return backward_common("vct_trace_backward_saved_noalloc", grid, pyramid, gbuf, params, lane_state,
+                           lane_state_bytes, true, grad_out, grad_base, nullptr, 0, stream, true);
 }
 
 int vct_bounce_workspace_bytes(const vct_grid* grid, size_t* bytes) {

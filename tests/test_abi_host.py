@@ -470,3 +470,32 @@ def test_anisotropic_grid_size_and_validation():
     assert lib.vct_unpack_level_dir(ctypes.byref(ani), fake, 1, 6, fake, None) == EINVAL
     assert lib.vct_unpack_level_dir(ctypes.byref(iso), fake, 1, 1, fake, None) == EINVAL
     assert "direction" in lib.vct_last_error().decode()
+
+
+def test_noalloc_backward_rejects_shapes_beyond_its_scratch_before_any_device_call():
+    """The allocation-free backward rejects a workspace larger than its
+    scratch (a 256^3 accumulator is 614 MB) with VCT_EWORKSPACE, and null
+    pointers with VCT_EINVAL, before it looks up the scratch or enqueues
+    anything (no GPU is needed for either answer)."""
+    lib = vct.lib()
+    p = B.cone_params(_params(alpha_thresh=0.99))
+    gb = B.CGBuffer()
+    gb.b, gb.h, gb.w = 1, 4, 4
+    gb.pos_rough = gb.normal = gb.cam_pos = 16          # never dereferenced: rejected first
+    fake = ctypes.c_void_p(16)
+    g = vct.Grid(256).c()
+    rc = lib.vct_trace_backward_saved_noalloc(ctypes.byref(g), fake, ctypes.byref(gb), ctypes.byref(p), fake,
+                                              1 << 20, fake, fake, None)
+    msg = lib.vct_last_error().decode()
+    assert rc == EWORKSPACE and "VCT_NOALLOC_SCRATCH_BYTES" in msg and msg.startswith(
+        "vct_trace_backward_saved_noalloc:"), msg
+    g = vct.Grid(16).c()
+    rc = lib.vct_trace_backward_saved_noalloc(ctypes.byref(g), None, ctypes.byref(gb), ctypes.byref(p), fake,
+                                              1 << 20, fake, fake, None)
+    assert rc == EINVAL and "non-null" in lib.vct_last_error().decode()
+    rc = lib.vct_trace_backward_saved_noalloc(ctypes.byref(g), fake, ctypes.byref(gb), ctypes.byref(p), fake, 8,
+                                              fake, fake, None)
+    assert rc == EWORKSPACE and "lane_state" in lib.vct_last_error().decode()
+    assert B.NOALLOC_SCRATCH_BYTES == 128 << 20
+    header = open(HEADER).read()
+    assert "#define VCT_NOALLOC_SCRATCH_BYTES (128ull << 20)" in header
