@@ -6,13 +6,17 @@ vct_trace_save (5 diffuse + specular + occlusion cones per pixel, keeping each
 cone's end state) and vct_trace_backward_saved (gradient into the float32 base
 grid for a seeded dL/d(out)).  Inputs are resident in HBM before timing.
 
-    python bench.py [--steps K] [--warmup W] [--dtype f32|f16|bf16] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--dtype f32|f16|bf16] [--no-cpu-baseline] [--no-configs]
 
 Prints one JSON line.  value = forward cone samples per second of the whole
 fwd+bwd step; the breakdown also gives the forward-only (vct_trace) rate, the
 per-call and per-kernel times (HIP events on the stream the library launches
 on), the step through vct_trace + vct_trace_backward (no saved state) and the
-float16-storage forward for comparison.
+float16-storage forward for comparison.  `configs` times every configuration
+of the workload family on its own (64^3 / 256^2; the 1080p scene at 64^3,
+128^3 and 256^3; float16 and bfloat16 pyramids; the 128^3 fitting step; the
+512^3 / 4 x 4K float16 scene), and `cpu_baseline` is the FP64 oracle on the
+host's cores (at most 16 processes), timed before the GPU is used.
 """
 import argparse
 import json
@@ -28,22 +32,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("cone samples/s + ms/frame at 1080p (fwd, fwd+bwd), % HBM peak, FP16 vs FP32 storage")
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed-FP32 instructions (the library is built with
-# them disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
-ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# Algorithmic FP32 operations per cone sample (FMA = 2), counted from the
-# formulas: forward sample 220 (schedule 8, position 6, per level 91 x 2 =
-# coordinates 6 + floor/frac 6 + 1-phi 3 + weights 12 + 8 taps x 4 channels FMA
-# 64, level blend 13, compositing 9, t update 2); the scatter pass re-does the
-# sample (220), forms the sample gradient (22) and the 16 taps x 4 channels
-# weighted contributions and their accumulation (128): 370.
-FLOPS_FWD_SAMPLE = 220
-FLOPS_BWD_SCATTER_SAMPLE = 370
+# MI355X's published FP32 vector peak (256 CUs at 2.4 GHz, counting packed
+# FP32 instructions), and the ceiling without them: every kernel here is built
+# with packed FP32 disabled, so its FMAs issue at 256 CUs x 4 SIMDs x 16 lanes
+# x 2 flops x 2.4 GHz.
+ALU_PEAK_TFLOPS = 157.3
+ALU_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Algorithmic FP32 operations (FMA = 2) of one cone sample, counted from the
+# formulas.  Common to every sample: schedule 8, position 6, compositing 9,
+# t update 2 (25); per level read: coordinates 6, floor/frac 6, 1 - phi 3,
+# weights 12, 8 taps x 4 channels FMA 64 (91); the blend of two levels 13.
+# A sample whose LOD is an integer reads one level (116), the others two (220).
+# The scatter pass re-does the sample, forms its gradient (22) and the taps x
+# channels weighted contributions with their accumulation (64 per level):
+# 202 and 370.
+FLOPS_FWD = {1: 116, 2: 220}
+FLOPS_BWD_SCATTER = {1: 202, 2: 370}
 BWD_KERNELS = ["clear accumulator", "bound from saved states", "scale", "pass 2 (re-march + scatter)", "mip adjoint"]
 WORKLOAD = "c1"
 WORKLOAD_DESC = ("procedural Cornell box 256^3 (9 levels, 4-8 boxes and spheres), 1 view 1920x1080, "
                  "5 diffuse cones (front + 4 at 45 deg, 60 deg aperture) + specular + occlusion, "
                  "beta 0.5, t0 0.001, max_dist 1, alpha_thresh 0.99")
+# the thesis's frame times (whole OpenGL frame, GTX 1070; context only)
+PAPER_FRAME_MS = {64: 16.66, 128: 31.3, 256: 127.4}
+
+
+def flops(counts, model):
+    """Algorithmic flops of a march with (samples, two-level samples)."""
+    n, n2 = counts
+    return (n - n2) * model[1] + n2 * model[2]
 
 
 def parse():
@@ -54,12 +71,19 @@ def parse():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the float16-storage forward comparison")
+    ap.add_argument("--no-configs", action="store_true", help="skip the per-configuration rows")
+    ap.add_argument("--cpu-workers", type=int, default=None,
+                    help="host processes for the oracle baseline (default: the host's cores, at most 16)")
     return ap.parse_args()
 
 
-# Sources that define the scatter pass; HBM traffic measured by rocprofv3 is
-# reported only while their digest matches the one recorded with the counters.
-PASS2_SOURCES = ["backward.hip", "bwd_pixel.h", "march.h", "texel.h", "vct_internal.h"]
+# Sources that define each profiled kernel; HBM traffic measured by rocprofv3
+# is reported only while their digest matches the one recorded with the counters.
+KERNEL_SOURCES = {
+    "k_bwd_pass2": ["backward.hip", "bwd_pixel.h", "march.h", "texel.h", "vct_internal.h"],
+    "k_trace": ["trace.hip", "march.h", "texel.h", "vct_internal.h"],
+}
+PASS2_SOURCES = KERNEL_SOURCES["k_bwd_pass2"]
 PROFILE = os.path.join(ROOT, "profiles", "cone_trace_256cubed_1080p_f32.md")
 
 
@@ -71,60 +95,112 @@ def code_text(text):
     return " ".join(text.split())
 
 
-def kernel_source_digest(csrc=None):
-    """Digest of the code (not the comments) of the scatter pass's sources."""
+def kernel_source_digest(csrc=None, kernel="k_bwd_pass2"):
+    """Digest of the code (not the comments) of a kernel's sources."""
     import hashlib
     csrc = csrc or os.path.join(ROOT, "paper_2104_00618_amd", "csrc")
+    files = PASS2_SOURCES if kernel == "k_bwd_pass2" else KERNEL_SOURCES[kernel]
     h = hashlib.sha256()
-    for f in PASS2_SOURCES:
+    for f in files:
         with open(os.path.join(csrc, f)) as fh:
             h.update(code_text(fh.read()).encode())
         h.update(b"\0")
     return h.hexdigest()[:16]
 
 
-def measured_pass2_traffic():
-    """(bytes per launch, note) from the committed profile, or (None, reason)."""
+def measured_traffic(kernel="k_bwd_pass2"):
+    """(bytes per launch, note) of a kernel from the committed profile, or (None, reason)."""
     try:
         text = open(PROFILE).read()
     except OSError:
         return None, "no profile"
-    m = re.search(r"traffic k_bwd_pass2: fetch_bytes=(\d+) write_bytes=(\d+) sources=([0-9a-f]+)", text)
+    m = re.search(r"traffic " + kernel + r": fetch_bytes=(\d+) write_bytes=(\d+) sources=([0-9a-f]+)", text)
     if not m:
         return None, "no traffic line in the profile"
-    if m.group(3) != kernel_source_digest():
+    if m.group(3) != kernel_source_digest(kernel=kernel):
         return None, "kernel sources changed since the counters were taken"
     return int(m.group(1)) + int(m.group(2)), f"FETCH_SIZE + WRITE_SIZE (calibrated) from {os.path.basename(PROFILE)}"
+
+
+def measured_pass2_traffic():
+    return measured_traffic("k_bwd_pass2")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, n_pix=12288, seed=0):
-    """The FP64 oracle as it stands doing the step on a seeded pixel sample of
-    the same frame: build_mips of the full grid, the forward of all cones of
-    n_pix pixels and its adjoint (seeded dL/d(out)).  Returns the baseline and
-    the timed parts (for the per-row table)."""
+# inputs of the oracle baseline's worker processes (set before they are forked)
+_CPU = {}
+
+
+def _cpu_chunk(i):
+    """Worker: the oracle's forward and adjoint of pixel chunk i (one thread)."""
     import oracle
+    from threadpoolctl import threadpool_limits
+
+    c = _CPU
+    sl = slice(i * c["per"], (i + 1) * c["per"])
+    pr, nr, go = c["pr"][:, :, sl], c["nr"][:, :, sl], c["gout"][:, :, sl]
+    w = c["w"]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        _, info = oracle.trace(c["mips"], pr, nr, w.cam_pos, w.params, return_info=True)
+        t1 = time.perf_counter()
+        g = oracle.trace_backward(c["mips"], pr, nr, w.cam_pos, w.params, go)
+        t2 = time.perf_counter()
+    return info["samples"], t1 - t0, t2 - t1, float(np.abs(g).sum())
+
+
+def cpu_workers(requested=None):
+    """Host processes for the oracle baseline: the host's cores, at most 16 (a
+    one-GPU machine's share)."""
+    return max(1, int(requested) if requested else min(16, os.cpu_count() or 1))
+
+
+def cpu_baseline(w, workers=1, per_worker=4096, seed=0):
+    """The FP64 oracle as it stands doing the step on a seeded pixel sample of
+    the same frame, on `workers` host processes: build_mips of the full grid
+    (one thread), then the forward of all cones of per_worker pixels and its
+    adjoint (seeded dL/d(out)) in each process, each on one thread.  Every
+    process runs the oracle's whole adjoint of its chunk, mip adjoint included.
+    The processes are forked here, so call this before the GPU is touched.
+    Returns the baseline and the timed parts (for the per-row table)."""
+    import multiprocessing as mp
+
+    import oracle
+    from threadpoolctl import threadpool_limits
     from tests.workloads import sample_pixels
 
+    n_pix = workers * per_worker
     v, y, x = sample_pixels(w.shape, n_pix, seed)
-    pr, nr = w.pos_rough[v, y, x][None, None], w.normal[v, y, x][None, None]
-    gout = np.random.default_rng(seed).normal(size=(1, 1, n_pix, 8)) * 1e-3
     t0 = time.perf_counter()
-    mips = oracle.build_mips(w.base)
+    with threadpool_limits(limits=1):
+        mips = oracle.build_mips(w.base)
     t1 = time.perf_counter()
-    _, info = oracle.trace(mips, pr, nr, w.cam_pos, w.params, return_info=True)
-    t2 = time.perf_counter()
-    oracle.trace_backward(mips, pr, nr, w.cam_pos, w.params, gout)
-    t3 = time.perf_counter()
-    n = info["samples"]
-    parts = {"mips_s": t1 - t0, "forward_s": t2 - t1, "backward_s": t3 - t2, "samples": n, "pixels": n_pix}
-    base = {"value": n / (t3 - t0), "unit": "cone samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"build_mips of the {w.n}^3 grid + forward and adjoint of all {w.params.n_diffuse + int(w.params.enable_spec) + int(w.params.enable_occ)} cones of "
-                      f"{n_pix} seeded pixels of the {w.shape[2]}x{w.shape[1]} frame ({n} samples; {t1 - t0:.1f} + "
-                      f"{t2 - t1:.1f} + {t3 - t2:.1f} s, NumPy FP64, single thread)"}
+    _CPU.update(w=w, mips=mips, per=per_worker, pr=w.pos_rough[v, y, x][None, None],
+                nr=w.normal[v, y, x][None, None],
+                gout=np.random.default_rng(seed).normal(size=(1, 1, n_pix, 8)) * 1e-3)
+    if workers == 1:
+        res = [_cpu_chunk(0)]
+        t2 = time.perf_counter()
+    else:
+        with mp.get_context("fork").Pool(workers) as pool:
+            t1 = time.perf_counter()
+            res = pool.map(_cpu_chunk, range(workers), chunksize=1)
+            t2 = time.perf_counter()
+    _CPU.clear()
+    n = sum(r[0] for r in res)
+    fwd_cpu, bwd_cpu = sum(r[1] for r in res), sum(r[2] for r in res)
+    parts = {"mips_s": t1 - t0, "parallel_s": t2 - t1, "samples": n, "pixels": n_pix, "workers": workers,
+             # (per-core rates times the cores: the two phases ran interleaved across processes)
+             "forward_samples_per_s": n / fwd_cpu * workers, "backward_samples_per_s": n / bwd_cpu * workers}
+    ncones = w.params.n_diffuse + int(w.params.enable_spec) + int(w.params.enable_occ)
+    base = {"value": n / ((t1 - t0) + (t2 - t1)), "unit": "cone samples/s", "cores": workers, "kind": "oracle",
+            "sample": f"build_mips of the {w.n}^3 grid (one thread, {t1 - t0:.1f} s), then the forward and adjoint "
+                      f"of all {ncones} cones of {n_pix} seeded pixels of the {w.shape[2]}x{w.shape[1]} frame "
+                      f"({n} samples) in {workers} processes of one thread each, {per_worker} pixels apiece, each "
+                      f"with its own mip adjoint ({t2 - t1:.1f} s wall); NumPy FP64"}
     return base, parts
 
 
@@ -219,12 +295,98 @@ def bench_bounce(vct, torch, grid, vt, vc, vlights, params, timed, steps):
            "bounce_kernels_ms": {k: float(t) for k, t in zip(BOUNCE_KERNELS, kms)},
            "remip_ms": remip_ms, "voxelize_mips_bounce_mips_ms": vox_ms + 2 * remip_ms + bounce_ms,
            "gather_samples_per_s": samples / (kms[3] * 1e-3),
-           "gather_frac_of_alu_peak": FLOPS_FWD_SAMPLE * samples / (kms[3] * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+           "gather_frac_of_alu_peak": FLOPS_FWD[2] * samples / (kms[3] * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
            "flag_GBps": flag_bytes / (kms[0] * 1e-3) / 1e9,
            "flag_frac_of_hbm_peak": flag_bytes / (kms[0] * 1e-3) / 1e9 / HBM_PEAK_GBS}
     log(f"bounce: {m} surface voxels, {samples} samples; voxelize+surface {vox_ms:.3f} ms, bounce {bounce_ms:.3f} ms "
         f"({', '.join(f'{k} {t:.3f}' for k, t in zip(BOUNCE_KERNELS, kms))}), re-mip {remip_ms:.3f} ms")
     return res
+
+
+def time_ms(torch, fn, reps, warm=1):
+    """Mean ms per call of fn over reps calls (CUDA events on the current stream)."""
+    for _ in range(warm):
+        fn()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e[0].record()
+    for _ in range(reps):
+        fn()
+    e[1].record()
+    torch.cuda.synchronize()
+    return e[0].elapsed_time(e[1]) / reps
+
+
+def bench_config(vct, torch, w, dtype, reps, label, backward=True):
+    """One configuration: forward (build_mips + trace) and training step
+    (build_mips + trace_save + trace_backward_saved) per frame, cone samples
+    and the rates.  Inputs resident in HBM; HIP events on the current stream."""
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    base, pr, nr, cam = T(w.base), T(w.pos_rough), T(w.normal), T(w.cam_pos)
+    g = vct.Grid(w.n, dtype=dtype)
+    pyr = vct.build_mips(base, g)
+    out = torch.empty(w.shape + (8,), dtype=torch.float32, device=dev)
+    counts = vct.count_sample_levels(pyr, g, pr, nr, cam, w.params)
+    npix = int(np.prod(w.shape))
+    mips_ms = time_ms(torch, lambda: vct.build_mips(base, g, pyr), reps)
+    trace_ms = time_ms(torch, lambda: vct.trace(pyr, g, pr, nr, cam, w.params, out), reps)
+    r = {"grid": w.n, "levels": w.levels, "views": w.shape[0], "height": w.shape[1], "width": w.shape[2],
+         "cones_per_pixel": w.params.n_diffuse + 2, "storage": dtype, "pyramid_bytes": int(pyr.numel()),
+         "samples_per_frame": counts[0], "two_level_samples": counts[1], "samples_per_pixel": counts[0] / npix,
+         "build_mips_ms": mips_ms, "trace_ms": trace_ms, "fwd_ms_per_frame": mips_ms + trace_ms,
+         "fwd_samples_per_s": counts[0] / ((mips_ms + trace_ms) * 1e-3),
+         "trace_frac_of_alu_peak": flops(counts, FLOPS_FWD) / (trace_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS}
+    if backward:
+        st = torch.empty(vct.lane_state_bytes(pr, nr, cam, w.params), dtype=torch.uint8, device=dev)
+        ws = torch.empty(vct.backward_workspace_bytes(g, pr, nr, cam, w.params) - st.numel(), dtype=torch.uint8,
+                         device=dev)
+        gout = T((np.random.default_rng(0).normal(size=w.shape + (8,)) * 1e-3).astype(np.float32))
+        gb = torch.empty_like(base)
+        save_ms = time_ms(torch, lambda: vct.trace_save(pyr, g, pr, nr, cam, w.params, out, st), reps)
+        bwd_ms = time_ms(torch, lambda: vct.trace_backward_saved(pyr, g, pr, nr, cam, w.params, st, gout, ws, gb),
+                         reps)
+        r.update(trace_save_ms=save_ms, trace_backward_saved_ms=bwd_ms, fwd_bwd_ms_per_frame=mips_ms + save_ms + bwd_ms,
+                 fwd_bwd_samples_per_s=counts[0] / ((mips_ms + save_ms + bwd_ms) * 1e-3))
+        del st, ws, gb, gout
+    log(f"{label}: {w.n}^3 {dtype}, {w.shape[0]}x{w.shape[2]}x{w.shape[1]}, {counts[0]} samples; fwd "
+        f"{r['fwd_ms_per_frame']:.3f} ms" + (f", fwd+bwd {r['fwd_bwd_ms_per_frame']:.3f} ms" if backward else ""))
+    del pyr, out, base
+    torch.cuda.empty_cache()
+    return r
+
+
+def bench_configs(vct, torch, make_workload):
+    """The configurations of the workload family, each timed on its own:
+    64^3 / 256^2 (6+1+1 cones, alpha_thresh 1), the 1080p scene at 64^3,
+    128^3 and 256^3 (the thesis's frame-time table sweeps the grid size),
+    float16 and bfloat16 pyramids of the 256^3 scene, the 128^3 / 8 x 512^2
+    fitting step and the 512^3 / 4 x 3840x2160 float16 scene."""
+    dev = "cuda:0"
+    cfg = {}
+    cfg["c0_64cubed_256sq_f32"] = bench_config(vct, torch, make_workload("c0", device=dev), "f32", 20, "c0")
+    sweep = {}
+    for n in (64, 128, 256):
+        wn = make_workload("c1", n=n, device=dev)
+        r = bench_config(vct, torch, wn, "f32", 10, f"1080p sweep {n}^3")
+        r["thesis_frame_ms_gtx1070"] = PAPER_FRAME_MS[n]
+        sweep[f"{n}cubed"] = r
+    cfg["c1_1080p_grid_sweep_f32"] = sweep
+    w1 = make_workload("c1", device=dev)
+    for dt in ("f16", "bf16"):
+        r = bench_config(vct, torch, w1, dt, 10, f"c2 {dt}")
+        r["trace_speedup_vs_f32"] = sweep["256cubed"]["trace_ms"] / r["trace_ms"]
+        r["fwd_speedup_vs_f32"] = sweep["256cubed"]["fwd_ms_per_frame"] / r["fwd_ms_per_frame"]
+        r["fwd_bwd_speedup_vs_f32"] = sweep["256cubed"]["fwd_bwd_ms_per_frame"] / r["fwd_bwd_ms_per_frame"]
+        cfg[f"c2_256cubed_1080p_{dt}"] = r
+    del w1
+    cfg["c3_fit_step_128cubed_8x512sq_f32"] = bench_config(vct, torch, make_workload("c3gt", device=dev), "f32", 10,
+                                                           "c3 fit step")
+    t0 = time.perf_counter()
+    w4 = make_workload("c4", device=dev)
+    log(f"c4 workload generated on the GPU in {time.perf_counter() - t0:.1f} s")
+    cfg["c4_512cubed_4x4k_f16"] = bench_config(vct, torch, w4, "f16", 3, "c4")
+    del w4
+    return cfg
 
 
 def main():
@@ -233,15 +395,24 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU "
               f"implementation", file=sys.stderr)
         sys.exit(2)
-    import torch
-
-    import paper_2104_00618_amd as vct
     from scenes import make_workload
 
-    dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     w = make_workload(WORKLOAD)
     log(f"workload generated in {time.perf_counter() - t0:.1f} s")
+    cpu_base = cpu_parts = None
+    if not args.no_cpu_baseline:
+        # first, before anything touches the GPU: the worker processes are forked
+        nw = cpu_workers(args.cpu_workers)
+        log(f"timing the oracle on {nw} host processes")
+        cpu_base, cpu_parts = cpu_baseline(w, workers=nw)
+        log(f"oracle: {cpu_base['value']:.3g} samples/s on {nw} cores")
+
+    import torch
+
+    import paper_2104_00618_amd as vct
+
+    dev = torch.device("cuda:0")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     base, pr, nr, cam = T(w.base), T(w.pos_rough), T(w.normal), T(w.cam_pos)
     rng = np.random.default_rng(0)
@@ -256,10 +427,11 @@ def main():
     ws_saved = ws[:ws_full - st_bytes]
     gbase = torch.empty_like(base)
     vct.build_mips(base, grid, pyr)
-    samples = vct.count_samples(pyr, grid, pr, nr, cam, w.params)
+    counts = vct.count_sample_levels(pyr, grid, pr, nr, cam, w.params)
+    samples = counts[0]
     npix = int(np.prod(w.shape))
-    log(f"{samples} cone samples per frame ({samples / npix:.1f} per pixel), workspace {ws.numel() / 2**30:.2f} GiB, "
-        f"lane states {st_bytes / 2**30:.2f} GiB")
+    log(f"{samples} cone samples per frame ({samples / npix:.1f} per pixel, {counts[1] / samples:.3f} read two "
+        f"levels), workspace {ws.numel() / 2**30:.2f} GiB, lane states {st_bytes / 2**30:.2f} GiB")
 
     # a plain copy of known size (256 MiB read + 256 MiB written): its
     # FETCH_SIZE / WRITE_SIZE counters calibrate the byte counters of the
@@ -308,14 +480,7 @@ def main():
     # outside the timed steps: the forward alone (inference) and the step
     # through the entry points that keep no state
     def timed(fn, k):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        fn()
-        e[0].record()
-        for _ in range(k):
-            fn()
-        e[1].record()
-        torch.cuda.synchronize()
-        return e[0].elapsed_time(e[1]) / k
+        return time_ms(torch, fn, k)
 
     fwd_ms = timed(lambda: vct.trace(pyr, grid, pr, nr, cam, w.params, out), args.steps)
     # final shading with the thesis's cone variants (first-hit diffuse, occlusion
@@ -378,6 +543,9 @@ def main():
     texel_bytes = 16 if args.dtype == "f32" else 8
     trace_bytes = samples * 16 * texel_bytes + npix * 64
     trace_gbs = trace_bytes / (fwd_ms * 1e-3) / 1e9
+    tr_traffic, tr_note = measured_traffic("k_trace") if (args.dtype == "f32" and WORKLOAD == "c1") else (
+        None, "counters were taken on the float32 1080p workload only")
+    fwd_flops = flops(counts, FLOPS_FWD)
     breakdown = {
         "build_mips_ms": mips_ms, "trace_save_ms": save_ms, "trace_backward_saved_ms": bwd_ms,
         "trace_backward_saved_kernels_ms": {n: float(t) for n, t in zip(BWD_KERNELS, bwd_k)},
@@ -391,12 +559,19 @@ def main():
         "fwd_bwd_ms_per_frame": mips_ms + save_ms + bwd_ms,
         "recompute_path": {"trace_backward_ms": recompute_bwd_ms,
                            "fwd_bwd_ms_per_frame": mips_ms + fwd_ms + recompute_bwd_ms},
-        "samples_per_frame": samples, "samples_per_pixel": samples / npix,
+        "samples_per_frame": samples, "two_level_samples_per_frame": counts[1],
+        "samples_per_pixel": samples / npix,
         "fwd_samples_per_s": samples / ((mips_ms + fwd_ms) * 1e-3),
         "trace_kernel_samples_per_s": samples / (fwd_ms * 1e-3),
-        "trace_kernel": {"logical_tap_GBps": trace_gbs, "frac_of_hbm_peak": trace_gbs / HBM_PEAK_GBS,
-                         "alu_TFLOPs": FLOPS_FWD_SAMPLE * samples / (fwd_ms * 1e-3) / 1e12,
-                         "frac_of_alu_peak": FLOPS_FWD_SAMPLE * samples / (fwd_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS},
+        "trace_kernel": {
+            "alu_TFLOPs": fwd_flops / (fwd_ms * 1e-3) / 1e12,
+            "frac_of_alu_peak": fwd_flops / (fwd_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+            "frac_of_nonpacked_alu_ceiling": fwd_flops / (fwd_ms * 1e-3) / 1e12 / ALU_NONPACKED_TFLOPS,
+            # the logical taps (16 texels a sample) are served from L1, L2 and the
+            # scalar cache: a cache-traffic figure, not a fraction of HBM bandwidth
+            "logical_tap_GBps": trace_gbs, "logical_tap_bytes_over_hbm_peak_cache_served": trace_gbs / HBM_PEAK_GBS,
+            "hbm_bytes_per_launch": tr_traffic, "hbm_bytes_note": tr_note,
+            "hbm_frac_of_peak": None if tr_traffic is None else tr_traffic / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
 
     if not args.no_compare and args.dtype == "f32":
@@ -432,18 +607,27 @@ def main():
             "fwd_bwd_speedup_vs_f32": breakdown["fwd_bwd_ms_per_frame"] / step16}
         log(f"f16 storage: mips {m16:.3f} ms, trace {f16:.3f} ms ({fwd_ms / f16:.2f}x vs f32); training step "
             f"{step16:.3f} ms ({breakdown['fwd_bwd_ms_per_frame'] / step16:.2f}x vs f32)")
+        del p16, o16, ws16
 
-    # dominant kernel of the step: the backward scatter pass (issue-bound VALU work)
+    # dominant kernel of the step: the backward scatter pass (VALU work plus
+    # integer atomics; its HBM traffic is a fraction of the bandwidth)
     p2_ms = float(bwd_k[3])
-    p2_tflops = FLOPS_BWD_SCATTER_SAMPLE * samples / (p2_ms * 1e-3) / 1e12
-    p2_traffic, p2_traffic_note = measured_pass2_traffic() if (args.dtype == "f32" and WORKLOAD == "c1") else (
+    p2_flops = flops(counts, FLOPS_BWD_SCATTER)
+    p2_tflops = p2_flops / (p2_ms * 1e-3) / 1e12
+    p2_traffic, p2_traffic_note = measured_traffic("k_bwd_pass2") if (args.dtype == "f32" and WORKLOAD == "c1") else (
         None, "counters were taken on the float32 1080p workload only")
     roofline = {"kernel": "k_bwd_pass2 (re-march + deterministic tap-gradient scatter), one launch per step",
                 "bound": "alu", "achieved": p2_tflops, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": p2_tflops / ALU_PEAK_TFLOPS, "traffic": p2_traffic, "traffic_note": p2_traffic_note,
-                "launch_ms": p2_ms,
-                "flops_per_launch": FLOPS_BWD_SCATTER_SAMPLE * samples,
-                "flops_model": f"{FLOPS_BWD_SCATTER_SAMPLE} FP32 ops per cone sample x {samples} samples"}
+                "peak_note": "MI355X published FP32 vector peak (counts packed FP32, which these kernels are "
+                             "built without)",
+                "peak_nonpacked": ALU_NONPACKED_TFLOPS, "frac_nonpacked": p2_tflops / ALU_NONPACKED_TFLOPS,
+                "traffic_frac_of_hbm_peak": None if p2_traffic is None else
+                p2_traffic / (p2_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "launch_ms": p2_ms, "flops_per_launch": p2_flops,
+                "flops_model": f"{FLOPS_BWD_SCATTER[2]} FP32 ops per two-level sample x {counts[1]} + "
+                               f"{FLOPS_BWD_SCATTER[1]} per one-level sample x {samples - counts[1]} "
+                               f"(vct_count_sample_levels)"}
     res = {
         "metric": METRIC,
         "value": samples / (ms_step * 1e-3),
@@ -459,62 +643,62 @@ def main():
     }
     mip_bytes = w.n ** 3 * 16 + int(pyr.numel()) - 2 * ((w.n // 16) ** 3) * 16   # base read + levels written
     vox_bytes = w.n ** 3 * (32 + 32 + 16)        # accumulators cleared, read back, base written
+    alu_row = lambda fl, ms: {"bound": "alu", "achieved": fl / (ms * 1e-3) / 1e12, "peak": ALU_PEAK_TFLOPS,  # noqa: E731
+                              "unit": "TFLOP/s", "frac": fl / (ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+                              "frac_nonpacked": fl / (ms * 1e-3) / 1e12 / ALU_NONPACKED_TFLOPS}
     rows = {
         "a1_build_mips": {"kernel": "k_mip_block", "ms": mips_ms, "bound": "hbm",
                           "achieved": mip_bytes / (mips_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": mip_bytes / (mips_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "model": f"float32 base read once + every level written ({mip_bytes} bytes)"},
-        "a2_a6_trace": {"kernel": "k_trace", "ms": fwd_ms, "bound": "alu",
-                        "achieved": FLOPS_FWD_SAMPLE * samples / (fwd_ms * 1e-3) / 1e12, "peak": ALU_PEAK_TFLOPS,
-                        "unit": "TFLOP/s",
-                        "frac": FLOPS_FWD_SAMPLE * samples / (fwd_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
-                        "model": f"{FLOPS_FWD_SAMPLE} FP32 ops per cone sample x {samples} samples",
-                        "logical_tap_GBps": trace_gbs},
+        "a2_a6_trace": dict(alu_row(fwd_flops, fwd_ms), kernel="k_trace", ms=fwd_ms,
+                            model=f"{FLOPS_FWD[2]} FP32 ops per two-level sample x {counts[1]} + {FLOPS_FWD[1]} per "
+                                  f"one-level sample x {samples - counts[1]}",
+                            logical_tap_GBps=trace_gbs),
         "a7_backward": dict(roofline, ms=bwd_ms),
-        "f1_shade": {"kernel": "k_shade", "ms": shade_ms["3_lights"], "pixels_per_s": npix / (shade_ms["3_lights"] * 1e-3),
-                     "samples": shade_samples, "samples_per_s": shade_samples / (shade_ms["3_lights"] * 1e-3),
-                     "bound": "alu",
-                     "achieved": FLOPS_FWD_SAMPLE * shade_samples / (shade_ms["3_lights"] * 1e-3) / 1e12,
-                     "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": FLOPS_FWD_SAMPLE * shade_samples / (shade_ms["3_lights"] * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
-                     "model": f"{FLOPS_FWD_SAMPLE} FP32 ops per cone sample (the trace's count: a lower bound, the "
-                              f"per-light terms are left out) x {shade_samples} samples (vct_count_shade_samples, "
-                              f"3 lights, the thesis's variants)"},
+        "f1_shade": dict(alu_row(FLOPS_FWD[2] * shade_samples, shade_ms["3_lights"]), kernel="k_shade",
+                         ms=shade_ms["3_lights"], pixels_per_s=npix / (shade_ms["3_lights"] * 1e-3),
+                         samples=shade_samples, samples_per_s=shade_samples / (shade_ms["3_lights"] * 1e-3),
+                         model=f"{FLOPS_FWD[2]} FP32 ops per cone sample (every sample counted as two-level; the "
+                               f"per-light terms are left out) x {shade_samples} samples (vct_count_shade_samples, "
+                               f"3 lights, the thesis's variants)"),
         "f2_voxelize": {"kernel": "k_clear + k_tri_setup + k_chunk_scan + k_raster + k_resolve", "ms": vox_ms,
                         "bound": "hbm", "achieved": vox_bytes / (vox_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": vox_bytes / (vox_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                         "model": f"80 B per voxel: 32 B accumulator cleared, read back, 16 B written ({vox_bytes} bytes)"},
-        "f3_bounce": {"kernel": "k_gather (k_flag: hbm)", "ms": bounce["bounce_ms"], "bound": "alu",
-                      "achieved": FLOPS_FWD_SAMPLE * bounce["samples"] / (bounce["bounce_kernels_ms"]["gather"] * 1e-3) / 1e12,
-                      "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": bounce["gather_frac_of_alu_peak"],
-                      "model": f"{FLOPS_FWD_SAMPLE} FP32 ops per cone sample x {bounce['samples']} samples",
-                      "flag_frac_of_hbm_peak": bounce["flag_frac_of_hbm_peak"]},
-        "f4_anisotropic": {"kernel": "k_trace<ANISO>", "ms": aniso["trace_ms"], "bound": "alu",
-                           "achieved": FLOPS_FWD_SAMPLE * aniso["samples_per_frame"] / (aniso["trace_ms"] * 1e-3) / 1e12,
-                           "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": FLOPS_FWD_SAMPLE * aniso["samples_per_frame"] / (aniso["trace_ms"] * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
-                           "model": f"{FLOPS_FWD_SAMPLE} FP32 ops per cone sample (the isotropic count: a lower bound, "
-                                    f"samples above level 0 read up to three directions)",
-                           "backward_ms": aniso["trace_backward_saved_ms"],
-                           "fwd_bwd_ms_per_frame": aniso["fwd_bwd_ms_per_frame"]},
+        "f3_bounce": dict(alu_row(FLOPS_FWD[2] * bounce["samples"], bounce["bounce_kernels_ms"]["gather"]),
+                          kernel="k_gather (k_flag: hbm)", ms=bounce["bounce_ms"],
+                          model=f"{FLOPS_FWD[2]} FP32 ops per cone sample x {bounce['samples']} samples",
+                          flag_frac_of_hbm_peak=bounce["flag_frac_of_hbm_peak"]),
+        "f4_anisotropic": dict(alu_row(FLOPS_FWD[2] * aniso["samples_per_frame"], aniso["trace_ms"]),
+                               kernel="k_trace<ANISO>", ms=aniso["trace_ms"],
+                               model=f"{FLOPS_FWD[2]} FP32 ops per cone sample (the isotropic count: a lower bound, "
+                                     f"samples above level 0 read up to three directions)",
+                               backward_ms=aniso["trace_backward_saved_ms"],
+                               fwd_bwd_ms_per_frame=aniso["fwd_bwd_ms_per_frame"]),
     }
     res["rows"] = rows
-    if not args.no_cpu_baseline:
-        log("timing the oracle on bounded samples (one thread)")
+    if not args.no_configs:
+        del ws, state, ws_saved
+        torch.cuda.empty_cache()
+        res["configs"] = bench_configs(vct, torch, make_workload)
+    if cpu_base is not None:
+        res["cpu_baseline"] = cpu_base
+        nw = cpu_parts["workers"]
+        rows["a1_build_mips"]["cpu_baseline"] = {"value": w.n ** 3 / cpu_parts["mips_s"], "unit": "base texels/s",
+                                                 "cores": 1, "kind": "oracle", "sample": f"the whole {w.n}^3 grid"}
+        rows["a2_a6_trace"]["cpu_baseline"] = {
+            "value": cpu_parts["forward_samples_per_s"], "unit": "cone samples/s", "cores": nw, "kind": "oracle",
+            "sample": f"all 7 cones of {cpu_parts['pixels']} seeded pixels in {nw} processes (per-core rate x cores)"}
+        rows["a7_backward"]["cpu_baseline"] = {
+            "value": cpu_parts["backward_samples_per_s"], "unit": "cone samples/s", "cores": nw, "kind": "oracle",
+            "sample": f"adjoint of all 7 cones of {cpu_parts['pixels']} seeded pixels in {nw} processes, each with "
+                      f"its own mip adjoint (per-core rate x cores)"}
+        log("timing the oracle on bounded samples of the other rows (one thread)")
         # one host thread for every library NumPy may call, so "cores": 1 is what ran
         from threadpoolctl import threadpool_limits
         with threadpool_limits(limits=1):
-            base_cpu, parts = cpu_baseline(w)
             other_rows = cpu_rows(w, vox_mesh, vlights)
-        res["cpu_baseline"] = base_cpu
-        rows["a1_build_mips"]["cpu_baseline"] = {"value": w.n ** 3 / parts["mips_s"], "unit": "base texels/s",
-                                                 "cores": 1, "kind": "oracle", "sample": f"the whole {w.n}^3 grid"}
-        rows["a2_a6_trace"]["cpu_baseline"] = {"value": parts["samples"] / parts["forward_s"], "unit": "cone samples/s",
-                                               "cores": 1, "kind": "oracle",
-                                               "sample": f"all 7 cones of {parts['pixels']} seeded pixels"}
-        rows["a7_backward"]["cpu_baseline"] = {"value": parts["samples"] / parts["backward_s"],
-                                               "unit": "cone samples/s", "cores": 1, "kind": "oracle",
-                                               "sample": f"adjoint of all 7 cones of {parts['pixels']} seeded pixels"}
         for k, v in other_rows.items():
             rows[k]["cpu_baseline"] = v
     print(json.dumps(res), flush=True)

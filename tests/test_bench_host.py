@@ -46,15 +46,50 @@ def test_digest_covers_every_source_of_the_scatter_pass(monkeypatch):
     assert bench.kernel_source_digest() == full
 
 
-def test_oracle_baseline_record_on_a_small_frame():
+@pytest.mark.parametrize("workers", [1, 2])
+def test_oracle_baseline_record_on_a_small_frame(workers):
     from tests.workloads import workload
     w = workload("c3fd")
-    base, parts = bench.cpu_baseline(w, n_pix=48)
+    base, parts = bench.cpu_baseline(w, workers=workers, per_worker=24)
     assert set(base) == {"value", "unit", "cores", "kind", "sample"}
-    assert base["kind"] == "oracle" and base["cores"] == 1 and base["unit"] == "cone samples/s"
-    assert base["value"] > 0 and parts["samples"] > 0 and parts["pixels"] == 48
-    assert f"{w.n}^3" in base["sample"] and "48 seeded pixels" in base["sample"]
-    assert parts["mips_s"] >= 0 and parts["forward_s"] > 0 and parts["backward_s"] > 0
+    assert base["kind"] == "oracle" and base["cores"] == workers and base["unit"] == "cone samples/s"
+    assert base["value"] > 0 and parts["samples"] > 0 and parts["pixels"] == 24 * workers
+    assert f"{w.n}^3" in base["sample"] and f"{24 * workers} seeded pixels" in base["sample"]
+    assert f"{workers} processes" in base["sample"]
+    assert parts["mips_s"] >= 0 and parts["parallel_s"] > 0
+    assert parts["forward_samples_per_s"] > 0 and parts["backward_samples_per_s"] > 0
+    # the same pixels give the same sample count however they are split
+    if workers == 2:
+        _, one = bench.cpu_baseline(w, workers=1, per_worker=48)
+        assert one["samples"] == parts["samples"]
+
+
+def test_worker_count_is_the_hosts_cores_up_to_sixteen():
+    assert bench.cpu_workers(3) == 3
+    assert 1 <= bench.cpu_workers() <= 16
+    assert bench.cpu_workers() == min(16, os.cpu_count() or 1)
+
+
+def test_flop_model_counts_levels_read():
+    assert bench.flops((10, 0), bench.FLOPS_FWD) == 10 * 116
+    assert bench.flops((10, 10), bench.FLOPS_FWD) == 10 * 220
+    assert bench.flops((10, 4), bench.FLOPS_BWD_SCATTER) == 6 * 202 + 4 * 370
+    # a second level adds its 91 flops and the 13 of the blend (forward), and
+    # the 64 of its weighted contributions (scatter)
+    assert bench.FLOPS_FWD[2] - bench.FLOPS_FWD[1] == 91 + 13
+    assert bench.FLOPS_BWD_SCATTER[2] - bench.FLOPS_BWD_SCATTER[1] == 91 + 13 + 64
+
+
+def test_trace_kernel_traffic_is_gated_on_its_own_sources(tmp_path, monkeypatch):
+    d_tr = bench.kernel_source_digest(kernel="k_trace")
+    d_p2 = bench.kernel_source_digest(kernel="k_bwd_pass2")
+    assert d_tr != d_p2
+    prof = tmp_path / "profile.md"
+    monkeypatch.setattr(bench, "PROFILE", str(prof))
+    prof.write_text(f"    traffic k_trace: fetch_bytes=10 write_bytes=5 sources={d_tr}\n"
+                    f"    traffic k_bwd_pass2: fetch_bytes=7 write_bytes=1 sources={d_tr}\n")
+    assert bench.measured_traffic("k_trace")[0] == 15
+    assert bench.measured_traffic("k_bwd_pass2")[0] is None     # another kernel's digest
 
 
 def test_digest_follows_code_not_comments(tmp_path):
