@@ -194,13 +194,19 @@ constexpr bool kShareFootprint = (DT & ~VCT_WIDE) == VCT_F32;
 // in scalar registers), so each load's offset is the tap's small step inside
 // the level, never a byte offset of 2 GiB or more, whatever the pyramid's size
 // below 4 GiB.  (Pyramids above 4 GiB keep the vector loads.)
+// True when `differs` is false in every active lane of the wave (a hook: a
+// host-emulation build gives each lane its own view).
+#ifndef VCT_WAVE_AGREES
+#define VCT_WAVE_AGREES(differs) (__ballot(differs) == 0)
+#endif
+
 template <int DT, bool SHARE = false>
 __device__ __forceinline__ float4 gather(const TraceArgs& a, const Taps& tp) {
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
     if constexpr (SHARE && (DT & VCT_WIDE) == 0) {
         const uint32_t i0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)tp.idx[0]);
         const int c0 = __builtin_amdgcn_readfirstlane(tp.clamp);
-        if (__ballot(tp.idx[0] != i0 || tp.clamp != c0) == 0) {
+        if (VCT_WAVE_AGREES(tp.idx[0] != i0 || tp.clamp != c0)) {
             // (the steps to the +x / +y / +z taps follow from the base texel and
             // the clamp pattern, so they are wave-uniform too)
             const uint32_t d1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tp.idx[1] - tp.idx[0]));
