@@ -3,7 +3,8 @@
 //   meta.txt   key value lines (grid, G-buffer shape, cone parameters, what to run)
 //   base.bin pos_rough.bin normal.bin cam.bin dirs.bin weights.bin gout.bin material.bin
 // and writes trace.bin, save.bin, count.bin, grad.bin, shade.bin and the
-// decoded levels level_<d>_<l>.bin next to them.
+// decoded levels level_<d>_<l>.bin next to them.  With --abi instead of a
+// directory it runs the argument-validation battery of abi_checks.cpp.
 #include <sys/mman.h>
 
 #include <map>
@@ -17,6 +18,7 @@ void emu_register(const void* p, size_t n, const char* name);
 void emu_clear_allocations();
 void emu_set_limits(uint64_t texels, uint64_t acc);
 void emu_shutdown();
+int run_abi_checks();
 
 namespace {
 
@@ -97,8 +99,14 @@ void check(int rc, const char* what) {
 
 int main(int argc, char** argv) {
     if (argc != 2) {
-        fprintf(stderr, "usage: %s <case dir>\n", argv[0]);
+        fprintf(stderr, "usage: %s <case dir> | --abi\n", argv[0]);
         return 2;
+    }
+    if (strcmp(argv[1], "--abi") == 0) {
+        const int n = run_abi_checks();
+        printf("abi checks passed: %d\n", n);
+        emu_shutdown();
+        return 0;
     }
     g_dir = argv[1];
     {

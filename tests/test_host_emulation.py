@@ -43,8 +43,9 @@ def _build(out_dir, extra):
                            os.path.join(out_dir, src + ".o")]))
     jobs.append(("emu.cpp", [CLANG, *flags, "-include", "emu.h", "-c", os.path.join(EMU, "emu.cpp"), "-o",
                              os.path.join(out_dir, "emu.o")]))
-    jobs.append(("harness.cpp", [CLANG, *flags, "-c", os.path.join(EMU, "harness.cpp"), "-o",
-                                 os.path.join(out_dir, "harness.o")]))
+    for name in ("harness.cpp", "abi_checks.cpp"):
+        jobs.append((name, [CLANG, *flags, "-c", os.path.join(EMU, name), "-o",
+                            os.path.join(out_dir, name[:-4] + ".o")]))
     procs = [(name, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True))
              for name, cmd in jobs]
     for name, p in procs:
@@ -243,3 +244,16 @@ def test_sanitized_build_runs_the_small_cases_clean(sanitized, tmp_path):
              gout=np.ones((1, 5, 3, 8), np.float32), noalloc=True)
     run_case(sanitized, str(tmp_path / "c"), w.base, w.pos_rough, w.normal, w.cam_pos, w.params, backward=False,
              shade=scene_lights(2), material=random_material(w.shape, seed=1))
+
+
+def test_sanitized_build_rejects_bad_arguments_cleanly(sanitized):
+    """The C ABI's validation under AddressSanitizer and
+    UndefinedBehaviorSanitizer: null, negative, non-finite, oversized and
+    overflowing arguments to every entry point give the documented code and
+    a "function: message" error without touching a buffer (the pointers
+    passed are not allocations), and valid size queries clear the error."""
+    r = subprocess.run([sanitized, "--abi"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    n = int(r.stdout.strip().rsplit(":", 1)[1])
+    print(f"abi checks passed: {n}")
+    assert n >= 90
