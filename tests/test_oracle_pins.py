@@ -286,6 +286,26 @@ def test_cone_axes_geometry():
     assert np.allclose(lanes["tmax"][6 * m:], np.minimum(1.0, np.linalg.norm(lv, axis=1)))
 
 
+def test_tangent_frame_handedness_on_slab_scenes():
+    """R10's frame, worked by hand: for n = +z, a = +y, t = a x n = +x and
+    b = n x t = +y; for n = +y, a = +x, t = +z and b = +x.  A narrow cone along
+    the tangent-space axis (0, 1, 0) must therefore reach an opaque slab
+    placed on the world +y side (first case) or +x side (second case), and
+    the cone along (0, -1, 0) must see nothing."""
+    n = 16
+    for nrm, axis in (((0.0, 0.0, 1.0), 1), ((0.0, 1.0, 0.0), 0)):
+        base = np.zeros((n, n, n, 4))
+        sl = [slice(None)] * 3
+        sl[2 - axis] = slice(12, None)                     # world axis -> array axis ([z][y][x])
+        base[tuple(sl)] = (1.0, 0.0, 0.0, 1.0)
+        pr, nr, cam = one_pixel((0.5, 0.5, 0.5), nrm)
+        for sign, lit in ((1.0, True), (-1.0, False)):
+            p = ConeParams(np.array([[0.0, sign, 0.0]], np.float32), np.ones(1, np.float32),
+                           diffuse_aperture=0.05, enable_spec=False, enable_occ=False, max_dist=0.45)
+            d = oracle.render(base, pr, nr, cam, p)[0, 0, 0, 0]
+            assert (d > 0.5) if lit else (d == 0.0), (nrm, sign, d)
+
+
 def test_invalid_pixels_are_zero_and_valid_ones_not():
     w = make_workload("c0", h=16, w=16, n=32)
     nr = w.normal.copy()

@@ -104,6 +104,30 @@ def test_empty_grid_gives_the_direct_phong_term(falloff, first_hit, brdf):
     np.testing.assert_allclose(out[0, 0, 0, 0:3], 0.0, atol=1e-15)
 
 
+def test_direct_term_is_scaled_by_the_light_visibility():
+    """A uniform black absorber (rgb 0, alpha a): the cones gather no colour,
+    so L is the direct term alone, and with one light it must be that
+    light's visibility V = o_min times the empty-grid Lambert + Phong sum;
+    V itself is (1 - a)^K over the K samples of the unmodified occlusion
+    cone toward the light."""
+    n = 16
+    a = 0.05
+    x, nrm, lp, cam = (0.5, 0.25, 0.5), (0.0, 1.0, 0.0), (0.75, 0.5, 0.5), (0.25, 0.5, 0.5)
+    pr, nr, mat, cm = one_pixel(x, nrm, cam, albedo=(0.75, 0.5, 0.25), shininess=32.0)
+    sp = ShadeParams(*lights(lp, idiff=(1.0, 0.5, 0.25), ispec=(0.375, 0.375, 0.375)),
+                     specular_color=(0.875, 0.875, 0.875), occlusion_falloff=False)
+    cp = cone_params(light_pos=lp, alpha_thresh=1.0)
+    empty = oracle.shade(uniform_mips(n, (0.0, 0.0, 0.0, 0.0)), pr, nr, mat, cm, cp, sp)[0, 0, 0]
+    mips = uniform_mips(n, (0.0, 0.0, 0.0, a))
+    out = oracle.shade(mips, pr, nr, mat, cm, cp, sp)[0, 0, 0]
+    lanes = oracle.cone_lanes(pr, nr, cm, cp.replace(diffuse_dirs=np.zeros((0, 3)), diffuse_weights=np.zeros(0),
+                                                       enable_spec=False), n)
+    k = int(oracle.march(mips, lanes, cp)["K"][0])
+    assert k > 3
+    assert out[3] == pytest.approx((1.0 - a) ** k, rel=1e-12)
+    np.testing.assert_allclose(out[0:3], out[3] * empty[0:3], rtol=1e-12)
+
+
 # --- first-hit diffuse cones --------------------------------------------------
 
 def test_first_hit_on_uniform_grids():

@@ -131,3 +131,17 @@ def test_degenerate_outside_and_nonfinite_triangles_produce_nothing():
                     np.float32)
     out = vx.voxelize(tris, np.ones((4, 3), np.float32), N, [LIGHT])
     assert not out.any()
+
+
+def test_snapping_rounds_to_the_nearest_subpixel_ties_to_even():
+    """Reading V6 worked on exact float32 inputs at N = 16 (4096 subpixels per
+    unit): k + 1/4 snaps down, k + 3/4 up, k + 1/2 to the even neighbour, on
+    both sides of the origin."""
+    n = 16
+    frac = [(4.25, 4), (4.75, 5), (4.5, 4), (5.5, 6), (-4.75, -5), (-4.25, -4), (-5.5, -6), (0.5, 0)]
+    coords = np.array([f for f, _ in frac], np.float64) / (vx.SUB * n)
+    tris = np.zeros((len(frac), 3, 3), np.float32)
+    tris[:, 0, 0] = coords
+    u, ok = vx.snap(tris, n)
+    assert ok.all()
+    assert u[:, 0, 0].tolist() == [k for _, k in frac]
