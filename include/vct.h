@@ -342,11 +342,15 @@ int vct_count_shade_samples(const vct_grid* grid, const void* pyramid, const vct
  * else all 0; same fixed-point averaging.
  *   tris       device float32 [n_tris][3][3] vertex positions, world units
  *   colors     device float32 [n_tris][3] triangle colours
- *   base       device float32 [N][N][N][4] premultiplied RGBA, overwritten (a vct_build_mips input)
+ *   base       device float32 [N][N][N][4] premultiplied RGBA, overwritten (a vct_build_mips input);
+ *              while the call runs it also holds the accumulator index of each reached voxel, so it
+ *              must not overlap tris, colors, normal, albedo or the workspace
  *   normal     device float32 [N][N][N][4] average normal, overwritten; or null (no surface attributes)
  *   albedo     device float32 [N][N][N][4] average colour, overwritten; null exactly when normal is
- *   workspace  device, vct_voxelize_workspace_bytes(grid, n_tris, surface) bytes (32 per voxel, 48 more
- *              with surface attributes, about 160 per triangle); surface != 0 sizes it for normal/albedo output
+ *   workspace  device, vct_voxelize_workspace_bytes(grid, n_tris, surface) bytes (room for an accumulator
+ *              of 32 bytes per voxel, 48 more with surface attributes, about 160 per triangle; only the
+ *              accumulators of voxels the mesh reaches are cleared and used); surface != 0 sizes it for
+ *              normal/albedo output
  * Errors: VCT_EINVAL for a bad grid, n_tris outside [0, 2^31), null buffers,
  * only one of normal / albedo given, n_lights outside 0..8, non-finite or
  * negative light parameters or attenuation all 0; VCT_EWORKSPACE if the

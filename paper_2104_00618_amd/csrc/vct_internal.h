@@ -161,7 +161,7 @@ struct EventSink {
     hipEvent_t* ev = nullptr;
     int n = 0, next = 0;
     void mark(hipStream_t s) {
-        if (next < n) hipEventRecord(ev[next++], s);
+        if (next < n) (void)hipEventRecord(ev[next++], s);
     }
 };
 

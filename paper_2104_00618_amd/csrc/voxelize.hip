@@ -25,10 +25,22 @@
 // each 1024) turns the counts into offsets; the raster pass then walks the
 // flattened pixel space, one lane per bounding-box pixel, each lane finding its
 // triangle by a binary search of the offsets.  A wall-sized triangle spreads
-// over many waves and a thousand one-pixel triangles fill a wave.  Per voxel the workspace holds {int64 r, g, b; uint32 count; pad}
-// (32 bytes), and with surface attributes {int64 nx, ny, nz, r, g, b} (48 bytes)
-// more, cleared by a fill kernel (no memset, so the path can be captured in a
-// graph); a resolve pass writes the float32 grids.
+// over many waves and a thousand one-pixel triangles fill a wave.
+//
+// Sparse accumulators: only voxels that a fragment reaches get one (most of a
+// scene's grid is empty).  The output grids are zero-filled first; while the
+// raster pass runs, the alpha word of a reached voxel in `base` holds the
+// index + 1 of its accumulator slot, taken from a counter by the first
+// fragment to claim the voxel (a compare-and-swap to a claim mark, then the
+// index is published; fragments that find the mark read the word again until
+// the index appears, which follows the claim directly).  A slot is {int64
+// r, g, b; uint32 count; uint32 voxel + 1} (32 bytes), and with surface
+// attributes {int64 nx, ny, nz, r, g, b} (48 bytes) more.  Only as many slots
+// as the triangles' bounding boxes hold pixels (at most one per voxel) are
+// cleared, by fill kernels (no memset, so the path can be captured in a
+// graph); the resolve pass walks the used slots and writes their voxels.
+// Which slot a voxel gets depends on arrival order; the integer sums in it do
+// not, so the grids are the same bits whatever the order.
 #include "vct_internal.h"
 
 namespace {
@@ -52,16 +64,40 @@ struct VoxArgs {
 
 struct VoxAcc {
     unsigned long long r, g, b;
-    unsigned int count, pad;
+    unsigned int count, voxel;   // voxel: linear voxel index + 1 (0: slot unused)
 };
+
+constexpr unsigned int kClaimed = 0xffffffffu;   // alpha word of a voxel whose slot is being taken
+constexpr int kMaxSpin = 1 << 24;                // bound of the wait for a claimed voxel's slot
 
 struct SurfAcc {
     unsigned long long n[3], c[3];
 };
 
-__global__ void k_clear(uint4* __restrict__ p, size_t n) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = make_uint4(0u, 0u, 0u, 0u);
+// Zero the output grids (n float4 each; normal and albedo may be null) and the slot counter.
+__global__ void k_clear(uint4* __restrict__ base, uint4* __restrict__ normal, uint4* __restrict__ albedo, size_t n,
+                        unsigned int* __restrict__ counter) {
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        base[i] = z;
+        if (normal) {
+            normal[i] = z;
+            albedo[i] = z;
+        }
+    }
+}
+
+// Zero the first min(*total, cap) slots: no more can be taken than there are
+// bounding-box pixels (each fragment claims at most one voxel) or voxels.
+__global__ void k_clear_slots(uint4* __restrict__ acc, uint4* __restrict__ surf, const unsigned long long* total_p,
+                              unsigned long long cap) {
+    const unsigned long long used = min(*total_p, cap);
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < used * 2; i += stride) acc[i] = z;
+    if (surf)
+        for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < used * 3; i += stride) surf[i] = z;
 }
 
 __device__ __forceinline__ long long floor_div(long long a, long long b) {   // b > 0
@@ -262,7 +298,9 @@ template <bool SURF>
 __global__ __launch_bounds__(256) void k_raster(VoxArgs a, const TriSetup* __restrict__ setup,
                                                 const unsigned long long* __restrict__ offs, long long n_tris,
                                                 const unsigned long long* __restrict__ total_p,
-                                                VoxAcc* __restrict__ acc, SurfAcc* __restrict__ surf) {
+                                                VoxAcc* __restrict__ acc, SurfAcc* __restrict__ surf,
+                                                unsigned int* __restrict__ base_words,
+                                                unsigned int* __restrict__ counter) {
     const unsigned long long total = *total_p;
     const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
     const long long h = kSub / 2;
@@ -315,13 +353,28 @@ __global__ __launch_bounds__(256) void k_raster(VoxArgs a, const TriSetup* __res
                 lb += kk * a.light_color[l][2];
             }
             const size_t vi = (size_t)((v[2] * a.n + v[1]) * a.n + v[0]);
-            VoxAcc* q = acc + vi;
+            // the voxel's slot: its alpha word in base, claimed by the first fragment
+            unsigned int* word = base_words + vi * 4 + 3;
+            unsigned int s = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (s == 0u) {
+                s = atomicCAS(word, 0u, kClaimed);
+                if (s == 0u) {
+                    const unsigned int slot = atomicAdd(counter, 1u);
+                    acc[slot].voxel = (unsigned int)vi + 1u;      // read by the resolve pass only
+                    s = slot + 1u;
+                    atomicExch(word, s);
+                }
+            }
+            for (int spin = 0; s == kClaimed && spin < kMaxSpin; ++spin)
+                s = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (s == kClaimed) continue;   // (not reached: a claim is published right after it is made)
+            VoxAcc* q = acc + (s - 1u);
             atomicAdd(&q->r, to_fixed(lr * r.col[0]));
             atomicAdd(&q->g, to_fixed(lg * r.col[1]));
             atomicAdd(&q->b, to_fixed(lb * r.col[2]));
             atomicAdd(&q->count, 1u);
             if constexpr (SURF) {
-                SurfAcc* u = surf + vi;
+                SurfAcc* u = surf + (s - 1u);
                 for (int i = 0; i < 3; ++i) {
                     atomicAdd(&u->n[i], to_fixed(r.n[i]));
                     atomicAdd(&u->c[i], to_fixed(r.col[i]));
@@ -331,38 +384,35 @@ __global__ __launch_bounds__(256) void k_raster(VoxArgs a, const TriSetup* __res
     }
 }
 
+// One thread per used slot: write its voxel in the output grids (the other
+// voxels keep the zeros of k_clear).
 template <bool SURF>
 __global__ __launch_bounds__(256) void k_resolve(const VoxAcc* __restrict__ acc, const SurfAcc* __restrict__ surf,
-                                                 float4* __restrict__ base, float4* __restrict__ normal,
-                                                 float4* __restrict__ albedo, size_t n) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+                                                 const unsigned int* __restrict__ counter, float4* __restrict__ base,
+                                                 float4* __restrict__ normal, float4* __restrict__ albedo) {
+    const unsigned int used = *counter;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < used; i += (size_t)gridDim.x * blockDim.x) {
         const VoxAcc q = acc[i];
-        float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
-        const float inv = q.count ? 1.0f / ((float)q.count * kFix) : 0.0f;
-        if (q.count)
-            o = make_float4((float)(long long)q.r * inv, (float)(long long)q.g * inv, (float)(long long)q.b * inv,
-                            1.0f);
-        base[i] = o;
+        const size_t v = (size_t)q.voxel - 1u;
+        const float inv = 1.0f / ((float)q.count * kFix);
+        base[v] = make_float4((float)(long long)q.r * inv, (float)(long long)q.g * inv, (float)(long long)q.b * inv,
+                              1.0f);
         if constexpr (SURF) {
-            float4 nn = make_float4(0.f, 0.f, 0.f, 0.f), cc = nn;
-            if (q.count) {                               // empty voxels (most of them) never read their sums
-                const SurfAcc u = surf[i];
-                nn = make_float4((float)(long long)u.n[0] * inv, (float)(long long)u.n[1] * inv,
-                                 (float)(long long)u.n[2] * inv, 1.0f);
-                cc = make_float4((float)(long long)u.c[0] * inv, (float)(long long)u.c[1] * inv,
-                                 (float)(long long)u.c[2] * inv, 1.0f);
-            }
-            normal[i] = nn;
-            albedo[i] = cc;
+            const SurfAcc u = surf[i];
+            normal[v] = make_float4((float)(long long)u.n[0] * inv, (float)(long long)u.n[1] * inv,
+                                    (float)(long long)u.n[2] * inv, 1.0f);
+            albedo[v] = make_float4((float)(long long)u.c[0] * inv, (float)(long long)u.c[1] * inv,
+                                    (float)(long long)u.c[2] * inv, 1.0f);
         }
     }
 }
 
 }  // namespace
 
-// Workspace: the per-voxel accumulators (with surface attributes, their sums
-// follow), then per-triangle setup records, the pixel offsets, the pixel total
-// and the block sums of the offset scan.
+// Workspace: room for one accumulator slot per voxel (with surface attributes,
+// the surface sums of every slot follow), then per-triangle setup records, the
+// pixel offsets, the pixel total, the slot counter and the block sums of the
+// offset scan.
 size_t vct_voxelize_acc_bytes(int n, bool surface) {
     return (size_t)n * n * n * (sizeof(VoxAcc) + (surface ? sizeof(SurfAcc) : 0));
 }
@@ -398,11 +448,13 @@ hipError_t vct_launch_voxelize(const vct_grid* g, const float* tris, const float
     TriSetup* setup = reinterpret_cast<TriSetup*>(w + acc_bytes);
     unsigned long long* offs = reinterpret_cast<unsigned long long*>(setup + n_tris);
     unsigned long long* total = offs + n_tris;
-    unsigned long long* bsum = total + 32;      // (the 256 bytes after the offsets hold the total)
+    unsigned int* counter = reinterpret_cast<unsigned int*>(total + 1);
+    unsigned long long* bsum = total + 32;      // (the 256 bytes after the offsets hold the total and the counter)
     const long long nb = (n_tris + kScanBlock - 1) / kScanBlock;
-    const int fill_blocks = (int)min((acc_bytes / 16 + 255) / 256, (size_t)65536);
+    const int fill_blocks = (int)min((nvox + 255) / 256, (size_t)16384);
     es.mark(st);
-    hipLaunchKernelGGL(k_clear, dim3(fill_blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(ws), acc_bytes / 16);
+    hipLaunchKernelGGL(k_clear, dim3(fill_blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(base),
+                       reinterpret_cast<uint4*>(normal), reinterpret_cast<uint4*>(albedo), nvox, counter);
     es.mark(st);
     if (n_tris > 0) {
         hipLaunchKernelGGL(k_tri_setup, dim3((unsigned)((n_tris + 255) / 256)), dim3(256), 0, st, a, tris, colors,
@@ -410,21 +462,26 @@ hipError_t vct_launch_voxelize(const vct_grid* g, const float* tris, const float
         hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nb), dim3(256), 0, st, offs, n_tris, bsum);
         hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, st, bsum, nb, total);
         hipLaunchKernelGGL(k_block_offsets, dim3((unsigned)nb), dim3(256), 0, st, offs, n_tris, bsum);
+        hipLaunchKernelGGL(k_clear_slots, dim3(1024), dim3(256), 0, st, reinterpret_cast<uint4*>(acc),
+                           reinterpret_cast<uint4*>(surf), total, (unsigned long long)nvox);
+        unsigned int* words = reinterpret_cast<unsigned int*>(base);
         if (surface)
-            hipLaunchKernelGGL(k_raster<true>, dim3(2048), dim3(256), 0, st, a, setup, offs, n_tris, total, acc, surf);
+            hipLaunchKernelGGL(k_raster<true>, dim3(2048), dim3(256), 0, st, a, setup, offs, n_tris, total, acc, surf,
+                               words, counter);
         else
             hipLaunchKernelGGL(k_raster<false>, dim3(2048), dim3(256), 0, st, a, setup, offs, n_tris, total, acc,
-                               surf);
+                               surf, words, counter);
     }
     es.mark(st);
-    const int res_blocks = (int)min((nvox + 255) / 256, (size_t)65536);
-    if (surface)
-        hipLaunchKernelGGL(k_resolve<true>, dim3(res_blocks), dim3(256), 0, st, acc, surf,
-                           reinterpret_cast<float4*>(base), reinterpret_cast<float4*>(normal),
-                           reinterpret_cast<float4*>(albedo), nvox);
-    else
-        hipLaunchKernelGGL(k_resolve<false>, dim3(res_blocks), dim3(256), 0, st, acc, surf,
-                           reinterpret_cast<float4*>(base), nullptr, nullptr, nvox);
+    if (n_tris > 0) {
+        if (surface)
+            hipLaunchKernelGGL(k_resolve<true>, dim3(1024), dim3(256), 0, st, acc, surf, counter,
+                               reinterpret_cast<float4*>(base), reinterpret_cast<float4*>(normal),
+                               reinterpret_cast<float4*>(albedo));
+        else
+            hipLaunchKernelGGL(k_resolve<false>, dim3(1024), dim3(256), 0, st, acc, surf, counter,
+                               reinterpret_cast<float4*>(base), nullptr, nullptr);
+    }
     es.mark(st);
     return hipGetLastError();
 }

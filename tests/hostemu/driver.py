@@ -70,3 +70,24 @@ def run_case(binary, d, base, pr, nr, cam, p, dtype="f32", levels=None, aniso=Fa
         res["levels"] = [[np.fromfile(f"{d}/level_{di}_{l}.bin", np.float32).reshape((n >> l,) * 3 + (4,))
                           for l in range(levels)] for di in range(6 if aniso else 1)]
     return res
+
+
+def run_voxelize(binary, d, tris, colors, n, lights, ambient=0.1, diffuse=1.0, surface=True, timeout=600):
+    """vct_voxelize through the checked build; returns base (and normal, albedo) as [n, n, n, 4]."""
+    os.makedirs(d, exist_ok=True)
+    tris = np.ascontiguousarray(tris, np.float32).reshape(-1, 3, 3)
+    L = np.array([[*pos, *col, *att] for pos, col, att in lights], np.float32).reshape(-1, 9)
+    tris.tofile(f"{d}/tris.bin")
+    np.ascontiguousarray(colors, np.float32).tofile(f"{d}/colors.bin")
+    L.tofile(f"{d}/lights.bin")
+    with open(f"{d}/vmeta.txt", "w") as f:
+        for k, v in dict(n=n, n_tris=len(tris), surface=int(surface), n_lights=len(L), ambient=ambient,
+                         diffuse=diffuse).items():
+            f.write(f"{k} {float(v)!r}\n")
+    r = subprocess.run([binary, "--voxelize", d], capture_output=True, text=True, timeout=timeout)
+    if r.returncode != 0 or "EMU OK" not in r.stdout:
+        raise RuntimeError(f"checked build failed ({r.returncode}):\n{r.stdout[-2000:]}\n{r.stderr[-4000:]}")
+    out = [np.fromfile(f"{d}/vox_base.bin", np.float32).reshape(n, n, n, 4)]
+    if surface:
+        out += [np.fromfile(f"{d}/vox_{k}.bin", np.float32).reshape(n, n, n, 4) for k in ("normal", "albedo")]
+    return out

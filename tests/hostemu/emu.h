@@ -121,6 +121,22 @@ inline T atomicAdd(T* p, T v) {
     *p = old + v;
     return old;
 }
+template <typename T>
+inline T atomicCAS(T* p, T cmp, T v) {
+    const T old = *p;
+    if (old == cmp) *p = v;
+    return old;
+}
+template <typename T>
+inline T atomicExch(T* p, T v) {
+    const T old = *p;
+    *p = v;
+    return old;
+}
+#ifndef __HIP_MEMORY_SCOPE_AGENT
+#define __HIP_MEMORY_SCOPE_AGENT 3
+#endif
+#define __hip_atomic_load(p, order, scope) (*(p))
 
 // ---- memory checks
 void emu_check_texel(uint64_t idx, const char* site);

@@ -4,7 +4,8 @@
 //   base.bin pos_rough.bin normal.bin cam.bin dirs.bin weights.bin gout.bin material.bin
 // and writes trace.bin, save.bin, count.bin, grad.bin, shade.bin and the
 // decoded levels level_<d>_<l>.bin next to them.  With --abi instead of a
-// directory it runs the argument-validation battery of abi_checks.cpp.
+// directory it runs the argument-validation battery of abi_checks.cpp, and
+// with --voxelize <dir> the voxelization case of voxelize_case.cpp.
 #include <sys/mman.h>
 
 #include <map>
@@ -19,6 +20,7 @@ void emu_clear_allocations();
 void emu_set_limits(uint64_t texels, uint64_t acc);
 void emu_shutdown();
 int run_abi_checks();
+int run_voxelize_case(const char* dir);
 
 namespace {
 
@@ -98,8 +100,14 @@ void check(int rc, const char* what) {
 }  // namespace
 
 int main(int argc, char** argv) {
+    if (argc == 3 && strcmp(argv[1], "--voxelize") == 0) {
+        run_voxelize_case(argv[2]);
+        emu_shutdown();
+        printf("EMU OK\n");
+        return 0;
+    }
     if (argc != 2) {
-        fprintf(stderr, "usage: %s <case dir> | --abi\n", argv[0]);
+        fprintf(stderr, "usage: %s <case dir> | --abi | --voxelize <case dir>\n", argv[0]);
         return 2;
     }
     if (strcmp(argv[1], "--abi") == 0) {
