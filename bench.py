@@ -544,10 +544,32 @@ def main():
              "trace_save_ms": asave_ms, "trace_backward_saved_ms": abwd_ms,
              "fwd_bwd_ms_per_frame": amips_ms + asave_ms + abwd_ms,
              "backward_slowdown_vs_isotropic": abwd_ms / bwd_ms}
-    del pa, aws
+    del pa
     log(f"anisotropic: mips {amips_ms:.3f} ms, trace {atrace_ms:.3f} ms ({asamples} samples, "
         f"{atrace_ms / fwd_ms:.2f}x the isotropic trace); trace_save {asave_ms:.3f} ms, "
         f"backward {abwd_ms:.3f} ms ({abwd_ms / bwd_ms:.2f}x the isotropic backward)")
+    if args.dtype == "f32" and not args.no_compare:
+        # the same anisotropic frame with float16 storage (1.6x the isotropic
+        # bytes, three directions read per level above 0)
+        gh = vct.Grid(w.n, dtype="f16", anisotropic=True)
+        ph = torch.empty(vct.pyramid_bytes(gh), dtype=torch.uint8, device=dev)
+        hmips_ms = timed(lambda: vct.build_mips(base, gh, ph), args.steps)
+        htrace_ms = timed(lambda: vct.trace(ph, gh, pr, nr, cam, w.params, out), args.steps)
+        hsave_ms = timed(lambda: vct.trace_save(ph, gh, pr, nr, cam, w.params, out, state), args.steps)
+        hbwd_ms = timed(lambda: vct.trace_backward_saved(ph, gh, pr, nr, cam, w.params, state, gout, aws, gbase),
+                        args.steps)
+        aniso["f16_storage"] = {
+            "pyramid_bytes": int(ph.numel()), "build_mips_ms": hmips_ms, "trace_ms": htrace_ms,
+            "fwd_ms_per_frame": hmips_ms + htrace_ms, "trace_save_ms": hsave_ms,
+            "trace_backward_saved_ms": hbwd_ms, "fwd_bwd_ms_per_frame": hmips_ms + hsave_ms + hbwd_ms,
+            "trace_speedup_vs_f32": atrace_ms / htrace_ms,
+            "fwd_speedup_vs_f32": (amips_ms + atrace_ms) / (hmips_ms + htrace_ms),
+            "fwd_bwd_speedup_vs_f32": (amips_ms + asave_ms + abwd_ms) / (hmips_ms + hsave_ms + hbwd_ms)}
+        del ph
+        log(f"anisotropic f16 storage: mips {hmips_ms:.3f} ms, trace {htrace_ms:.3f} ms "
+            f"({atrace_ms / htrace_ms:.2f}x the f32 trace); training step {hmips_ms + hsave_ms + hbwd_ms:.3f} ms "
+            f"({aniso['f16_storage']['fwd_bwd_speedup_vs_f32']:.2f}x)")
+    del aws
 
     texel_bytes = 16 if args.dtype == "f32" else 8
     trace_bytes = samples * 16 * texel_bytes + npix * 64
