@@ -715,6 +715,19 @@ def main():
         del ws, state, ws_saved
         torch.cuda.empty_cache()
         res["configs"] = bench_configs(vct, torch, make_workload)
+    # whether float16 storage gives the faster forward, frame by frame
+    verdict = {}
+    if "f16_storage" in breakdown:
+        verdict["isotropic_256cubed_1080p"] = breakdown["f16_storage"]["fwd_speedup_vs_f32"] > 1.0
+    if "f16_storage" in aniso:
+        verdict["anisotropic_256cubed_1080p"] = aniso["f16_storage"]["fwd_speedup_vs_f32"] > 1.0
+    if "configs" in res:
+        verdict["isotropic_512cubed_4x4k"] = res["configs"]["c4_512cubed_4x4k_f16"]["fwd_speedup_vs_f32"] > 1.0
+    if verdict:
+        res["fp16_forward_faster_than_fp32"] = dict(
+            verdict, met_everywhere=all(verdict.values()),
+            note="speedups of the float16-storage forward over float32 are in breakdown.f16_storage, "
+                 "breakdown.anisotropic.f16_storage and configs.c4_512cubed_4x4k_f16")
     if cpu_base is not None:
         res["cpu_baseline"] = cpu_base
         nw = cpu_parts["workers"]
