@@ -282,16 +282,16 @@ __device__ __forceinline__ void hold(Held& h, uint32_t k, int kc, uint32_t dx, u
     h.qv = qv;
 }
 
-// Emit one level's tap gradients of the wave.  Lanes whose samples share the
+// The group loop of one level's emission.  Lanes whose samples share the
 // same base texel and clamp pattern have the same 8 taps; each such group is
-// summed across the wave (fixed order) and 32 lanes (8 for alpha only) then
-// add its taps x channels as fixed-point integers: to the workgroup's LDS
-// table for the coarse levels (side <= 8), to the global accumulator otherwise.
-template <bool ALPHA_ONLY, bool HOLD = false>
-__device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, float wl, const float gs[4],
-                                           const EmitLane& e, int E, int lev_shift,
-                                           unsigned long long* __restrict__ acc, unsigned long long* small,
-                                           uint32_t small_off, int lane, Held* held = nullptr) {
+// summed across the wave (fixed order), after which 32 lanes (8 for alpha
+// only) hold its taps x channels.  sink(k, kc, lev, dx, dy, dz, sum, emitter,
+// ch) receives each group: its base texel, clamp pattern, level and index
+// steps (wave-uniform), the lane's sum, whether the lane emits it, and its
+// channel.
+template <bool ALPHA_ONLY, typename Sink>
+__device__ __forceinline__ void emit_groups(bool live, const LevelGeom& geo, float wl, const float gs[4],
+                                            const EmitLane& e, int lane, Sink&& sink) {
     unsigned long long mask = __ballot(live);
     if (mask == 0) return;   // (wave-uniform: no lane emits on this level)
     float wp[8];
@@ -322,6 +322,22 @@ __device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, floa
         const uint32_t dx = (uint32_t)__builtin_amdgcn_readlane((int)geo.dx, leader);
         const uint32_t dy = (uint32_t)__builtin_amdgcn_readlane((int)geo.dy, leader);
         const uint32_t dz = (uint32_t)__builtin_amdgcn_readlane((int)geo.dz, leader);
+        sink(k, kc, lev, dx, dy, dz, sum, emitter, ch);
+        mask &= ~gm;
+    }
+}
+
+// Emit one level's tap gradients of the wave as fixed-point integers: to the
+// workgroup's LDS table for the coarse levels (side <= 8), to the global
+// accumulator otherwise.
+template <bool ALPHA_ONLY, bool HOLD = false>
+__device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, float wl, const float gs[4],
+                                           const EmitLane& e, int E, int lev_shift,
+                                           unsigned long long* __restrict__ acc, unsigned long long* small,
+                                           uint32_t small_off, int lane, Held* held = nullptr) {
+    emit_groups<ALPHA_ONLY>(live, geo, wl, gs, e, lane,
+                            [&](uint32_t k, int kc, int lev, uint32_t dx, uint32_t dy, uint32_t dz, float sum,
+                                bool emitter, int ch) {
         const long long qv = emitter ? fixed_point(sum, E - lev_shift * lev) : 0;
         if constexpr (HOLD) {
             // (the two levels of a sample differ in parity, and a level keeps
@@ -333,8 +349,29 @@ __device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, floa
         } else {
             add_fixed(k + (dx & e.xm) + (dy & e.ym) + (dz & e.zm), ch, qv, acc, small, small_off);
         }
-        mask &= ~gm;
-    }
+    });
+}
+
+// Anisotropic pyramids above level 0, when every emitting lane of the wave has
+// the same cone axis (so the same direction weights w_a^2 and direction
+// signs): the three directions' sums are the axis-free sum times w_a^2, so
+// each group runs one butterfly and adds it at the three directions' offsets.
+template <bool ALPHA_ONLY>
+__device__ __forceinline__ void emit_level_dirs(bool live, const LevelGeom& geo, float wl, const float gs[4],
+                                                const EmitLane& e, int E, const float wt[3], const int dsel[3],
+                                                const DirTable* D, unsigned long long* __restrict__ acc,
+                                                unsigned long long* small, uint32_t small_off, int lane) {
+    emit_groups<ALPHA_ONLY>(live, geo, wl, gs, e, lane,
+                            [&](uint32_t k, int, int lev, uint32_t dx, uint32_t dy, uint32_t dz, float sum,
+                                bool emitter, int ch) {
+        const uint32_t tap = k + (dx & e.xm) + (dy & e.ym) + (dz & e.zm);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            if (wt[ax] == 0.0f) continue;
+            const long long qv = emitter ? fixed_point(sum * wt[ax], E) : 0;
+            add_fixed(tap + D->delta[dsel[ax]][lev], ch, qv, acc, small, small_off);
+        }
+    });
 }
 
 // One level's emission.  Isotropic pyramids: level l's integers carry the
@@ -342,7 +379,9 @@ __device__ __forceinline__ void emit_level(bool live, const LevelGeom& geo, floa
 // Anisotropic pyramids: scale 2^E at every level (their mip adjoint is not a
 // fixed factor); above level 0 the sample read the three directions of its
 // axis signs with weights w_a^2, so each gets the gradient with that weight at
-// its direction's offset (a separate group key, since the base index moves).
+// its direction's offset: with one butterfly per group when the wave's lanes
+// share their axis (emit_level_dirs), else one per direction (a separate group
+// key each, since the base index moves).
 template <bool ALPHA_ONLY, bool ANISO, bool HOLD>
 __device__ __forceinline__ void emit_dirs(const TraceArgs& a, const DirTable* D, const Cone& c, bool live,
                                           const LevelGeom& geo, float wl, const float gs[4], const EmitLane& e, int E,
@@ -354,6 +393,27 @@ __device__ __forceinline__ void emit_dirs(const TraceArgs& a, const DirTable* D,
         const bool base_level = live && geo.level == 0;
         emit_level<ALPHA_ONLY>(base_level, geo, wl, gs, e, E, 0, acc, small, small_off, lane);
         const float W[3] = {c.Wx, c.Wy, c.Wz};
+        const bool up = live && !base_level;
+        const unsigned long long upm = __ballot(up);
+        if (upm == 0) return;
+        const int ld = __builtin_ctzll(upm);
+        const float Wl[3] = {__int_as_float(__builtin_amdgcn_readlane(__float_as_int(W[0]), ld)),
+                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(W[1]), ld)),
+                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(W[2]), ld))};
+        const bool same = __float_as_int(W[0]) == __float_as_int(Wl[0]) &&
+                          __float_as_int(W[1]) == __float_as_int(Wl[1]) &&
+                          __float_as_int(W[2]) == __float_as_int(Wl[2]);
+        if (__ballot(up && !same) == 0) {
+            float wt[3];
+            int dsel[3];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                wt[ax] = Wl[ax] * Wl[ax] * a.inv_scale2;
+                dsel[ax] = 2 * ax + (Wl[ax] < 0.0f ? 1 : 0);
+            }
+            emit_level_dirs<ALPHA_ONLY>(up, geo, wl, gs, e, E, wt, dsel, D, acc, small, small_off, lane);
+            return;
+        }
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             const float wt = W[ax] * W[ax] * a.inv_scale2;

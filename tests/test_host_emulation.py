@@ -138,19 +138,30 @@ def test_emulated_tiny_and_partial_pyramids(checked, tmp_path, n, levels, shape)
     _case(checked, tmp_path, base, pr, nr, cam, _params(), f"{n}^3 levels {levels} {shape}", levels=levels)
 
 
-@pytest.mark.parametrize("n", [2, 8])
-def test_emulated_anisotropic_pyramids(checked, tmp_path, n):
+@pytest.mark.parametrize("n,flat", [(2, False), (8, False), (8, True)])
+def test_emulated_anisotropic_pyramids(checked, tmp_path, n, flat):
+    """Anisotropic forward, saved forward, backward and the allocation-free
+    backward.  flat: every pixel on one plane with one normal, so the diffuse
+    cones of a wave share their axis and the scatter pass sums each group once
+    for the three directions."""
     base = random_grid(n, seed=30 + n, alpha_max=0.35)
     pr, nr, cam = random_gbuffer(1, 8, 8, seed=40 + n, n=max(n, 8))
+    if flat:
+        g = np.linspace(0.2, 0.8, 8, dtype=np.float32)
+        pr[0, :, :, 0], pr[0, :, :, 1] = np.meshgrid(g, g)
+        pr[0, :, :, 2] = 0.3
+        nr[0, :, :, 0:3] = (0.0, 0.0, 1.0)
+        nr[0, :, :, 3] = 1.0
     p = _params()
     gout = np.random.default_rng(n).normal(size=(1, 8, 8, 8)).astype(np.float32)
     am = va.build_aniso_mips(base)
     ref, info = va.trace_aniso(am, pr, nr, cam, p, return_info=True)
     gout[info["ambiguous"]] = 0.0
     res = run_case(checked, str(tmp_path), base, pr, nr, cam, p, aniso=True, gout=gout, noalloc=True)
-    _check_forward(res, ref, info["ambiguous"], f"anisotropic {n}^3")
+    label = f"anisotropic {n}^3{' flat' if flat else ''}"
+    _check_forward(res, ref, info["ambiguous"], label)
     assert np.array_equal(res["grad_noalloc"].view(np.uint32), res["grad"].view(np.uint32))
-    _check_grad(res["grad"], va.trace_backward_aniso(am, pr, nr, cam, p, gout), f"anisotropic {n}^3")
+    _check_grad(res["grad"], va.trace_backward_aniso(am, pr, nr, cam, p, gout), label)
 
 
 def test_emulated_shading_matches_oracle(checked, tmp_path):
