@@ -116,8 +116,10 @@ __device__ __forceinline__ Pass1Out pass1_march(const TraceArgs& a, const LevelT
         // isotropic ones they measured flat)
         float4 s = sample_at<DT, ANISO, ANISO && kShareFootprint<DT>>(a, T, c, t, lam, D);
         float tr = 1.0f - r.A;
-        // |T_{k-1}| / |T_k| for every sample k that follows another (T_k >= 2^-24 here)
-        if (k > 0) r.SQ += fabsf(r.Tlast) / fabsf(tr);
+        // |T_{k-1}| / |T_k| for every sample k that follows another (T_k >= 2^-24
+        // here, so the hardware reciprocal is within 1 ulp; the bound's 1.001
+        // covers that as it covers the rounding of the sums)
+        if (k > 0) r.SQ += fabsf(r.Tlast) * __builtin_amdgcn_rcpf(fabsf(tr));
         acc_colour(r.C[0], tr, s.x);
         acc_colour(r.C[1], tr, s.y);
         acc_colour(r.C[2], tr, s.z);
