@@ -791,7 +791,7 @@ hipError_t vct_launch_trace_save(const TraceArgs& a, int dtype, float* out, void
         es.mark(s);
         float4* o = reinterpret_cast<float4*>(out);
         LaneState* st = reinterpret_cast<LaneState*>(state);
-        vct_dispatch_dt(dtype, a.wide != 0, [&](auto dt) {
+        (void)vct_dispatch_dt(dtype, a.wide != 0, [&](auto dt) {   // (launch errors: hipGetLastError below)
             constexpr int DT = decltype(dt)::value;
             if (a.aniso)
                 hipLaunchKernelGGL((k_trace_save<DT, true>), dim3(a.n_tiles), dim3(kThreads), 0, s, a, o, st);

@@ -272,7 +272,7 @@ hipError_t vct_launch_bounce(const TraceArgs& a, int dtype, const float* base, c
                  reinterpret_cast<const float4*>(albedo), reinterpret_cast<float4*>(out), list, total, queue, lg};
     es.mark(st);
     if (a.n_diffuse > 0) {
-        vct_dispatch_dt(dtype, a.wide != 0, [&](auto dt) {
+        (void)vct_dispatch_dt(dtype, a.wide != 0, [&](auto dt) {   // (launch errors: hipGetLastError below)
             launch_gather<decltype(dt)::value>(a, b, st);
             return hipSuccess;
         });
