@@ -111,10 +111,10 @@ __device__ __forceinline__ Pass1Out pass1_march(const TraceArgs& a, const LevelT
         if (!t_within(t, c.tmax) || !(r.A < a.alpha_thresh)) break;
         float d = fmaxf(c.two_tan * t.hi, a.voxel);
         float lam = lod_of(a, d);
-        // (wave-uniform footprint reads on anisotropic float32 pyramids: the
-        // forward that keeps lane states ran 4.9 -> 4.0 ms with them; on
-        // isotropic ones they measured flat)
-        float4 s = sample_at<DT, ANISO, ANISO && kShareFootprint<DT>>(a, T, c, t, lam, D);
+        // (wave-uniform footprint reads on float32 pyramids: the forward that
+        // keeps lane states ran 4.9 -> 4.0 ms with them on anisotropic
+        // pyramids, 1.99 -> 1.96 ms on isotropic ones)
+        float4 s = sample_at<DT, ANISO, kShareFootprint<DT>>(a, T, c, t, lam, D);
         float tr = 1.0f - r.A;
         // |T_{k-1}| / |T_k| for every sample k that follows another (T_k >= 2^-24
         // here, so the hardware reciprocal is within 1 ulp; the bound's 1.001
