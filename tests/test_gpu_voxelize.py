@@ -71,6 +71,37 @@ def test_voxelize_is_deterministic_in_any_triangle_order():
     assert np.array_equal(a.view(np.uint32), c.view(np.uint32))
 
 
+def test_voxelize_stacked_copies_contend_for_the_same_slots():
+    """1,024 coincident copies of one quad, each copy with its own colour:
+    every voxel the quad reaches is claimed by the fragments of all 1,024
+    copies at once.  Occupancy, colours and normals match the oracle, the
+    colour is that of one copy times the mean colour of the copies, and two
+    runs agree bit for bit."""
+    n, k = 32, 1024
+    quad = np.array([[[0.1, 0.2, 0.45], [0.9, 0.2, 0.45], [0.9, 0.85, 0.55]],
+                     [[0.1, 0.2, 0.45], [0.9, 0.85, 0.55], [0.1, 0.85, 0.55]]], np.float32)
+    cols = np.random.default_rng(7).uniform(0.1, 1.0, size=(k, 3)).astype(np.float32)
+    tris = np.tile(quad, (k, 1, 1))
+    stacked_cols = np.repeat(cols, 2, axis=0)
+    a = gpu_voxelize(tris, stacked_cols, n, surface=True)
+    b = gpu_voxelize(tris, stacked_cols, n, surface=True)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    ref, cnt, rn, ra = vx.voxelize(tris, stacked_cols, n, LIGHTS, return_counts=True, return_surface=True)
+    one = vx.voxelize(quad, np.ones((2, 3), np.float32), n, LIGHTS)
+    occ = cnt > 0
+    assert occ.sum() > 200 and cnt[occ].min() >= k
+    np.testing.assert_array_equal(a[0][..., 3], occ.astype(np.float32))
+    mean = cols.astype(np.float64).mean(0)
+    np.testing.assert_allclose(ref[occ, 0:3], one[occ, 0:3] * mean, rtol=1e-12)
+    err = np.abs(a[0][..., 0:3] - ref[..., 0:3]).max() / np.abs(ref[..., 0:3]).max()
+    en = np.abs(a[1][..., 0:3] - rn[..., 0:3]).max()
+    ea = np.abs(a[2][..., 0:3] - ra[..., 0:3]).max()
+    print(f"{k} stacked quads at {n}^3: {int(occ.sum())} voxels, {int(cnt.max())} fragments at most; colour max rel "
+          f"{err:.2e}, normal {en:.2e}, albedo {ea:.2e}", flush=True)
+    assert err <= 1e-5 and en <= 1e-6 and ea <= 1e-6
+
+
 def test_voxelized_grid_feeds_mips_and_trace():
     """Mesh -> voxelize -> build_mips -> trace on the GPU against the same
     pipeline in the oracles."""
