@@ -71,6 +71,27 @@ def test_voxelize_is_deterministic_in_any_triangle_order():
     assert np.array_equal(a.view(np.uint32), c.view(np.uint32))
 
 
+@pytest.mark.parametrize("n_tris", [4096, 4097])
+def test_voxelize_offset_scan_either_side_of_one_workgroup(n_tris):
+    """Up to 4,096 triangles the offset scan runs in one workgroup, above it in
+    three phases: a mesh of either size (small random triangles, a tenth of
+    them without pixels) matches the oracle."""
+    rng = np.random.default_rng(n_tris)
+    ctr = rng.uniform(0.0, 1.0, size=(n_tris, 1, 3))
+    tris = (ctr + rng.uniform(-0.03, 0.03, size=(n_tris, 3, 3))).astype(np.float32)
+    tris[::10, 1] = tris[::10, 0]                           # degenerate: no pixels
+    cols = rng.uniform(0.1, 1.0, size=(n_tris, 3)).astype(np.float32)
+    got = gpu_voxelize(tris, cols, 64, surface=True)
+    ref, cnt, rn, ra = vx.voxelize(tris, cols, 64, LIGHTS, return_counts=True, return_surface=True)
+    np.testing.assert_array_equal(got[0][..., 3], (cnt > 0).astype(np.float32))
+    err = np.abs(got[0][..., :3] - ref[..., :3]).max() / np.abs(ref[..., :3]).max()
+    en = np.abs(got[1][..., :3] - rn[..., :3]).max()
+    ea = np.abs(got[2][..., :3] - ra[..., :3]).max()
+    print(f"voxelize {n_tris} triangles at 64^3: {int((cnt > 0).sum())} voxels; colour max rel {err:.2e}, "
+          f"normal {en:.2e}, albedo {ea:.2e}", flush=True)
+    assert err <= 1e-5 and en <= 1e-6 and ea <= 1e-6
+
+
 def test_voxelize_stacked_copies_contend_for_the_same_slots():
     """1,024 coincident copies of one quad, each copy with its own colour:
     every voxel the quad reaches is claimed by the fragments of all 1,024
@@ -120,6 +141,35 @@ def test_voxelized_grid_feeds_mips_and_trace():
     e = range_errors(out, ref, ~info["ambiguous"].reshape(-1))
     print(f"voxelize -> trace 64^3: {fmt(e)}", flush=True)
     assert worst(e)[0] <= 1e-5
+
+
+@pytest.mark.parametrize("n,n_tris", [(16, 0), (16, 1), (64, 1)])
+def test_voxelize_clears_every_output_grid_whatever_it_held(n, n_tris):
+    """The three output grids start filled with garbage: the base grid is
+    zero-filled before the raster pass, normal and albedo by workgroups of the
+    raster launch (by the first fill when there are no triangles).  Every voxel
+    no fragment reaches is zero in all three, and the reached ones match the
+    oracle."""
+    if n_tris:
+        tris, cols = mesh(5)
+    else:
+        tris, cols = np.zeros((0, 3, 3), np.float32), np.zeros((0, 3), np.float32)
+    grids = [torch.full((n, n, n, 4), v, dtype=torch.float32, device=DEV) for v in (5.0, float("nan"), -3.0)]
+    vct.voxelize(dev(tris), dev(cols), vct.Grid(n), LIGHTS, base=grids[0], surface=True, normal=grids[1],
+                 albedo=grids[2])
+    torch.cuda.synchronize()
+    got = [g.cpu().numpy() for g in grids]
+    ref, cnt, rn, ra = vx.voxelize(tris, cols, n, LIGHTS, return_counts=True, return_surface=True)
+    occ = cnt > 0
+    assert (occ.sum() > 100) == bool(n_tris)
+    for g in got:
+        assert (g[~occ] == 0).all()
+    np.testing.assert_array_equal(got[0][..., 3], occ.astype(np.float32))
+    if n_tris:
+        err = np.abs(got[0][..., :3] - ref[..., :3]).max() / np.abs(ref[..., :3]).max()
+        en = np.abs(got[1][..., :3] - rn[..., :3]).max()
+        ea = np.abs(got[2][..., :3] - ra[..., :3]).max()
+        assert err <= 1e-5 and en <= 1e-6 and ea <= 1e-6
 
 
 def test_voxelize_empty_and_nonfinite_inputs():

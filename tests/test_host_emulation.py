@@ -213,13 +213,14 @@ def test_emulated_bounce_matches_oracle(checked, tmp_path, kind, aniso):
     assert np.array_equal(got[same].view(np.uint32), base[same].view(np.uint32))
 
 
-@pytest.mark.parametrize("surface", [True, False])
-def test_emulated_voxelization_matches_oracle(checked, sanitized, tmp_path, surface):
+@pytest.mark.parametrize("surface,small", [(True, 0), (False, 0), (True, 4200)])
+def test_emulated_voxelization_matches_oracle(checked, sanitized, tmp_path, surface, small):
     """vct_voxelize through the checked build (setup, offset scan, the raster
     pass that claims one accumulator slot per reached voxel, the resolve of
     the used slots) and its AddressSanitizer build, on the Cornell mesh plus
     random triangles at 16^3: occupancy bit-exact, colours within 1e-5 of the
-    largest, normals and albedo within 1e-6."""
+    largest, normals and albedo within 1e-6.  With 4,200 more small triangles
+    the mesh passes the one-workgroup scan's 4,096 and takes the blocked one."""
     from oracle import vct_voxelize as vx
     from scenes.mesh import cornell_mesh
     n = 16
@@ -227,6 +228,11 @@ def test_emulated_voxelization_matches_oracle(checked, sanitized, tmp_path, surf
     rng = np.random.default_rng(11)
     tris = np.concatenate([tris, rng.uniform(-0.1, 1.1, size=(24, 3, 3)).astype(np.float32)])
     cols = np.concatenate([cols, rng.uniform(0, 1, size=(24, 3)).astype(np.float32)])
+    if small:
+        ctr = rng.uniform(0.0, 1.0, size=(small, 1, 3))
+        tris = np.concatenate([tris, (ctr + rng.uniform(-0.06, 0.06, size=(small, 3, 3))).astype(np.float32)])
+        cols = np.concatenate([cols, rng.uniform(0, 1, size=(small, 3)).astype(np.float32)])
+        assert len(tris) > 4096
     lights = [((0.5, 0.95, 0.5), (1.0, 1.0, 1.0), (1.0, 0.5, 0.25)), ((0.2, 0.3, 0.8), (0.4, 0.3, 0.2), (1, 0, 0))]
     ref = vx.voxelize(tris, cols, n, lights, return_surface=True)
     for build in (checked, sanitized):
