@@ -108,18 +108,33 @@ def kernel_source_digest(csrc=None, kernel="k_bwd_pass2"):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel="k_bwd_pass2"):
-    """(bytes per launch, note) of a kernel from the committed profile, or (None, reason)."""
+def _traffic_line(kernel):
+    """The committed profile's traffic line of a kernel (a regex match), or (None, reason)."""
     try:
         text = open(PROFILE).read()
     except OSError:
         return None, "no profile"
-    m = re.search(r"traffic " + kernel + r": fetch_bytes=(\d+) write_bytes=(\d+) sources=([0-9a-f]+)", text)
+    m = re.search(r"traffic " + kernel + r": fetch_bytes=(\d+) write_bytes=(\d+)(?: l2_hit=([0-9.]+))? "
+                  r"sources=([0-9a-f]+)", text)
     if not m:
         return None, "no traffic line in the profile"
-    if m.group(3) != kernel_source_digest(kernel=kernel):
+    if m.group(4) != kernel_source_digest(kernel=kernel):
         return None, "kernel sources changed since the counters were taken"
+    return m, None
+
+
+def measured_traffic(kernel="k_bwd_pass2"):
+    """(bytes per launch, note) of a kernel from the committed profile, or (None, reason)."""
+    m, why = _traffic_line(kernel)
+    if m is None:
+        return None, why
     return int(m.group(1)) + int(m.group(2)), f"FETCH_SIZE + WRITE_SIZE (calibrated) from {os.path.basename(PROFILE)}"
+
+
+def measured_l2_hit(kernel="k_bwd_pass2"):
+    """L2 hit rate TCC_HIT / (TCC_HIT + TCC_MISS) of a kernel from the committed profile, or None."""
+    m, _ = _traffic_line(kernel)
+    return float(m.group(3)) if (m is not None and m.group(3)) else None
 
 
 def measured_pass2_traffic():
@@ -602,7 +617,9 @@ def main():
             # scalar cache: a cache-traffic figure, not a fraction of HBM bandwidth
             "logical_tap_GBps": trace_gbs, "logical_tap_bytes_over_hbm_peak_cache_served": trace_gbs / HBM_PEAK_GBS,
             "hbm_bytes_per_launch": tr_traffic, "hbm_bytes_note": tr_note,
-            "hbm_frac_of_peak": None if tr_traffic is None else tr_traffic / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "hbm_GBps": None if tr_traffic is None else tr_traffic / (fwd_ms * 1e-3) / 1e9,
+            "hbm_frac_of_peak": None if tr_traffic is None else tr_traffic / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "l2_hit_rate": measured_l2_hit("k_trace") if tr_traffic is not None else None},
     }
 
     if not args.no_compare and args.dtype == "f32":
@@ -655,6 +672,8 @@ def main():
                 "peak_nonpacked": ALU_NONPACKED_TFLOPS, "frac_nonpacked": p2_tflops / ALU_NONPACKED_TFLOPS,
                 "traffic_frac_of_hbm_peak": None if p2_traffic is None else
                 p2_traffic / (p2_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "traffic_GBps": None if p2_traffic is None else p2_traffic / (p2_ms * 1e-3) / 1e9,
+                "l2_hit_rate": measured_l2_hit("k_bwd_pass2") if p2_traffic is not None else None,
                 "launch_ms": p2_ms, "flops_per_launch": p2_flops,
                 "flops_model": f"{FLOPS_BWD_SCATTER[2]} FP32 ops per two-level sample x {counts[1]} + "
                                f"{FLOPS_BWD_SCATTER[1]} per one-level sample x {samples - counts[1]} "

@@ -92,6 +92,18 @@ def test_trace_kernel_traffic_is_gated_on_its_own_sources(tmp_path, monkeypatch)
     assert bench.measured_traffic("k_bwd_pass2")[0] is None     # another kernel's digest
 
 
+def test_l2_hit_rate_comes_with_the_traffic_line(tmp_path, monkeypatch):
+    d_tr = bench.kernel_source_digest(kernel="k_trace")
+    prof = tmp_path / "profile.md"
+    monkeypatch.setattr(bench, "PROFILE", str(prof))
+    prof.write_text(f"    traffic k_trace: fetch_bytes=10 write_bytes=5 l2_hit=0.817 sources={d_tr}\n"
+                    f"    traffic k_bwd_pass2: fetch_bytes=7 write_bytes=1 l2_hit=0.191 sources=0123456789abcdef\n")
+    assert bench.measured_traffic("k_trace")[0] == 15 and bench.measured_l2_hit("k_trace") == 0.817
+    assert bench.measured_l2_hit("k_bwd_pass2") is None          # stale digest: neither figure
+    prof.write_text(f"    traffic k_trace: fetch_bytes=10 write_bytes=5 sources={d_tr}\n")
+    assert bench.measured_traffic("k_trace")[0] == 15 and bench.measured_l2_hit("k_trace") is None
+
+
 def test_digest_follows_code_not_comments(tmp_path):
     import shutil
     src = os.path.join(ROOT, "paper_2104_00618_amd", "csrc")
