@@ -353,8 +353,10 @@ int vct_count_shade_samples(const vct_grid* grid, const void* pyramid, const vct
  *              normal/albedo output
  * Errors: VCT_EINVAL for a bad grid, n_tris outside [0, 2^31), null buffers,
  * only one of normal / albedo given, n_lights outside 0..8, non-finite or
- * negative light parameters or attenuation all 0; VCT_EWORKSPACE if the
- * workspace is too small. */
+ * negative light parameters or attenuation all 0, or two of base, normal,
+ * albedo and the workspace's first vct_voxelize_workspace_bytes bytes
+ * overlapping each other or tris / colors; VCT_EWORKSPACE if the workspace is
+ * too small. */
 int vct_voxelize_workspace_bytes(const vct_grid* grid, int64_t n_tris, int32_t surface, size_t* bytes);
 int vct_voxelize(const vct_grid* grid, const float* tris, const float* colors, int64_t n_tris,
                  const vct_voxelize_params* params, float* base, float* normal, float* albedo, void* workspace,
@@ -382,7 +384,9 @@ int vct_voxelize(const vct_grid* grid, const float* tris, const float* colors, i
  *              every voxel that could be a surface voxel, and a flag bit)
  * The cones' terms are summed in cone order, as in vct_trace's D, so the result
  * is the same on every run.
- * Errors: VCT_EINVAL for a bad grid or cone parameters or a null pointer;
+ * Errors: VCT_EINVAL for a bad grid or cone parameters, a null pointer, the
+ * workspace's first vct_bounce_workspace_bytes bytes overlapping any buffer,
+ * or out overlapping pyramid, normal, albedo or (other than exactly) base;
  * VCT_EWORKSPACE if the workspace is too small. */
 int vct_bounce_workspace_bytes(const vct_grid* grid, size_t* bytes);
 int vct_bounce(const vct_grid* grid, const void* pyramid, const float* base, const float* normal,

@@ -50,6 +50,28 @@ void ok() { g_err.clear(); }
 
 bool finite(float v) { return isfinite(v); }
 
+// A named byte range of a caller's buffer.
+struct Span {
+    const char* name;
+    const void* p;
+    size_t bytes;
+};
+
+// Fails with VCT_EINVAL if two of the spans share a byte (null or empty spans
+// share none).  Used where kernels index through values other kernels of the
+// same call wrote to device memory: an output that aliased their storage
+// would turn into indices past a buffer's end.
+int check_disjoint(const char* fn, const Span* s, int n) {
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            if (!s[i].p || !s[j].p || !s[i].bytes || !s[j].bytes) continue;
+            const uintptr_t a = (uintptr_t)s[i].p, b = (uintptr_t)s[j].p;
+            if (a < b + s[j].bytes && b < a + s[i].bytes)
+                return fail(VCT_EINVAL, fn, "%s and %s overlap", s[i].name, s[j].name);
+        }
+    return 0;
+}
+
 int check_grid(const char* fn, const vct_grid* g) {
     if (!g) return fail(VCT_EINVAL, fn, "grid is null");
     if (g->n < 1 || g->n > VCT_MAX_N || (g->n & (g->n - 1)))
@@ -413,6 +435,19 @@ int vct_voxelize(const vct_grid* grid, const float* tris, const float* colors, i
     const size_t need = vct_voxelize_workspace_size(grid->n, n_tris, surface);
     if (workspace_bytes < need)
         return fail(VCT_EWORKSPACE, fn, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    {
+        // outputs and workspace pairwise apart, and apart from the mesh (tris
+        // and colors are only read, so they may share memory)
+        const size_t grid_bytes = (size_t)grid->n * grid->n * grid->n * 16;
+        const Span out[] = {{"base", base, grid_bytes}, {"normal", normal, grid_bytes},
+                            {"albedo", albedo, grid_bytes}, {"workspace", workspace, need}};
+        if (int r = check_disjoint(fn, out, 4)) return r;
+        for (const Span& in : {Span{"tris", tris, (size_t)n_tris * 36}, Span{"colors", colors, (size_t)n_tris * 12}})
+            for (const Span& o : out) {
+                const Span pair[] = {o, in};
+                if (int r = check_disjoint(fn, pair, 2)) return r;
+            }
+    }
     hipError_t e = vct_launch_voxelize(grid, tris, colors, n_tris, params, base, normal, albedo, workspace, stream,
                                        es);
     if (e != hipSuccess) return device_error(fn, e);
@@ -555,6 +590,23 @@ int vct_bounce(const vct_grid* grid, const void* pyramid, const float* base, con
     if (workspace_bytes < need)
         return fail(VCT_EWORKSPACE, fn, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
     PyrLayout L = vct_make_layout(grid->n, grid->levels, grid->dtype, grid->anisotropic);
+    {
+        // the workspace apart from every buffer, out apart from every input
+        // but base (out == base is the in-place form); the inputs are only read
+        const size_t grid_bytes = (size_t)grid->n * grid->n * grid->n * 16;
+        const Span ins[] = {{"pyramid", pyramid, (size_t)L.bytes}, {"base", base, grid_bytes},
+                            {"normal", normal, grid_bytes}, {"albedo", albedo, grid_bytes}};
+        const Span ws{"workspace", workspace, need}, o{"out", out, grid_bytes};
+        const Span pair_wo[] = {ws, o};
+        if (int r = check_disjoint(fn, pair_wo, 2)) return r;
+        for (const Span& in : ins) {
+            const Span pair_w[] = {ws, in};
+            if (int r = check_disjoint(fn, pair_w, 2)) return r;
+            if (in.p == base && out == base) continue;
+            const Span pair_o[] = {o, in};
+            if (int r = check_disjoint(fn, pair_o, 2)) return r;
+        }
+    }
     const vct_gbuffer none{};
     TraceArgs a = make_args(grid, L, pyramid, &none, params);
     a.enable_spec = 0;

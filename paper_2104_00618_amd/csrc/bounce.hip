@@ -131,7 +131,8 @@ __global__ __launch_bounds__(256) void k_list(const unsigned long long* __restri
     const unsigned long long below = (1ull << lane) - 1ull;
     for (uint32_t i = 0; i < kBlockVox / 4 && w0 + i < nvox; i += 64) {
         const unsigned long long mk = masks[(w0 + i) >> 6];
-        if ((mk >> lane) & 1ull) list[pos + (uint32_t)__popcll(mk & below)] = visit_to_linear(w0 + i + lane, lg);
+        const uint32_t at = pos + (uint32_t)__popcll(mk & below);   // (< nvox: one bit per voxel)
+        if (((mk >> lane) & 1ull) && at < nvox) list[at] = visit_to_linear(w0 + i + lane, lg);
         pos += (uint32_t)__popcll(mk);
     }
 }
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(1024) void k_gather(TraceArgs a, BounceArgs b) {
     __shared__ uint32_t s_tile;
     load_level_table(a, &T);
     load_dir_table(a, &D);
-    const uint32_t total = *b.total;
+    const uint32_t total = min(*b.total, 1u << (3 * b.lg));   // (the list holds at most n^3 entries)
     const uint32_t nt = (total + 63u) / 64u;
     const uint32_t per_xcd = (nt + 7u) / 8u;
     const uint32_t xcd = blockIdx.x & 7u;

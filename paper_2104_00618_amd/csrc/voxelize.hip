@@ -411,18 +411,22 @@ __global__ __launch_bounds__(256) void k_raster(VoxArgs a, const TriSetup* __res
             // the voxel's slot: its alpha word in base, claimed by the first fragment
             unsigned int* word = base_words + vi * 4 + 3;
             unsigned int s = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // (a voxel is claimed once, so at most n^3 slots are taken; the
+            // bound on s below only keeps a word that held anything else, were
+            // base to alias another buffer, from indexing past the slots)
+            const unsigned int cap = (unsigned int)a.n * a.n * a.n;
             if (s == 0u) {
                 s = atomicCAS(word, 0u, kClaimed);
                 if (s == 0u) {
                     const unsigned int slot = atomicAdd(counter, 1u);
-                    acc[slot].voxel = (unsigned int)vi + 1u;      // read by the resolve pass only
+                    if (slot < cap) acc[slot].voxel = (unsigned int)vi + 1u;   // read by the resolve pass only
                     s = slot + 1u;
                     atomicExch(word, s);
                 }
             }
             for (int spin = 0; s == kClaimed && spin < kMaxSpin; ++spin)
                 s = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (s == kClaimed) continue;   // (not reached: a claim is published right after it is made)
+            if (s == kClaimed || s > cap) continue;   // (not reached: see above; a claim is published right away)
             VoxAcc* q = acc + (s - 1u);
             atomicAdd(&q->r, to_fixed(lr * r.col[0]));
             atomicAdd(&q->g, to_fixed(lg * r.col[1]));
@@ -443,9 +447,10 @@ __global__ __launch_bounds__(256) void k_raster(VoxArgs a, const TriSetup* __res
 // voxels keep the zeros of k_clear).
 template <bool SURF>
 __global__ __launch_bounds__(256) void k_resolve(const VoxAcc* __restrict__ acc, const SurfAcc* __restrict__ surf,
-                                                 const unsigned int* __restrict__ counter, float4* __restrict__ base,
+                                                 const unsigned int* __restrict__ counter, unsigned int cap,
+                                                 float4* __restrict__ base,
                                                  float4* __restrict__ normal, float4* __restrict__ albedo) {
-    const unsigned int used = *counter;
+    const unsigned int used = min(*counter, cap);
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < used; i += (size_t)gridDim.x * blockDim.x) {
         const VoxAcc q = acc[i];
         const size_t v = (size_t)q.voxel - 1u;
@@ -537,11 +542,11 @@ hipError_t vct_launch_voxelize(const vct_grid* g, const float* tris, const float
     es.mark(st);
     if (n_tris > 0) {
         if (surface)
-            hipLaunchKernelGGL(k_resolve<true>, dim3(1024), dim3(256), 0, st, acc, surf, counter,
+            hipLaunchKernelGGL(k_resolve<true>, dim3(1024), dim3(256), 0, st, acc, surf, counter, (unsigned)nvox,
                                reinterpret_cast<float4*>(base), reinterpret_cast<float4*>(normal),
                                reinterpret_cast<float4*>(albedo));
         else
-            hipLaunchKernelGGL(k_resolve<false>, dim3(1024), dim3(256), 0, st, acc, surf, counter,
+            hipLaunchKernelGGL(k_resolve<false>, dim3(1024), dim3(256), 0, st, acc, surf, counter, (unsigned)nvox,
                                reinterpret_cast<float4*>(base), nullptr, nullptr);
     }
     es.mark(st);

@@ -275,6 +275,27 @@ int run_abi_checks() {
         EXPECT(vct_bounce_workspace_bytes(&g, &bws), VCT_OK, "vct_bounce_workspace_bytes", nullptr);
         EXPECT(vct_bounce(&g, vfake, fake, fake, fake, &p, fake, vfake, bws - 1, nullptr), VCT_EWORKSPACE,
                "vct_bounce", "workspace");
+        // overlapping buffers (rejected before anything is enqueued; addresses only, never dereferenced)
+        v.n_lights = 1;
+        {
+            const uintptr_t A = uintptr_t(1) << 40;
+            const size_t gbytes = (size_t)g.n * g.n * g.n * 16;
+            auto at = [&](size_t off) { return reinterpret_cast<float*>(A + off); };
+            EXPECT(vct_voxelize(&g, at(8 * gbytes), at(9 * gbytes), 10, &v, at(0), at(gbytes / 2), at(2 * gbytes),
+                                at(3 * gbytes), vws, nullptr),
+                   VCT_EINVAL, "vct_voxelize", "base and normal overlap");
+            EXPECT(vct_voxelize(&g, at(gbytes - 8), at(9 * gbytes), 10, &v, at(0), at(gbytes), at(2 * gbytes),
+                                at(3 * gbytes), vws, nullptr),
+                   VCT_EINVAL, "vct_voxelize", "base and tris overlap");
+            size_t pbytes = 0;
+            EXPECT(vct_pyramid_bytes(&g, &pbytes), VCT_OK, "vct_pyramid_bytes", nullptr);
+            EXPECT(vct_bounce(&g, at(0), at(pbytes), at(pbytes + gbytes), at(pbytes + 2 * gbytes), &p,
+                              at(pbytes + gbytes + 64), at(pbytes + 4 * gbytes), bws, nullptr),
+                   VCT_EINVAL, "vct_bounce", "out and normal overlap");
+            EXPECT(vct_bounce(&g, at(0), at(pbytes), at(pbytes + gbytes), at(pbytes + 2 * gbytes), &p, at(pbytes),
+                              at(64), bws, nullptr),
+                   VCT_EINVAL, "vct_bounce", "workspace and pyramid overlap");
+        }
     }
 
     // diagnostics

@@ -411,6 +411,57 @@ def test_voxelize_validation_and_workspace_size():
     assert rc == EWORKSPACE and "workspace" in lib.vct_last_error().decode()
 
 
+def test_voxelize_rejects_overlapping_buffers():
+    """base holds slot indices while the call runs and the raster launch zeroes
+    normal and albedo beside it, so outputs, workspace and mesh must be apart
+    (every case here is rejected before anything is enqueued)."""
+    lib = vct.lib()
+    g = vct.Grid(32).c()
+    gb = 32 ** 3 * 16
+    ws = ctypes.c_size_t()
+    lib.vct_voxelize_workspace_bytes(ctypes.byref(g), 3, 1, ctypes.byref(ws))
+    good = B.voxelize_params([((0.5, 0.9, 0.5), (1, 1, 1), (1, 0, 0))])
+    A = 1 << 32
+    base, normal, albedo, work, tris, cols = A, A + gb, A + 2 * gb, A + 3 * gb, A + 3 * gb + ws.value, A + 4 * gb + ws.value
+    cases = [(dict(normal=base + 256), "base and normal"), (dict(albedo=normal + gb - 16), "normal and albedo"),
+             (dict(work=albedo + 4096), "albedo and workspace"), (dict(work=base), "base and workspace"),
+             (dict(tris=base + gb - 8), "base and tris"), (dict(cols=work + ws.value - 4), "workspace and colors")]
+    for kw, msg in cases:
+        a = dict(base=base, normal=normal, albedo=albedo, work=work, tris=tris, cols=cols)
+        a.update(kw)
+        v = {k: ctypes.c_void_p(x) for k, x in a.items()}
+        rc = lib.vct_voxelize(ctypes.byref(g), v["tris"], v["cols"], 3, ctypes.byref(good), v["base"], v["normal"],
+                              v["albedo"], v["work"], ws.value, None)
+        assert rc == EINVAL and msg in lib.vct_last_error().decode(), (kw, lib.vct_last_error())
+
+
+def test_bounce_rejects_overlapping_buffers():
+    """The bounce indexes through its own flag masks and voxel list: the
+    workspace must be apart from every buffer, and out apart from every input
+    but base itself (the in-place form)."""
+    lib = vct.lib()
+    g = vct.Grid(32).c()
+    gb = 32 ** 3 * 16
+    need, pb = ctypes.c_size_t(), ctypes.c_size_t()
+    lib.vct_bounce_workspace_bytes(ctypes.byref(g), ctypes.byref(need))
+    lib.vct_pyramid_bytes(ctypes.byref(g), ctypes.byref(pb))
+    p = B.cone_params(_params())
+    A = 1 << 32
+    pyr, base, normal, albedo, out = A, A + pb.value, A + pb.value + gb, A + pb.value + 2 * gb, A + pb.value + 3 * gb
+    work = out + gb
+    cases = [(dict(out=normal + 16), "out and normal"), (dict(out=base + 16), "out and base"),
+             (dict(out=pyr + pb.value - 16), "out and pyramid"), (dict(work=pyr + 256), "workspace and pyramid"),
+             (dict(work=albedo), "workspace and albedo"), (dict(out=base, work=base + gb - 64), "workspace and out"),   # in place: out is base
+             (dict(work=out - need.value + 16), "workspace and out")]
+    for kw, msg in cases:
+        a = dict(pyr=pyr, base=base, normal=normal, albedo=albedo, out=out, work=work)
+        a.update(kw)
+        v = {k: ctypes.c_void_p(x) for k, x in a.items()}
+        rc = lib.vct_bounce(ctypes.byref(g), v["pyr"], v["base"], v["normal"], v["albedo"], ctypes.byref(p), v["out"],
+                            v["work"], need.value, None)
+        assert rc == EINVAL and msg in lib.vct_last_error().decode(), (kw, lib.vct_last_error())
+
+
 def test_bounce_validation_and_workspace_size():
     lib = vct.lib()
     g = vct.Grid(64).c()
