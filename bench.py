@@ -735,16 +735,16 @@ def main():
         torch.cuda.empty_cache()
         res["configs"] = bench_configs(vct, torch, make_workload)
     # whether float16 storage gives the faster forward, frame by frame
-    verdict = {}
+    f16_faster = {}
     if "f16_storage" in breakdown:
-        verdict["isotropic_256cubed_1080p"] = breakdown["f16_storage"]["fwd_speedup_vs_f32"] > 1.0
+        f16_faster["isotropic_256cubed_1080p"] = breakdown["f16_storage"]["fwd_speedup_vs_f32"] > 1.0
     if "f16_storage" in aniso:
-        verdict["anisotropic_256cubed_1080p"] = aniso["f16_storage"]["fwd_speedup_vs_f32"] > 1.0
+        f16_faster["anisotropic_256cubed_1080p"] = aniso["f16_storage"]["fwd_speedup_vs_f32"] > 1.0
     if "configs" in res:
-        verdict["isotropic_512cubed_4x4k"] = res["configs"]["c4_512cubed_4x4k_f16"]["fwd_speedup_vs_f32"] > 1.0
-    if verdict:
+        f16_faster["isotropic_512cubed_4x4k"] = res["configs"]["c4_512cubed_4x4k_f16"]["fwd_speedup_vs_f32"] > 1.0
+    if f16_faster:
         res["fp16_forward_faster_than_fp32"] = dict(
-            verdict, met_everywhere=all(verdict.values()),
+            f16_faster, met_everywhere=all(f16_faster.values()),
             note="speedups of the float16-storage forward over float32 are in breakdown.f16_storage, "
                  "breakdown.anisotropic.f16_storage and configs.c4_512cubed_4x4k_f16")
     if cpu_base is not None:
