@@ -444,7 +444,7 @@ __global__ __launch_bounds__(256) void k_raster(VoxArgs a, const TriSetup* __res
 }
 
 // One thread per used slot: write its voxel in the output grids (the other
-// voxels keep the zeros of k_clear).
+// voxels keep the zeros of k_clear and of the raster launch's fill).
 template <bool SURF>
 __global__ __launch_bounds__(256) void k_resolve(const VoxAcc* __restrict__ acc, const SurfAcc* __restrict__ surf,
                                                  const unsigned int* __restrict__ counter, unsigned int cap,
