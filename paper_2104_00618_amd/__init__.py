@@ -6,5 +6,6 @@ from .binding import (Grid, KernelEvents, VctError, VCTTrace, backward_workspace
                       count_sample_levels,
                       count_shade_samples,
                       cone_params, lane_state_bytes, lib, pyramid_bytes, render, shade, shade_params, trace, trace_backward,
-                      trace_backward_saved, trace_save, unpack_level, unpack_level_dir, voxelize,
+                      trace_backward_saved, trace_backward_saved_noalloc, trace_save, unpack_level,
+                      unpack_level_dir, voxelize,
                       voxelize_params, voxelize_workspace_bytes, bounce, bounce_workspace_bytes)

@@ -2,8 +2,9 @@
 library's calls, which enqueue on the capturing stream) and replayed.  The
 library clears its buffers with fill kernels, never a memset or a copy, and
 synchronises with nothing, so a training step (build_mips + trace_save +
-trace_backward_saved, and the forward trace) and a revoxelized bounce frame
-(voxelize with surface attributes + build_mips + bounce) can be captured.
+trace_backward_saved, and the forward trace), the same step through the
+allocation-free backward, and a revoxelized bounce frame (voxelize with
+surface attributes + build_mips + bounce) can be captured.
 Every replay is compared bit for bit with the same calls made eagerly into
 other buffers, with the inputs changed in place by eager work and the device
 synchronised between replays."""
@@ -79,6 +80,41 @@ def test_training_step_graph_replays_equal_eager_calls(dtype):
             assert same_bits(static[k], eager[k]), f"replay {r}: {k} differs from the eager call"
         assert static["gb"].abs().max().item() > 0
         print(f"{dtype} replay {r}: trace, training step and gradient equal to the eager calls", flush=True)
+
+
+def test_allocation_free_backward_under_capture_equals_the_saved_backward():
+    """The entry point for callers that cannot allocate, captured in a graph
+    (its scratch is the library's per-GPU array, set up by an eager call
+    before the capture): every replay equals the allocating saved backward
+    called eagerly."""
+    w = make_workload("c0", h=64, w=96)
+    base, pr, nr, cam = dev(w.base), dev(w.pos_rough), dev(w.normal), dev(w.cam_pos)
+    grid = vct.Grid(w.n)
+    gout = dev(np.random.default_rng(5).normal(size=w.shape + (8,)).astype(np.float32) * 1e-2)
+    pyr = torch.empty(vct.pyramid_bytes(grid), dtype=torch.uint8, device=DEV)
+    out = torch.empty(w.shape + (8,), device=DEV)
+    st = torch.empty(vct.lane_state_bytes(pr, nr, cam, w.params), dtype=torch.uint8, device=DEV)
+    gb_graph = torch.empty((w.n,) * 3 + (4,), device=DEV)
+    ws = torch.empty(vct.backward_workspace_bytes(grid, pr, nr, cam, w.params) - st.numel(), dtype=torch.uint8,
+                     device=DEV)
+    gb_eager = torch.empty_like(gb_graph)
+
+    def step():
+        vct.build_mips(base, grid, pyr)
+        vct.trace_save(pyr, grid, pr, nr, cam, w.params, out, st)
+        vct.trace_backward_saved_noalloc(pyr, grid, pr, nr, cam, w.params, st, gout, gb_graph)
+
+    graph = capture(step)
+    for r in range(3):
+        if r:
+            base.mul_(0.7).add_(0.03 * r).clamp_(0.0, 1.0)
+            torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        vct.trace_backward_saved(pyr, grid, pr, nr, cam, w.params, st, gout, ws, gb_eager)
+        torch.cuda.synchronize()
+        assert same_bits(gb_graph, gb_eager), f"replay {r}: the captured allocation-free backward differs"
+        assert gb_graph.abs().max().item() > 0
 
 
 def test_revoxelized_bounce_frame_graph_replays_equal_eager_calls():
