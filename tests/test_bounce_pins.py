@@ -137,6 +137,24 @@ def test_uniform_medium_follows_the_linear_recurrence(k):
     np.testing.assert_array_equal(out[..., 3], a)
 
 
+def test_bounce_traces_the_diffuse_cones_only():
+    """In a uniform medium every cone takes the closed-form schedule length K,
+    so the bounce's sample count is (surface voxels) x (diffuse cones) x K:
+    no specular or occlusion cone is traced (B2)."""
+    dirs = np.array([[0, 0, 1], [0.6, 0, 0.8], [0, -0.6, 0.8]], np.float32)
+    p = ConeParams(dirs, np.array([0.5, 0.3, 0.2], np.float32), diffuse_aperture=math.pi / 3, step_factor=0.5,
+                   t0=0.01, normal_offset=1.0, max_dist=0.5, alpha_thresh=1.0, enable_spec=True, enable_occ=True)
+    base = np.zeros((N, N, N, 4))
+    base[..., 0:3] = 0.1
+    base[..., 3] = 0.05
+    normal = np.zeros((N, N, N, 4))
+    normal[2:5, 3:7, 4:9, 0:3] = (0.0, 0.0, 1.0)            # 3 x 4 x 5 surface voxels
+    albedo = np.full((N, N, N, 4), 0.5)
+    _, info = vb.bounce(base, normal, albedo, p, return_info=True)
+    assert int(info["surface"].sum()) == 60
+    assert info["samples"] == 60 * 3 * _uniform_samples(p)
+
+
 def test_sampled_voxels_match_the_whole_grid():
     _, base, normal, albedo = _row_scene(10)
     normal[..., 0:3] = np.random.default_rng(0).normal(size=(N, N, N, 3))

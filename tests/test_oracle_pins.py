@@ -208,6 +208,32 @@ def test_lod_is_log2_of_diameter_over_voxel_size():
     assert out[0, 0, 0, 1] == pytest.approx(0.5 * ((1 - f) * 1.0 + f * 0.5), abs=1e-9)
 
 
+def test_lod_saturates_at_the_top_level():
+    """A cone wider than the grid: once its diameter passes 2^(L-1) voxels the
+    LOD stays at the top level L-1 (reading R5), whose single texel is the
+    mean of the base grid, so every such sample equals that mean (to the
+    rounding of its eight tap weights, which sum to 1)."""
+    n = 8
+    g = random_grid(n, seed=9).astype(np.float64)
+    mips = oracle.build_mips(g)
+    top = len(mips) - 1
+    gamma = 2 * math.atan(2.0)                       # d = 4 t: t grows 3x a step once d > v0
+    p = single_cone_params(gamma, beta=0.5, t0=0.01, t_max=8.0, offset=0.0)
+    pr, nr, cam = one_pixel((0.4, 0.55, 0.2), (0.0, 0.0, 1.0))
+    lanes = oracle.cone_lanes(pr, nr, cam, p, n)
+    res = oracle.march(mips, lanes, p, record=True)
+    v0 = 1.0 / n
+    saturated = 0
+    for idx, ti, d, lam, a_prev, s in res["steps"]:
+        assert np.all(lam <= top)
+        sat = d >= 2.0 ** top * v0
+        assert np.all(lam[sat] == top)
+        np.testing.assert_allclose(s[sat], np.broadcast_to(mips[top][0, 0, 0], s[sat].shape), rtol=1e-14)
+        saturated += int(sat.sum())
+    assert saturated >= 3
+    np.testing.assert_allclose(mips[top][0, 0, 0], g.mean(axis=(0, 1, 2)), rtol=1e-14)
+
+
 # ------------------------------------------------- P6 linearity of one sample
 def test_p6_single_sample_march_is_linear_in_the_grid():
     n = 16

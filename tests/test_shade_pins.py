@@ -104,6 +104,24 @@ def test_empty_grid_gives_the_direct_phong_term(falloff, first_hit, brdf):
     np.testing.assert_allclose(out[0, 0, 0, 0:3], 0.0, atol=1e-15)
 
 
+def test_zero_shininess_makes_the_phong_factor_one():
+    """(R.w)^0 = 1 for every view, 0^0 = 1 included (reading S5): with the
+    camera where R.w = 0 the Phong factor is 0 at shininess 32 and 1 at 0."""
+    n = 16
+    mips = uniform_mips(n, (0.0, 0.0, 0.0, 0.0))
+    x, nrm = (0.5, 0.25, 0.5), (0.0, 1.0, 0.0)
+    s2 = math.sqrt(0.5)
+    lp = (0.75, 0.5, 0.5)          # L = (1, 1, 0)/sqrt 2, R = (-1, 1, 0)/sqrt 2
+    cam = (0.75, 0.5, 0.5)         # w = L, so R.w = 0
+    sp = ShadeParams(*lights(lp, idiff=(1.0, 0.5, 0.25), ispec=(0.375, 0.375, 0.375)),
+                     specular_color=(0.875, 0.875, 0.875))
+    lambert = np.array([0.75 * 1.0, 0.5 * 0.5, 0.25 * 0.25]) * s2
+    for shin, phong in ((32.0, 0.0), (0.0, 1.0)):
+        pr, nr, mat, cm = one_pixel(x, nrm, cam, albedo=(0.75, 0.5, 0.25), shininess=shin)
+        out = oracle.shade(mips, pr, nr, mat, cm, cone_params(), sp)[0, 0, 0]
+        np.testing.assert_allclose(out[0:3], lambert + 0.875 * 0.375 * phong, rtol=1e-12, atol=1e-12)
+
+
 def test_direct_term_is_scaled_by_the_light_visibility():
     """A uniform black absorber (rgb 0, alpha a): the cones gather no colour,
     so L is the direct term alone, and with one light it must be that

@@ -35,6 +35,19 @@ def test_axis_aligned_quad_fills_exactly_its_pixel_centres():
     assert set(np.unique(cnt[expect])) == {1}
 
 
+def test_quad_wider_than_the_grid_fills_its_whole_layer():
+    """Every pixel centre of the N x N viewport lies inside, the last row and
+    column included: one layer of N^2 voxels, one fragment each."""
+    z = 0.4
+    out, cnt = vx.voxelize(quad(-0.01, 1.01, -0.02, 1.03, z), np.ones((2, 3), np.float32), N, [LIGHT],
+                           return_counts=True)
+    layer = int(math.floor(z * N))
+    expect = np.zeros((N, N, N), dtype=bool)
+    expect[layer] = True
+    np.testing.assert_array_equal(out[..., 3] == 1.0, expect)
+    assert set(np.unique(cnt[expect])) == {1}
+
+
 def test_edges_through_pixel_centres_are_covered_once():
     # corners on pixel centres: all four edges and the diagonal pass through centres
     c = lambda i: (i + 0.5) * V0  # noqa: E731
@@ -80,7 +93,7 @@ def test_direct_light_closed_form_and_attenuation():
     tris = quad(0.1, 0.9, 0.1, 0.9, z)
     col = np.array([[0.8, 0.5, 0.25]] * 2, np.float32)
     lp, h = (0.5, 0.5, 0.85), 0.35
-    att = (1.0, 2.0, 3.0)
+    att = (1.5, 2.0, 3.0)
     amb, dif = 0.125, 0.75
     out = vx.voxelize(tris, col, N, [(lp, (1.0, 0.5, 0.25), att)], ambient=amb, diffuse=dif)
     layer = int(z * N)
@@ -88,7 +101,7 @@ def test_direct_light_closed_form_and_attenuation():
         p = np.array([(i + 0.5) * V0, (j + 0.5) * V0, z])
         d = np.linalg.norm(np.array(lp) - p)
         cos = (lp[2] - z) / d
-        expect = np.array(col[0], np.float64) * (amb + dif * cos) * np.array([1.0, 0.5, 0.25]) / (1 + 2 * d + 3 * d * d)
+        expect = np.array(col[0], np.float64) * (amb + dif * cos) * np.array([1.0, 0.5, 0.25]) / (1.5 + 2 * d + 3 * d * d)
         np.testing.assert_allclose(out[layer, j, i, 0:3], expect, rtol=1e-12)
         assert out[layer, j, i, 3] == 1.0
     # facing away from the light: ambient only
