@@ -374,14 +374,68 @@ __device__ __forceinline__ void emit_level_dirs(bool live, const LevelGeom& geo,
     });
 }
 
+// Anisotropic pyramids above level 0, when the wave's lanes have different
+// cone axes: lanes are grouped by footprint and by the signs of their axis
+// (which pick the three directional pyramids, so each direction's offset is
+// uniform in a group), once for the three directions; each group then runs
+// one butterfly per axis, with the lane's gradient scaled by its w_a^2 for
+// that axis, and adds the sum at that direction's offset.  (Grouping once in
+// place of once per direction: the group loop, the slot-order weights and the
+// clamp key are shared by the three.)
+template <bool ALPHA_ONLY>
+__device__ __forceinline__ void emit_level_axes(bool live, const LevelGeom& geo, float wl, const float gs[4],
+                                                const EmitLane& e, int E, const float wt[3], int sgn,
+                                                const DirTable* D, unsigned long long* __restrict__ acc,
+                                                unsigned long long* small, uint32_t small_off, int lane) {
+    unsigned long long mask = __ballot(live);
+    if (mask == 0) return;   // (wave-uniform)
+    float wp[8];
+    emit_weights(geo, wl, e, wp);
+    float wpart[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wpart[k] = dpp<kDppXor15>(wp[k + 4]);
+    const uint32_t key = live ? geo.base : 0xffffffffu;
+    const int kcl = (geo.dx == 0 ? 1 : 0) | (geo.dy == 0 ? 2 : 0) | (geo.dz == 0 ? 4 : 0) | (sgn << 3);
+    const bool emitter = ALPHA_ONLY ? ((lane & 0x31) == 0) : (lane < 32);
+    const int ch = ALPHA_ONLY ? 3 : e.ch;
+    while (mask) {
+        const int leader = __builtin_ctzll(mask);
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
+        const int kc = __builtin_amdgcn_readlane(kcl, leader);
+        const bool in = live && key == k && kcl == kc;
+        const unsigned long long gm = __ballot(in);
+        const int lev = __builtin_amdgcn_readlane(geo.level, leader);
+        const uint32_t dx = (uint32_t)__builtin_amdgcn_readlane((int)geo.dx, leader);
+        const uint32_t dy = (uint32_t)__builtin_amdgcn_readlane((int)geo.dy, leader);
+        const uint32_t dz = (uint32_t)__builtin_amdgcn_readlane((int)geo.dz, leader);
+        const uint32_t tap = k + (dx & e.xm) + (dy & e.ym) + (dz & e.zm);
+        const int sg = kc >> 3;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            float sum;
+            if (ALPHA_ONLY) {
+                sum = bfly8(wp, wpart, in ? gs[3] * wt[ax] : 0.f);
+            } else {
+                float g[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) g[m] = in ? gs[m] * wt[ax] : 0.f;
+                sum = bfly32(wp, wpart, g);
+            }
+            const long long qv = emitter ? fixed_point(sum, E) : 0;
+            add_fixed(tap + D->delta[2 * ax + ((sg >> ax) & 1)][lev], ch, qv, acc, small, small_off);
+        }
+        mask &= ~gm;
+    }
+}
+
 // One level's emission.  Isotropic pyramids: level l's integers carry the
 // scale 2^(E - 3l) (the 1/8 per level of the mip adjoint folded in).
 // Anisotropic pyramids: scale 2^E at every level (their mip adjoint is not a
 // fixed factor); above level 0 the sample read the three directions of its
 // axis signs with weights w_a^2, so each gets the gradient with that weight at
 // its direction's offset: with one butterfly per group when the wave's lanes
-// share their axis (emit_level_dirs), else one per direction (a separate group
-// key each, since the base index moves).
+// share their axis (emit_level_dirs), else one per axis in a group keyed by the
+// footprint and the axis's signs (emit_level_axes).
 template <bool ALPHA_ONLY, bool ANISO, bool HOLD>
 __device__ __forceinline__ void emit_dirs(const TraceArgs& a, const DirTable* D, const Cone& c, bool live,
                                           const LevelGeom& geo, float wl, const float gs[4], const EmitLane& e, int E,
@@ -414,18 +468,17 @@ __device__ __forceinline__ void emit_dirs(const TraceArgs& a, const DirTable* D,
             emit_level_dirs<ALPHA_ONLY>(up, geo, wl, gs, e, E, wt, dsel, D, acc, small, small_off, lane);
             return;
         }
+        // (a lane of a pixel with no surface has no cone and its W is whatever
+        // the registers held: its axis weights and signs are only read through
+        // the group test, which such a lane never passes)
+        float wt[3];
+        int sgn = 0;
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            const float wt = W[ax] * W[ax] * a.inv_scale2;
-            const bool on = live && !base_level && wt != 0.0f;
-            LevelGeom gd = geo;
-            gd.base += on ? D->delta[2 * ax + (W[ax] < 0.0f ? 1 : 0)][geo.level] : 0u;
-            // every lane's weights enter the butterfly (times a zero gradient
-            // outside the group), so they must be finite: a lane of a pixel
-            // with no surface has no cone, and its W is whatever the
-            // registers held
-            emit_level<ALPHA_ONLY>(on, gd, on ? wl * wt : 0.0f, gs, e, E, 0, acc, small, small_off, lane);
+            wt[ax] = W[ax] * W[ax] * a.inv_scale2;
+            sgn |= (W[ax] < 0.0f ? 1 : 0) << ax;
         }
+        emit_level_axes<ALPHA_ONLY>(up, geo, wl, gs, e, E, wt, sgn, D, acc, small, small_off, lane);
     }
 }
 
